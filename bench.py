@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Projection benchmark on one MI355X.
+
+One step = one pass of the whole ghost-cell projection on the multi-body 256^3 workload
+(8 perturbed icospheres of 20,480 triangles on a stretched grid): cell classification,
+ghost-cell stencils and multigrid hierarchy, divergence right-hand side, pressure Poisson
+solve from p = 0 to relative residual 1e-10, velocity correction.  The body mesh is uploaded
+and validated once; inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the design doc for the fields).  --gpus N > 1 is not supported.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SWEEP_BYTES = {"fp64": 25.0, "fp32": 13.0}  # algorithmic bytes per cell of one fused sweep
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, cycles_needed, n_sample_cycles=3):
+    """The oracle as it stands on the same workload: classification, stencils, right-hand
+    side, a sample of V-cycles and the correction, timed on the host; the V-cycle time is
+    scaled to the number of cycles the full solve needs."""
+    import numpy as np
+    from oracle import OracleProblem
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    P = OracleProblem(wl.xf, wl.yf, wl.zf)
+    P.set_mesh(wl.verts, wl.tris)
+    u, v, w = wl.velocity()
+    t0 = time.perf_counter()
+    P.classify()
+    P.build_stencils()
+    t1 = time.perf_counter()
+    f = P.rhs(u, v, w)
+    t2 = time.perf_counter()
+    p, st = P.solve(f, fixed_cycles=n_sample_cycles)
+    t3 = time.perf_counter()
+    P.correct(u, v, w, p)
+    t4 = time.perf_counter()
+    per_cycle = (t3 - t2) / n_sample_cycles
+    t_step = (t1 - t0) + (t2 - t1) + per_cycle * cycles_needed + (t4 - t3)
+    del np
+    return {"value": 1.0 / t_step, "unit": "projections/s", "cores": threads, "kind": "oracle",
+            "sample": "one projection of the same 256^3 workload with %d of its %d V-cycles timed "
+                      "(classification %.2fs, stencils+hierarchy, %.3fs per V-cycle, scaled)"
+                      % (n_sample_cycles, cycles_needed, t1 - t0, per_cycle)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+    from paper_2505_17287_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    wl = I.multibody(args.n)
+    log("workload", wl.name, wl.shape, "triangles", len(wl.tris))
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision=args.precision)
+    g.set_geometry(wl.verts, wl.tris)
+    u0, v0, w0 = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in wl.velocity())
+    u, v, w = u0.clone(), v0.clone(), w0.clone()
+    p = torch.empty(g.shape, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        counts = g.classify()
+        ng = g.build_ghost_stencils()
+        u.copy_(u0)
+        v.copy_(v0)
+        w.copy_(w0)
+        _, st = g.project(u, v, w, dt=1.0, p=p, rel_tol=1e-10, precision=args.precision)
+        return counts, ng, st
+
+    for q in range(args.warmup):
+        counts, ng, st = step()
+        log("warmup", q, "cycles", st.cycles, "rel", st.rel_residual, "status", st.status)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    t0 = time.perf_counter()
+    cyc = []
+    for q in range(args.steps):
+        counts, ng, st = step()
+        cyc.append(st.cycles)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile()
+    g.set_profiling(False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = 1000.0 / ms
+
+    # dominant kernel: the fused red-black sweep of level 0
+    kind = "fp64" if args.precision == "fp64" else "fp32"
+    n_sw = prof["n_fp64"] if kind == "fp64" else prof["n_fp32"]
+    ms_sw = prof["ms_fp64"] if kind == "fp64" else prof["ms_fp32"]
+    avg_ms = ms_sw / max(n_sw, 1)
+    bytes_per_launch = SWEEP_BYTES[kind] * wl.ncells
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_rbgs_fused<%s>" % ("double" if kind == "fp64" else "float"),
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 5), "launches_timed": int(n_sw),
+                "bytes_per_launch": bytes_per_launch}
+    out = {
+        "metric": "Poisson solves/s + HBM GB/s at 256^3, rel-res 1e-10; p50/p99 serve latency",
+        "value": round(value, 3),
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": wl.ncells, "triangles": int(len(wl.tris)),
+                   "fluid_ghost_dead": [int(x) for x in counts], "ghosts": int(ng),
+                   "cycles": int(np.median(cyc)), "rel_tol": 1e-10, "precision": args.precision,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, int(np.median(cyc)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

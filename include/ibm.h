@@ -1,0 +1,185 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) ghost-cell immersed-boundary projection library.
+ *
+ * The library implements the pressure-projection half of the fractional-step method
+ * (Kumar, Seo, Mittal, Romero, Fatica, "A GPU-Accelerated Sharp-Interface Immersed
+ * Boundary Solver for Large-Scale Flow Simulations", Section 2.1) with the ghost-cell
+ * treatment of an immersed triangulated body (Section 2.2, Eq. 2 and Eq. 3):
+ *
+ *     classify cells -> ghost-cell stencils -> pressure Poisson solve -> velocity correction
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns ibm_status.  Negative values are errors; positive values are
+ *     usable results with a warning (see ibm_solve_stats).  A failed call leaves the handle
+ *     usable; ibm_last_error() describes the last failure.
+ *   - Cell fields are FP64, contiguous, layout [nz][ny][nx] (x fastest).  Face-normal
+ *     velocities use the staggered (MAC) layout u[nz][ny][nx+1], v[nz][ny+1][nx],
+ *     w[nz+1][ny][nx].  A grid with nz == 1 is two-dimensional (no z coupling, bilinear
+ *     4-cell stencils).
+ *   - "host" pointers are read during the call and copied; "device" pointers must point to
+ *     device memory of the workspace's device and are only borrowed for the call.
+ *   - All GPU work is enqueued on `stream` (a hipStream_t; NULL = the default stream).
+ *     The library never allocates device memory: every device buffer it uses lives in the
+ *     caller-owned workspace bound by ibm_bind_workspace (small pinned host buffers are
+ *     allocated at grid creation for status read-back).
+ *   - Call order: create -> bind_workspace -> set_geometry -> classify ->
+ *     build_ghost_stencils -> poisson_solve / project.  Out-of-order calls return
+ *     IBM_E_STATE; set_geometry invalidates classification and stencils.
+ *   - One host thread per handle at a time.  Distinct handles are independent and may run
+ *     concurrently on different streams.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibm_grid ibm_grid; /* opaque: one per problem */
+
+typedef enum {
+    IBM_OK = 0,
+    IBM_NOT_CONVERGED = 1, /* max_cycles reached; p and stats are valid */
+    IBM_E_ARG = -1,        /* invalid argument (sizes, non-monotone or non-finite coordinates) */
+    IBM_E_STATE = -2,      /* call out of order */
+    IBM_E_GEOMETRY = -3,   /* mesh not closed / not consistently oriented, or no fluid cell */
+    IBM_E_NOMEM = -4,      /* workspace too small for this grid / mesh / ghost count */
+    IBM_E_DEVICE = -5,     /* HIP error; message in ibm_last_error */
+    IBM_E_NUMERIC = -6     /* NaN/Inf or divergence; p holds the last finite iterate */
+} ibm_status;
+
+typedef enum { IBM_FP64 = 0, IBM_MIXED = 1 } ibm_precision;
+
+/* Solver options.  Defaults (ibm_default_opts): rel_tol 1e-10, max_cycles 200, V(2,2),
+   64 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested. */
+typedef struct {
+    double rel_tol;          /* stop when ||r'||_2 <= rel_tol * ||f - Vmean(f)||_2 (fluid rows) */
+    int max_cycles;          /* V-cycles (FP64) or refinement steps (mixed) */
+    int nu1, nu2;            /* pre- and post-smoothing sweeps per level */
+    int coarsest_sweeps;     /* red-black sweeps on the coarsest level */
+    ibm_precision precision; /* IBM_MIXED: FP32 V-cycle inside FP64 iterative refinement */
+    int use_initial_guess;   /* 1: start from the p passed in */
+    int fixed_cycles;        /* > 0: run exactly this many cycles, no convergence test */
+} ibm_solve_opts;
+
+typedef struct {
+    int cycles;                /* V-cycles / refinement steps performed */
+    double rel_residual;       /* ||r'||_2 / ||f'||_2 after the last cycle */
+    double ghost_residual_max; /* reserved: max ghost-equation residual (0 if not computed) */
+    double lambda;             /* uniform source shift making the Neumann system consistent */
+    double div_max;            /* projection only: max |D u| over fluid cells after correction */
+    double t_setup, t_solve, t_correct; /* seconds (host wall clock around the enqueue+sync) */
+} ibm_solve_stats;
+
+/* Fill `o` with the defaults listed above. */
+void ibm_default_opts(ibm_solve_opts *o);
+
+/* Create a handle for an nx x ny x nz cell grid with face coordinates xf[nx+1], yf[ny+1],
+   zf[nz+1] (host, strictly increasing, finite; nx, ny >= 2, nz >= 1).  Cell centres,
+   widths and the 7-point flux coefficients follow Section 2.1 (central differences on a
+   non-uniform Cartesian grid).  No device work is done here. */
+ibm_status ibm_create_grid(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                           ibm_grid **out);
+
+/* Bytes of device workspace needed for this grid size, a mesh of at most nv_max vertices
+   and nt_max triangles, at most max_ghosts ghost cells, and the given precision.  Needs no
+   handle, so it can drive admission decisions. */
+size_t ibm_workspace_bytes(int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t max_ghosts,
+                           ibm_precision prec);
+
+/* Exact workspace size for an existing handle (its multigrid plan depends on the face
+   coordinates).  ibm_workspace_bytes is an upper bound of this for any coordinates. */
+size_t ibm_grid_workspace_bytes(const ibm_grid *g, int64_t nv_max, int64_t nt_max, int64_t max_ghosts,
+                                ibm_precision prec);
+
+/* Bind a caller-owned device buffer (>= ibm_workspace_bytes(...) bytes, 256-byte aligned)
+   as the handle's workspace and upload the grid metrics.  `prec` = the most demanding
+   precision the handle will be used with.  The buffer must outlive every later call. */
+ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64_t nv_max, int64_t nt_max,
+                              int64_t max_ghosts, ibm_precision prec, void *stream);
+
+/* Set the immersed body: verts[nv][3] (host, FP64), tris[nt][3] (host, int32, outward
+   counter-clockwise).  The mesh must be closed and consistently oriented (every directed
+   edge once, its reverse once) -> else IBM_E_GEOMETRY.  Several disjoint closed bodies may
+   be passed as one mesh.  Uploads the mesh and builds the triangle bucket grid on the GPU. */
+ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                            void *stream);
+
+/* Classify every cell (Section 2.2, ray tracing): a cell is solid when its centre lies
+   strictly inside the body by the parity of crossings of the +z ray through the column
+   centre; ghost = solid with a fluid cell among its 26 neighbours; dead = other solid.
+   counts_out[3] (host) receives the fluid, ghost and dead counts.  Synchronises `stream`. */
+ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]);
+
+/* Build the ghost-cell stencils (Section 2.2, Eq. 2 and 3): body intercept = closest mesh
+   point, normal, image point = mirror of the ghost centre through the intercept, the 8 (2D:
+   4) cells around the image point and the weights of Eq. 2 with the Neumann condition in
+   place of the ghost's own value when it belongs to its own box.  Also builds the multigrid
+   hierarchy.  n_ghost_out (host) receives the ghost count.  Synchronises `stream`. */
+ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_out);
+
+/* Copy ghost data to host arrays (any may be NULL): cell[n_G] int32 linear cell index,
+   bi_xyz/n_xyz/ip_xyz[3*n_G], stencil[8*n_G] int32 (-1 = unused or the ghost's own
+   Neumann slot), beta[8*n_G], flags[n_G] (bit0 degenerate, bit1 clamped image point, bit2
+   facet-normal fallback, bit3 ghost in its own box).  Synchronises `stream`. */
+ibm_status ibm_get_ghosts(const ibm_grid *g, void *stream, int32_t *cell, double *bi_xyz, double *n_xyz,
+                          double *ip_xyz, int32_t *stencil, double *beta, int32_t *flags);
+
+/* Neumann data dp/dn at each body intercept (host, n_G values; NULL = all zero, the
+   projection's condition).  Default after build_ghost_stencils: zero. */
+ibm_status ibm_set_neumann_data(ibm_grid *g, const double *dpdn, void *stream);
+
+/* Copy the cell types (0 fluid, 1 ghost, 2 dead; uint8 [nz][ny][nx]) to device memory. */
+ibm_status ibm_get_cell_types(const ibm_grid *g, uint8_t *dst_device, void *stream);
+
+/* Solve the pressure Poisson equation S p = rhs - lambda on fluid cells with the implicit
+   ghost equations, gauge sum_fluid V p = 0 (Section 2.1: the pressure equation of the
+   fractional step; the solver is a geometric multigrid V-cycle with red-black Gauss-Seidel
+   smoothing).  rhs, p: device, [nz][ny][nx] FP64.  p is overwritten (initial guess read when
+   o->use_initial_guess); dead cells are set to 0.  Synchronises `stream` once per cycle. */
+ibm_status ibm_poisson_solve(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o,
+                             ibm_solve_stats *s, void *stream);
+
+/* Full projection (Section 2.1, fractional step): rhs = (D u*)/dt on fluid cells, solve,
+   then u_f -= dt (p_nb - p_c)/d_f on every interior face touching a fluid cell.  u, v, w:
+   device MAC arrays, corrected in place; p: device, out. */
+ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, double *p,
+                       const ibm_solve_opts *o, ibm_solve_stats *s, void *stream);
+
+/* Non-blocking step API for serving: begin enqueues the initial residual, step enqueues
+   n_cycles cycles plus an asynchronous read-back of the residual norm, poll never blocks
+   (done = 1 once converged, failed or out of cycles; stats valid then).  rhs and p must stay
+   valid until done.  At completion the gauge is applied on the handle's stream. */
+ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, void *stream);
+ibm_status ibm_solve_step(ibm_grid *g, int n_cycles);
+ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *s);
+
+/* Level count and dims of the multigrid hierarchy (after build_ghost_stencils). */
+ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims /* 3*n_levels, may be NULL */);
+
+/* ---- single-step hooks for kernel-level parity tests -------------------------------- */
+
+/* n red-black sweeps of level 0 on p (device, in/out) with right-hand side rhs and shift
+   lambda; refresh != 0 follows each sweep with a ghost refresh. */
+ibm_status ibm_debug_sweep(ibm_grid *g, double *p, const double *rhs, double lambda, int n, int refresh,
+                           void *stream);
+/* (S p) on fluid rows, 0 elsewhere (device in/out). */
+ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stream);
+
+/* Timing of the level-0 smoother: with profiling on, every fine-level red-black sweep is
+   bracketed by HIP events on its launch stream (at most 32 sweeps between two host
+   synchronisations are timed).  get_profile returns the summed milliseconds and the number
+   of timed FP64 and FP32 sweeps since profiling was switched on. */
+ibm_status ibm_set_profiling(ibm_grid *g, int on);
+ibm_status ibm_get_profile(const ibm_grid *g, double *ms_fp64, int64_t *n_fp64, double *ms_fp32, int64_t *n_fp32);
+
+void ibm_destroy_grid(ibm_grid *g);
+const char *ibm_last_error(const ibm_grid *g); /* g == NULL: last error of this thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBM_H */

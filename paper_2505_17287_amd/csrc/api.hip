@@ -1,0 +1,833 @@
+// C ABI of the ghost-cell IBM projection library (declarations and contracts: include/ibm.h).
+// Host-side logic only: argument checks, workspace layout, call-order state, mesh
+// validation, multigrid level planning and the solve drivers.  Every step of the method
+// runs in the kernels of geometry.hip and solver.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ibm_impl.hpp"
+
+using namespace ibm;
+
+namespace {
+
+thread_local std::string t_last_error;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+ibm_status fail(ibm_grid *g, ibm_status st, const std::string &msg) {
+    t_last_error = msg;
+    if (g) g->err = msg;
+    return st;
+}
+
+ibm_status hip_fail(ibm_grid *g, hipError_t e, const char *where) {
+    return fail(g, IBM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                         \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(g, _e, where); \
+    } while (0)
+
+bool finite_increasing(const double *f, int n) {
+    for (int i = 0; i <= n; ++i)
+        if (!std::isfinite(f[i])) return false;
+    for (int i = 0; i < n; ++i)
+        if (!(f[i + 1] > f[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+namespace ibm {
+
+// Semi-coarsening plan: an axis is coarsenable when its count is even and >= 4; among the
+// coarsenable axes, those whose smallest width is below 1.5x the smallest width of any
+// coarsenable axis are halved.  Coarse faces are every other fine face.
+void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, LevelHost *lev,
+                 int *nlev) {
+    LevelHost &L0 = lev[0];
+    L0.n[0] = nx;
+    L0.n[1] = ny;
+    L0.n[2] = nz;
+    const double *fs[3] = {xf, yf, zf};
+    for (int d = 0; d < 3; ++d) {
+        L0.halved[d] = 0;
+        L0.f[d].assign(fs[d], fs[d] + L0.n[d] + 1);
+        L0.c[d].resize(L0.n[d]);
+        L0.w[d].resize(L0.n[d]);
+        for (int i = 0; i < L0.n[d]; ++i) {
+            L0.c[d][i] = 0.5 * (L0.f[d][i] + L0.f[d][i + 1]);
+            L0.w[d][i] = L0.f[d][i + 1] - L0.f[d][i];
+        }
+    }
+    int n = 1;
+    while (n < MAX_LEVELS) {
+        LevelHost &F = lev[n - 1];
+        double m = INFINITY;
+        bool can[3];
+        double mw[3];
+        for (int d = 0; d < 3; ++d) {
+            can[d] = F.n[d] >= 4 && F.n[d] % 2 == 0;
+            mw[d] = *std::min_element(F.w[d].begin(), F.w[d].end());
+            if (can[d]) m = std::min(m, mw[d]);
+        }
+        int h[3];
+        bool any = false;
+        for (int d = 0; d < 3; ++d) {
+            h[d] = (can[d] && mw[d] < 1.5 * m) ? 1 : 0;
+            any = any || h[d];
+        }
+        if (!any) break;
+        LevelHost &C = lev[n];
+        for (int d = 0; d < 3; ++d) {
+            C.halved[d] = h[d];
+            C.n[d] = h[d] ? F.n[d] / 2 : F.n[d];
+            C.f[d].resize(C.n[d] + 1);
+            for (int q = 0; q <= C.n[d]; ++q) C.f[d][q] = F.f[d][h[d] ? 2 * q : q];
+            C.c[d].resize(C.n[d]);
+            C.w[d].resize(C.n[d]);
+            for (int i = 0; i < C.n[d]; ++i) {
+                C.c[d][i] = 0.5 * (C.f[d][i] + C.f[d][i + 1]);
+                C.w[d][i] = C.f[d][i + 1] - C.f[d][i];
+            }
+        }
+        ++n;
+    }
+    *nlev = n;
+}
+
+size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t gmax,
+              ibm_precision prec, LevelHost *lev, int nlev) {
+    const int64_t N = (int64_t)nx * ny * nz, ncol = (int64_t)nx * ny;
+    const int n[3] = {nx, ny, nz};
+    ibm_grid tmp;
+    ibm_grid *G = g ? g : &tmp;
+    G->type = P.take<uint8_t>(N);
+    G->p2 = P.take<double>(N);
+    G->frhs = P.take<double>(N);
+    if (prec == IBM_MIXED) {
+        G->e32a = P.take<float>(N);
+        G->e32b = P.take<float>(N);
+        G->r32 = P.take<float>(N);
+    } else {
+        G->e32a = G->e32b = G->r32 = nullptr;
+    }
+    for (int d = 0; d < 3; ++d) {
+        G->faces[d] = P.take<double>(n[d] + 1);
+        G->c0[d] = P.take<double>(n[d]);
+        G->w0[d] = P.take<double>(n[d]);
+        G->dc0[d] = P.take<double>(n[d]);
+        G->am0[d] = P.take<double>(n[d]);
+        G->ap0[d] = P.take<double>(n[d]);
+        G->am0f[d] = P.take<float>(n[d]);
+        G->ap0f[d] = P.take<float>(n[d]);
+        G->w0f[d] = P.take<float>(n[d]);
+    }
+    G->verts = P.take<double>(3 * std::max<int64_t>(nv_max, 3));
+    G->tris = P.take<int32_t>(3 * std::max<int64_t>(nt_max, 1));
+    G->bucket_cnt = P.take<int32_t>(NBUCKET_MAX + 1);
+    G->bucket_off = P.take<int32_t>(NBUCKET_MAX + 1);
+    G->bucket_ent = P.take<int32_t>(8 * std::max<int64_t>(nt_max, 1) + 16);
+    G->col_cnt = P.take<int32_t>(ncol + 1);
+    G->col_off = P.take<int32_t>(ncol + 1);
+    G->col_fill = P.take<int32_t>(std::max<int64_t>(ncol + 1, NBUCKET_MAX + 1));
+    G->cross_cap = 8 * ncol + 4 * std::max<int64_t>(nt_max, 1) + 1024;
+    G->crossings = P.take<double>(std::max<int64_t>(G->cross_cap, N / 256 + 1024));
+    G->blk_cnt = (int32_t *)P.take<int64_t>(8192);
+    G->counters = P.take<int64_t>(16);
+    const int64_t gm = std::max<int64_t>(gmax, 1);
+    G->g_cell = P.take<int32_t>(gm);
+    G->g_st = P.take<int32_t>(8 * gm);
+    G->g_flags = P.take<int32_t>(gm);
+    G->g_tri = P.take<int32_t>(gm);
+    G->g_mask = P.take<uint8_t>(gm);
+    G->g_bi = P.take<double>(3 * gm);
+    G->g_n = P.take<double>(3 * gm);
+    G->g_ip = P.take<double>(3 * gm);
+    G->g_beta = P.take<double>(8 * gm);
+    G->g_betag = P.take<double>(gm);
+    G->g_dl = P.take<double>(gm);
+    G->g_h = P.take<double>(gm);
+    G->g_data = P.take<double>(gm);
+    for (int l = 0; l < nlev; ++l) {
+        LevelHost &L = lev[l];
+        const int64_t NC = L.ncell();
+        if (l >= 1) {
+            L.active = P.take<uint8_t>(NC);
+            for (int d = 0; d < 3; ++d) {
+                L.T64[d] = P.take<double>(NC);
+                L.T32[d] = P.take<float>(NC);
+                L.w64[d] = P.take<double>(L.n[d]);
+                L.w32[d] = P.take<float>(L.n[d]);
+                L.c64[d] = P.take<double>(2 * L.n[d] + 1);  // centres, then the faces
+            }
+            L.e64 = P.take<double>(NC);
+            L.R64 = P.take<double>(NC);
+            L.e32 = P.take<float>(NC);
+            L.R32 = P.take<float>(NC);
+        }
+        if (l + 1 < nlev) {
+            for (int d = 0; d < 3; ++d) {
+                L.plo[d] = P.take<int>(L.n[d]);
+                L.phi[d] = P.take<int>(L.n[d]);
+                L.pt[d] = P.take<double>(L.n[d]);
+            }
+        }
+    }
+    G->partials = P.take<double>(std::max<int64_t>(4 * RED_BLOCKS, N / 256 + 1024));
+    G->sc = P.take<Scalars>(1);
+    return P.off + 256;
+}
+
+}  // namespace ibm
+
+
+extern "C" {
+
+void ibm_default_opts(ibm_solve_opts *o) {
+    if (!o) return;
+    o->rel_tol = 1e-10;
+    o->max_cycles = 200;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->coarsest_sweeps = 64;
+    o->precision = IBM_FP64;
+    o->use_initial_guess = 0;
+    o->fixed_cycles = 0;
+}
+
+ibm_status ibm_create_grid(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                           ibm_grid **out) {
+    if (!out) return fail(nullptr, IBM_E_ARG, "ibm_create_grid: out is NULL");
+    *out = nullptr;
+    if (nx < 2 || ny < 2 || nz < 1) return fail(nullptr, IBM_E_ARG, "ibm_create_grid: need nx, ny >= 2 and nz >= 1");
+    if ((int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return fail(nullptr, IBM_E_ARG, "ibm_create_grid: more than 2^31 cells");
+    if (!xf || !yf || !zf) return fail(nullptr, IBM_E_ARG, "ibm_create_grid: NULL face array");
+    if (!finite_increasing(xf, nx) || !finite_increasing(yf, ny) || !finite_increasing(zf, nz))
+        return fail(nullptr, IBM_E_ARG, "ibm_create_grid: face coordinates must be finite and strictly increasing");
+    ibm_grid *g = new ibm_grid();
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->N = (int64_t)nx * ny * nz;
+    g->xf.assign(xf, xf + nx + 1);
+    g->yf.assign(yf, yf + ny + 1);
+    g->zf.assign(zf, zf + nz + 1);
+    plan_levels(nx, ny, nz, xf, yf, zf, g->lev, &g->nlev);
+    g->stage = ST_CREATED;
+    *out = g;
+    return IBM_OK;
+}
+
+size_t ibm_workspace_bytes(int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t max_ghosts,
+                           ibm_precision prec) {
+    if (nx < 2 || ny < 2 || nz < 1) return 0;
+    // Upper bound for any face coordinates: the fine level exactly, plus coarse levels of at
+    // most half the previous level's cells each (their sum stays below N) at 61 B per coarse
+    // cell, plus per-level 1D arrays and alignment.
+    LevelHost lev[1];
+    lev[0].n[0] = nx;
+    lev[0].n[1] = ny;
+    lev[0].n[2] = nz;
+    Plan P;
+    size_t b = layout(nullptr, P, nx, ny, nz, nv_max, nt_max, max_ghosts, prec, lev, 1);
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t axes = (int64_t)nx + ny + nz;
+    return b + (size_t)N * 61 + (size_t)MAX_LEVELS * (size_t)(axes * 64 + 32 * 256) + (1 << 20);
+}
+
+size_t ibm_grid_workspace_bytes(const ibm_grid *gc, int64_t nv_max, int64_t nt_max, int64_t max_ghosts,
+                                ibm_precision prec) {
+    if (!gc) return 0;
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    LevelHost lev[MAX_LEVELS];
+    for (int l = 0; l < g->nlev; ++l)
+        for (int d = 0; d < 3; ++d) {
+            lev[l].n[d] = g->lev[l].n[d];
+            lev[l].halved[d] = g->lev[l].halved[d];
+        }
+    Plan P;
+    return layout(nullptr, P, g->nx, g->ny, g->nz, nv_max, nt_max, max_ghosts, prec, lev, g->nlev);
+}
+
+ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64_t nv_max, int64_t nt_max,
+                              int64_t max_ghosts, ibm_precision prec, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_bind_workspace: NULL handle");
+    if (!device_ptr || ((uintptr_t)device_ptr & 255)) return fail(g, IBM_E_ARG, "workspace must be 256-byte aligned");
+    if (nv_max < 3 || nt_max < 1 || max_ghosts < 0) return fail(g, IBM_E_ARG, "invalid mesh / ghost capacities");
+    size_t need = ibm_grid_workspace_bytes(g, nv_max, nt_max, max_ghosts, prec);
+    if (bytes < need)
+        return fail(g, IBM_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    Plan P;
+    P.base = (char *)device_ptr;
+    layout(g, P, g->nx, g->ny, g->nz, nv_max, nt_max, max_ghosts, prec, g->lev, g->nlev);
+    g->ws = (char *)device_ptr;
+    g->ws_bytes = bytes;
+    g->nv_max = nv_max;
+    g->nt_max = nt_max;
+    g->ghost_max = max_ghosts;
+    g->prec = prec;
+    if (!g->sc_host) HIP_TRY(hipHostMalloc((void **)&g->sc_host, sizeof(Scalars), hipHostMallocDefault), "hipHostMalloc");
+    const std::vector<double> *fs[3] = {&g->xf, &g->yf, &g->zf};
+    for (int d = 0; d < 3; ++d)
+        HIP_TRY(hipMemcpyAsync(g->faces[d], fs[d]->data(), sizeof(double) * fs[d]->size(), hipMemcpyHostToDevice, s),
+                "upload faces");
+    for (int l = 1; l < g->nlev; ++l)
+        for (int d = 0; d < 3; ++d)
+            HIP_TRY(hipMemcpyAsync(g->lev[l].c64[d] + g->lev[l].n[d], g->lev[l].f[d].data(),
+                                   sizeof(double) * (g->lev[l].n[d] + 1), hipMemcpyHostToDevice, s),
+                    "upload coarse faces");
+    HIP_TRY(hipMemsetAsync(g->sc, 0, sizeof(Scalars), s), "memset scalars");
+    HIP_TRY(launch_metrics(g, s), "metrics");
+    HIP_TRY(hipStreamSynchronize(s), "bind sync");
+    g->stage = ST_BOUND;
+    g->ng = 0;
+    return IBM_OK;
+}
+
+ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                            void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_geometry: NULL handle");
+    if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_set_geometry before ibm_bind_workspace");
+    if (!verts || !tris || nv < 3 || nt < 1) return fail(g, IBM_E_ARG, "ibm_set_geometry: empty mesh");
+    if (nv > g->nv_max || nt > g->nt_max) return fail(g, IBM_E_NOMEM, "mesh larger than the bound capacities");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(verts[i])) return fail(g, IBM_E_ARG, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < 3 * nt; ++i)
+        if (tris[i] < 0 || tris[i] >= nv) return fail(g, IBM_E_ARG, "triangle index out of range");
+    // closed and consistently oriented: every directed edge once and its reverse once
+    std::vector<int64_t> e(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int q = 0; q < 3; ++q) e[3 * t + q] = (int64_t)tris[3 * t + q] * nv + tris[3 * t + (q + 1) % 3];
+    std::sort(e.begin(), e.end());
+    for (size_t i = 0; i < e.size(); ++i) {
+        if (i + 1 < e.size() && e[i + 1] == e[i])
+            return fail(g, IBM_E_GEOMETRY, "mesh is not consistently oriented (directed edge used twice)");
+        int64_t a = e[i] / nv, b = e[i] % nv;
+        if (a == b) return fail(g, IBM_E_GEOMETRY, "degenerate edge");
+        if (!std::binary_search(e.begin(), e.end(), b * nv + a))
+            return fail(g, IBM_E_GEOMETRY, "mesh is not closed (edge without its reverse)");
+    }
+    // bucket grid over the mesh bounding box: buckets at least as large as the largest
+    // triangle extent, so a triangle overlaps at most 2 buckets per axis
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext[3] = {0, 0, 0};
+    for (int64_t t = 0; t < nt; ++t) {
+        double tl[3] = {INFINITY, INFINITY, INFINITY}, th[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = 0; q < 3; ++q)
+            for (int d = 0; d < 3; ++d) {
+                double x = verts[3 * tris[3 * t + q] + d];
+                tl[d] = std::min(tl[d], x);
+                th[d] = std::max(th[d], x);
+            }
+        for (int d = 0; d < 3; ++d) {
+            ext[d] = std::max(ext[d], th[d] - tl[d]);
+            lo[d] = std::min(lo[d], tl[d]);
+            hi[d] = std::max(hi[d], th[d]);
+        }
+    }
+    double span[3], vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        span[d] = std::max(hi[d] - lo[d], 1e-12);
+        vol *= span[d];
+    }
+    double target = std::cbrt(vol / (double)std::max<int64_t>(nt, 1));
+    int64_t total = 1;
+    for (int d = 0; d < 3; ++d) {
+        double sz = std::max(ext[d], target);
+        int nbd = (int)std::max(1.0, std::floor(span[d] / sz));
+        g->nb[d] = std::min(nbd, 256);
+        total *= g->nb[d];
+    }
+    while (total > NBUCKET_MAX) {
+        for (int d = 0; d < 3; ++d) g->nb[d] = std::max(1, g->nb[d] / 2);
+        total = (int64_t)g->nb[0] * g->nb[1] * g->nb[2];
+    }
+    for (int d = 0; d < 3; ++d) {
+        g->bmin[d] = lo[d];
+        g->bsize[d] = span[d] / g->nb[d];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(g->verts, verts, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s), "upload verts");
+    HIP_TRY(hipMemcpyAsync(g->tris, tris, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s), "upload tris");
+    g->nv = nv;
+    g->nt = nt;
+    HIP_TRY(launch_buckets(g, s), "bucket grid");
+    int64_t bucket_overflow = 0;
+    HIP_TRY(hipMemcpyAsync(&bucket_overflow, g->counters + 6, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read");
+    HIP_TRY(hipStreamSynchronize(s), "set_geometry sync");  // host arrays may be freed after return
+    if (bucket_overflow) return fail(g, IBM_E_NOMEM, "triangle bucket grid overflow");
+    g->stage = ST_GEOMETRY;
+    g->ng = 0;
+    return IBM_OK;
+}
+
+ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_classify: NULL handle");
+    if (g->stage < ST_GEOMETRY) return fail(g, IBM_E_STATE, "ibm_classify before ibm_set_geometry");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    int64_t c[4];
+    HIP_TRY(launch_classify(g, s, c), "classify");
+    int64_t odd = c[3] & (((int64_t)1 << 40) - 1);
+    bool overflow = (c[3] >> 40) != 0;
+    if (overflow) return fail(g, IBM_E_NOMEM, "too many ray crossings for the workspace");
+    g->nfluid = c[0];
+    g->nghost_cells = c[1];
+    g->ndead = c[2];
+    if (counts_out) {
+        counts_out[0] = c[0];
+        counts_out[1] = c[1];
+        counts_out[2] = c[2];
+    }
+    if (c[1] > g->ghost_max) {
+        g->stage = ST_GEOMETRY;
+        return fail(g, IBM_E_NOMEM, "ghost cells " + std::to_string(c[1]) + " exceed the bound capacity " +
+                                        std::to_string(g->ghost_max));
+    }
+    if (c[0] == 0) return fail(g, IBM_E_GEOMETRY, "no fluid cell");
+    g->ng = c[1];
+    (void)odd;
+    g->stage = ST_CLASSIFIED;
+    return IBM_OK;
+}
+
+ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_out) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_build_ghost_stencils: NULL handle");
+    if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_build_ghost_stencils before ibm_classify");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemsetAsync(g->counters + 5, 0, sizeof(int64_t), s), "memset");
+    HIP_TRY(launch_stencils(g, s), "ghost stencils");
+    if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_data, 0, sizeof(double) * g->ng, s), "memset neumann");
+    HIP_TRY(launch_ghost_h(g, s), "ghost rhs");
+    HIP_TRY(launch_hierarchy(g, s), "hierarchy");
+    int64_t ndeg = 0;
+    HIP_TRY(hipMemcpyAsync(&ndeg, g->counters + 5, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read counters");
+    HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s), "read scalars");
+    HIP_TRY(hipStreamSynchronize(s), "stencils sync");
+    g->ndegenerate = ndeg;
+    g->vol_fluid = g->sc_host->vol[0];
+    for (int l = 0; l < g->nlev; ++l) g->lev[l].vol_active = g->sc_host->vol[l];
+    if (n_ghost_out) *n_ghost_out = g->ng;
+    g->stage = ST_STENCILS;
+    return IBM_OK;
+}
+
+ibm_status ibm_get_ghosts(const ibm_grid *gc, void *stream, int32_t *cell, double *bi_xyz, double *n_xyz,
+                          double *ip_xyz, int32_t *stencil, double *beta, int32_t *flags) {
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_get_ghosts: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_get_ghosts before ibm_build_ghost_stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    const int64_t ng = g->ng;
+    if (ng > 0) {
+        if (cell) HIP_TRY(hipMemcpyAsync(cell, g->g_cell, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (bi_xyz) HIP_TRY(hipMemcpyAsync(bi_xyz, g->g_bi, sizeof(double) * 3 * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (n_xyz) HIP_TRY(hipMemcpyAsync(n_xyz, g->g_n, sizeof(double) * 3 * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (ip_xyz) HIP_TRY(hipMemcpyAsync(ip_xyz, g->g_ip, sizeof(double) * 3 * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (stencil)
+            HIP_TRY(hipMemcpyAsync(stencil, g->g_st, sizeof(int32_t) * 8 * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (beta) HIP_TRY(hipMemcpyAsync(beta, g->g_beta, sizeof(double) * 8 * ng, hipMemcpyDeviceToHost, s), "copy");
+        if (flags) HIP_TRY(hipMemcpyAsync(flags, g->g_flags, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, s), "copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "get_ghosts sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_set_neumann_data(ibm_grid *g, const double *dpdn, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_neumann_data: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_set_neumann_data before ibm_build_ghost_stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    if (g->ng > 0) {
+        if (dpdn) {
+            for (int64_t q = 0; q < g->ng; ++q)
+                if (!std::isfinite(dpdn[q])) return fail(g, IBM_E_ARG, "non-finite Neumann data");
+            HIP_TRY(hipMemcpyAsync(g->g_data, dpdn, sizeof(double) * g->ng, hipMemcpyHostToDevice, s), "upload");
+        } else {
+            HIP_TRY(hipMemsetAsync(g->g_data, 0, sizeof(double) * g->ng, s), "memset");
+        }
+        HIP_TRY(launch_ghost_h(g, s), "ghost rhs");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "neumann sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_get_cell_types(const ibm_grid *gc, uint8_t *dst_device, void *stream) {
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    if (!g || !dst_device) return fail(g, IBM_E_ARG, "ibm_get_cell_types: NULL argument");
+    if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_get_cell_types before ibm_classify");
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(dst_device, g->type, (size_t)g->N, hipMemcpyDeviceToDevice, (hipStream_t)stream), "copy");
+    return IBM_OK;
+}
+
+ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims) {
+    if (!g || !n_levels) return fail(const_cast<ibm_grid *>(g), IBM_E_ARG, "ibm_get_levels: NULL argument");
+    *n_levels = g->nlev;
+    if (dims)
+        for (int l = 0; l < g->nlev; ++l)
+            for (int d = 0; d < 3; ++d) dims[3 * l + d] = g->lev[l].n[d];
+    return IBM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// solve drivers
+// ------------------------------------------------------------------------------------------
+
+static ibm_status check_opts(ibm_grid *g, const ibm_solve_opts *o) {
+    if (!o) return fail(g, IBM_E_ARG, "NULL options");
+    if (!(o->rel_tol >= 0.0) || o->max_cycles < 1 || o->nu1 < 0 || o->nu2 < 0 || o->coarsest_sweeps < 0 ||
+        o->fixed_cycles < 0)
+        return fail(g, IBM_E_ARG, "invalid solver options");
+    if (o->precision == IBM_MIXED && g->prec != IBM_MIXED)
+        return fail(g, IBM_E_STATE, "mixed precision needs a workspace bound with IBM_MIXED");
+    if (o->precision != IBM_FP64 && o->precision != IBM_MIXED) return fail(g, IBM_E_ARG, "unknown precision");
+    return IBM_OK;
+}
+
+// enqueue: lambda reset, reference norm, initial iterate + ghost refresh, first residual norm
+static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, hipStream_t s) {
+    hipError_t e;
+    if ((e = hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s)) != hipSuccess) return e;
+    if ((e = ref_norm_pass(g, rhs, s)) != hipSuccess) return e;
+    if ((e = init_solution(g, p, g->p2, o->use_initial_guess, s)) != hipSuccess) return e;
+    if ((e = norm_pass(g, g->p2, rhs, s, o->precision == IBM_MIXED, true)) != hipSuccess) return e;
+    return hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s);
+}
+
+static hipError_t enqueue_cycle(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, int *cur,
+                                hipStream_t s) {
+    double *bufs[2] = {p, g->p2};
+    hipError_t e;
+    if (o->precision == IBM_MIXED) e = vcycle_mixed(g, bufs, cur, rhs, s, o);
+    else e = vcycle_f64(g, bufs, cur, rhs, s, o);
+    if (e != hipSuccess) return e;
+    return norm_pass(g, bufs[*cur], rhs, s, o->precision == IBM_MIXED, false);
+}
+
+// accumulate the timed smoother launches of the batch that just completed
+static void prof_collect(ibm_grid *g) {
+    Prof &P = g->prof;
+    for (int q = 0; q + 1 < P.used; q += 2) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, P.ev[q], P.ev[q + 1]) == hipSuccess) {
+            P.ms[P.kind[q / 2]] += ms;
+            P.count[P.kind[q / 2]] += 1;
+        }
+    }
+    P.used = 0;
+}
+
+static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, ibm_solve_stats *st,
+                             hipStream_t s) {
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "solve before ibm_build_ghost_stencils");
+    ibm_status cs = check_opts(g, o);
+    if (cs != IBM_OK) return cs;
+    if (!rhs || !p) return fail(g, IBM_E_ARG, "NULL rhs or p");
+    double t0 = now_s();
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(enqueue_begin(g, rhs, p, o, s), "solve begin");
+    HIP_TRY(hipStreamSynchronize(s), "solve sync");
+    Scalars *hs = g->sc_host;
+    if (hs->bad) return fail(g, IBM_E_NUMERIC, "non-finite right-hand side or initial guess");
+    double r0 = hs->norm;
+    if (!(hs->ref > 0.0)) {
+        // zero-mean-free right-hand side: measure against the initial residual
+        double ref = r0;
+        HIP_TRY(hipMemcpyAsync(&g->sc->ref, &ref, sizeof(double), hipMemcpyHostToDevice, s), "set ref");
+        hs->ref = ref;
+    }
+    int cur = 1;
+    double *bufs[2] = {p, g->p2};
+    int cycles = 0;
+    ibm_status status = IBM_OK;
+    double rel = hs->ref > 0.0 ? r0 / hs->ref : 0.0;
+    if (hs->ref > 0.0) {
+        const int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
+        for (cycles = 1; cycles <= ncyc; ++cycles) {
+            HIP_TRY(enqueue_cycle(g, rhs, p, o, &cur, s), "cycle");
+            HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read norm");
+            HIP_TRY(hipStreamSynchronize(s), "cycle sync");
+            if (g->prof.on) prof_collect(g);
+            rel = hs->rel;
+            if (hs->bad || !std::isfinite(hs->norm)) {
+                status = IBM_E_NUMERIC;
+                break;
+            }
+            if (hs->norm > 1e3 * std::max(r0, hs->ref)) {
+                status = IBM_E_NUMERIC;
+                break;
+            }
+            if (o->fixed_cycles <= 0 && rel <= o->rel_tol) break;
+        }
+        if (cycles > ncyc) cycles = ncyc;
+        if (status == IBM_OK && o->fixed_cycles <= 0 && rel > o->rel_tol) status = IBM_NOT_CONVERGED;
+    }
+    HIP_TRY(gauge_pass(g, bufs[cur], p, s), "gauge");
+    HIP_TRY(hipStreamSynchronize(s), "gauge sync");
+    if (st) {
+        st->cycles = cycles;
+        st->rel_residual = rel;
+        st->ghost_residual_max = 0.0;
+        st->lambda = hs->lambda;
+        st->div_max = 0.0;
+        st->t_setup = 0.0;
+        st->t_solve = now_s() - t0;
+        st->t_correct = 0.0;
+    }
+    if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite or diverging residual");
+    return status;
+}
+
+extern "C" {
+
+ibm_status ibm_poisson_solve(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, ibm_solve_stats *s,
+                             void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_poisson_solve: NULL handle");
+    return solve_core(g, rhs, p, o, s, (hipStream_t)stream);
+}
+
+ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, double *p, const ibm_solve_opts *o,
+                       ibm_solve_stats *st, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_project: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_project before ibm_build_ghost_stencils");
+    if (!u || !v || !w || !p) return fail(g, IBM_E_ARG, "NULL velocity or pressure");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(g, IBM_E_ARG, "dt must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    double t0 = now_s();
+    double *f = g->frhs;
+    HIP_TRY(rhs_pass(g, u, v, w, dt, f, s), "rhs");
+    ibm_status rs = solve_core(g, f, p, o, st, s);
+    if (rs < 0) return rs;
+    double t1 = now_s();
+    HIP_TRY(correct_pass(g, u, v, w, p, dt, s), "correct");
+    HIP_TRY(divmax_pass(g, u, v, w, s), "divmax");
+    HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
+    HIP_TRY(hipStreamSynchronize(s), "project sync");
+    if (st) {
+        st->div_max = g->sc_host->div_max;
+        st->t_correct = now_s() - t1;
+        st->t_setup = 0.0;
+        (void)t0;
+    }
+    return rs;
+}
+
+// ---- step API --------------------------------------------------------------------------
+
+ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_solve_begin: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_solve_begin before ibm_build_ghost_stencils");
+    ibm_status cs = check_opts(g, o);
+    if (cs != IBM_OK) return cs;
+    if (!rhs || !p) return fail(g, IBM_E_ARG, "NULL rhs or p");
+    if (g->ss.active && !g->ss.done) return fail(g, IBM_E_STATE, "a solve is already in flight on this handle");
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    SolveState &S = g->ss;
+    S.active = true;
+    S.done = false;
+    S.rhs = rhs;
+    S.p_user = p;
+    S.o = *o;
+    S.stream = (hipStream_t)stream;
+    S.cycles = 0;
+    S.status = IBM_OK;
+    S.r0 = -1.0;
+    S.cur = 1;
+    S.t0 = now_s();
+    S.finishing = false;
+    if (!S.ev) HIP_TRY(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming), "event");
+    HIP_TRY(enqueue_begin(g, rhs, p, o, S.stream), "begin");
+    HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
+    S.ev_pending = true;
+    return IBM_OK;
+}
+
+ibm_status ibm_solve_step(ibm_grid *g, int n_cycles) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_solve_step: NULL handle");
+    SolveState &S = g->ss;
+    if (!S.active || S.done) return fail(g, IBM_E_STATE, "no solve in flight");
+    if (S.ev_pending || S.finishing) return fail(g, IBM_E_STATE, "previous step not yet polled");
+    if (n_cycles < 1) return fail(g, IBM_E_ARG, "n_cycles must be >= 1");
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    const int ncyc = S.o.fixed_cycles > 0 ? S.o.fixed_cycles : S.o.max_cycles;
+    for (int q = 0; q < n_cycles && S.cycles < ncyc; ++q) {
+        HIP_TRY(enqueue_cycle(g, S.rhs, S.p_user, &S.o, &S.cur, S.stream), "step");
+        S.cycles++;
+    }
+    HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream), "read");
+    HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
+    S.ev_pending = true;
+    return IBM_OK;
+}
+
+ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
+    if (!g || !done) return fail(g, IBM_E_ARG, "ibm_solve_poll: NULL argument");
+    SolveState &S = g->ss;
+    if (!S.active) return fail(g, IBM_E_STATE, "no solve started");
+    if (S.done) {
+        *done = 1;
+        return (ibm_status)S.status;
+    }
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    if (S.ev_pending) {
+        hipError_t q = hipEventQuery(S.ev);
+        if (q == hipErrorNotReady) {
+            *done = 0;
+            return IBM_OK;
+        }
+        if (q != hipSuccess) return hip_fail(g, q, "event query");
+        S.ev_pending = false;
+        if (g->prof.on) prof_collect(g);
+        Scalars *hs = g->sc_host;
+        if (S.finishing) {
+            S.done = true;
+            *done = 1;
+            if (st) {
+                st->cycles = S.cycles;
+                st->rel_residual = hs->rel;
+                st->ghost_residual_max = 0.0;
+                st->lambda = hs->lambda;
+                st->div_max = 0.0;
+                st->t_setup = 0.0;
+                st->t_solve = now_s() - S.t0;
+                st->t_correct = 0.0;
+            }
+            return (ibm_status)S.status;
+        }
+        bool finish = false;
+        if (S.r0 < 0.0) {
+            S.r0 = hs->norm;
+            if (hs->bad) {
+                S.status = IBM_E_NUMERIC;
+                finish = true;
+            } else if (!(hs->ref > 0.0)) {
+                double ref = S.r0;
+                hs->ref = ref;
+                HIP_TRY(hipMemcpyAsync(&g->sc->ref, &g->sc_host->ref, sizeof(double), hipMemcpyHostToDevice, S.stream),
+                        "set ref");
+                if (!(ref > 0.0)) finish = true;
+            }
+        } else {
+            const int ncyc = S.o.fixed_cycles > 0 ? S.o.fixed_cycles : S.o.max_cycles;
+            if (hs->bad || !std::isfinite(hs->norm) || hs->norm > 1e3 * std::max(S.r0, hs->ref)) {
+                S.status = IBM_E_NUMERIC;
+                finish = true;
+            } else if (S.o.fixed_cycles <= 0 && hs->rel <= S.o.rel_tol) {
+                finish = true;
+            } else if (S.cycles >= ncyc) {
+                if (S.o.fixed_cycles <= 0) S.status = IBM_NOT_CONVERGED;
+                finish = true;
+            }
+        }
+        if (finish) {
+            double *bufs[2] = {S.p_user, g->p2};
+            HIP_TRY(gauge_pass(g, bufs[S.cur], S.p_user, S.stream), "gauge");
+            HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream), "read");
+            HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
+            S.ev_pending = true;
+            S.finishing = true;
+            *done = 0;
+            return IBM_OK;
+        }
+        *done = -1;  // idle: waiting for ibm_solve_step
+        return IBM_OK;
+    }
+    *done = S.finishing ? 0 : -1;
+    return IBM_OK;
+}
+
+// ---- kernel-level hooks -----------------------------------------------------------------
+
+ibm_status ibm_debug_sweep(ibm_grid *g, double *p, const double *rhs, double lambda, int n, int refresh,
+                           void *stream) {
+    if (!g || !p || !rhs) return fail(g, IBM_E_ARG, "ibm_debug_sweep: NULL argument");
+    if (g->stage < ST_CLASSIFIED || (refresh && g->stage < ST_STENCILS))
+        return fail(g, IBM_E_STATE, "ibm_debug_sweep before classification / stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(&g->sc->lambda, &lambda, sizeof(double), hipMemcpyHostToDevice, s), "set lambda");
+    HIP_TRY(hipMemcpyAsync(g->p2, p, sizeof(double) * g->N, hipMemcpyDeviceToDevice, s), "copy");
+    double *bufs[2] = {p, g->p2};
+    int cur = 0;
+    for (int q = 0; q < n; ++q) {
+        HIP_TRY(sweep0_f64(g, bufs[cur], bufs[1 - cur], rhs, &g->sc->lambda, s), "sweep");
+        if (refresh) HIP_TRY(refresh_f64(g, bufs[cur], bufs[1 - cur], s), "refresh");
+        cur = 1 - cur;
+    }
+    if (cur == 1) HIP_TRY(hipMemcpyAsync(p, g->p2, sizeof(double) * g->N, hipMemcpyDeviceToDevice, s), "copy back");
+    HIP_TRY(hipStreamSynchronize(s), "debug sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stream) {
+    if (!g || !p || !out) return fail(g, IBM_E_ARG, "ibm_debug_apply: NULL argument");
+    if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_debug_apply before classification");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(apply0_f64(g, p, out, s), "apply");
+    HIP_TRY(hipStreamSynchronize(s), "apply sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_set_profiling(ibm_grid *g, int on) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_profiling: NULL handle");
+    Prof &P = g->prof;
+    if (on && P.ev.empty()) {
+        HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+        P.ev.resize(64);
+        P.kind.assign(32, 0);
+        for (auto &e : P.ev) HIP_TRY(hipEventCreate(&e), "event create");
+    }
+    P.on = on != 0;
+    P.used = 0;
+    P.ms[0] = P.ms[1] = 0.0;
+    P.count[0] = P.count[1] = 0;
+    return IBM_OK;
+}
+
+ibm_status ibm_get_profile(const ibm_grid *g, double *ms_fp64, int64_t *n_fp64, double *ms_fp32, int64_t *n_fp32) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_get_profile: NULL handle");
+    if (ms_fp64) *ms_fp64 = g->prof.ms[0];
+    if (n_fp64) *n_fp64 = g->prof.count[0];
+    if (ms_fp32) *ms_fp32 = g->prof.ms[1];
+    if (n_fp32) *n_fp32 = g->prof.count[1];
+    return IBM_OK;
+}
+
+void ibm_destroy_grid(ibm_grid *g) {
+    if (!g) return;
+    for (auto &e : g->prof.ev) (void)hipEventDestroy(e);
+    if (g->ss.ev) (void)hipEventDestroy(g->ss.ev);
+    if (g->sc_host) (void)hipHostFree(g->sc_host);
+    delete g;
+}
+
+const char *ibm_last_error(const ibm_grid *g) {
+    if (g) return g->err.c_str();
+    return t_last_error.c_str();
+}
+
+}  // extern "C"

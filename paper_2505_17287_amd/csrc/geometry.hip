@@ -1,0 +1,949 @@
+// Geometry kernels: grid metrics, triangle bucket grid, ray-parity classification, ghost
+// identification and compaction, body intercepts, image points and interpolation weights,
+// and the multigrid hierarchy (active masks, staircase transmissibilities, prolongation
+// tables).  Paper Section 2.1 (non-uniform Cartesian grid) and Section 2.2 (ghost cells).
+//
+// Floating-point contraction is disabled for this library, so every geometric predicate is
+// evaluated with the same IEEE operations in the same order as a plain sequential
+// evaluation: classification and intercepts are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_util.hpp"
+#include "ibm_impl.hpp"
+
+namespace ibm {
+
+// ---------------------------------------------------------------------------------------
+// grid metrics (Section 2.1): centres, widths, centre distances, flux coefficients
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_axis_metrics(int n, const double *__restrict__ f, double *c, double *w, double *dc, double *am,
+                               double *ap, float *amf, float *apf, float *wf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ci = 0.5 * (f[i] + f[i + 1]);
+    double wi = f[i + 1] - f[i];
+    c[i] = ci;
+    w[i] = wi;
+    // centre distance across face i (between cells i-1 and i); 0 at the low wall
+    double cm = (i > 0) ? 0.5 * (f[i - 1] + f[i]) : 0.0;
+    double cp = (i < n - 1) ? 0.5 * (f[i + 1] + f[i + 2]) : 0.0;
+    double d_lo = (i > 0) ? ci - cm : 0.0;
+    double d_hi = (i < n - 1) ? cp - ci : 0.0;
+    dc[i] = d_lo;
+    // per-volume flux coefficients; the box walls carry no flux (homogeneous Neumann)
+    double a_m = (i > 0) ? 1.0 / (wi * d_lo) : 0.0;
+    double a_p = (i < n - 1) ? 1.0 / (wi * d_hi) : 0.0;
+    am[i] = a_m;
+    ap[i] = a_p;
+    amf[i] = (float)a_m;
+    apf[i] = (float)a_p;
+    wf[i] = (float)wi;
+}
+
+__global__ void k_level_axis(int n, const double *__restrict__ f, double *c, double *w, float *wf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    c[i] = 0.5 * (f[i] + f[i + 1]);
+    w[i] = f[i + 1] - f[i];
+    wf[i] = (float)(f[i + 1] - f[i]);
+}
+
+hipError_t launch_metrics(ibm_grid *g, hipStream_t s) {
+    int n[3] = {g->nx, g->ny, g->nz};
+    for (int d = 0; d < 3; ++d) {
+        hipLaunchKernelGGL(k_axis_metrics, dim3((n[d] + 127) / 128), dim3(128), 0, s, n[d], g->faces[d], g->c0[d],
+                           g->w0[d], g->dc0[d], g->am0[d], g->ap0[d], g->am0f[d], g->ap0f[d], g->w0f[d]);
+    }
+    for (int l = 1; l < g->nlev; ++l) {
+        LevelHost &L = g->lev[l];
+        for (int d = 0; d < 3; ++d) {
+            // coarse faces were uploaded behind the centres array (see layout)
+            hipLaunchKernelGGL(k_level_axis, dim3((L.n[d] + 127) / 128), dim3(128), 0, s, L.n[d],
+                               L.c64[d] + L.n[d], L.c64[d], L.w64[d], L.w32[d]);
+        }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// exclusive scan of int32 counts (three kernels, fixed decomposition)
+// ---------------------------------------------------------------------------------------
+
+constexpr int SCAN_NT = 256, SCAN_PER = 16, SCAN_CH = SCAN_NT * SCAN_PER;
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_blocks(const int32_t *in, int32_t *out, int64_t n, int64_t *blk) {
+    __shared__ int64_t sh[SCAN_NT];
+    int tid = threadIdx.x;
+    int64_t base = (int64_t)blockIdx.x * SCAN_CH + (int64_t)tid * SCAN_PER;
+    int64_t loc[SCAN_PER];
+    int64_t s = 0;
+    for (int q = 0; q < SCAN_PER; ++q) {
+        int64_t idx = base + q;
+        loc[q] = s;
+        s += (idx < n) ? in[idx] : 0;
+    }
+    sh[tid] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread sums
+    for (int o = 1; o < SCAN_NT; o <<= 1) {
+        int64_t v = (tid >= o) ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += v;
+        __syncthreads();
+    }
+    int64_t excl = sh[tid] - s;
+    for (int q = 0; q < SCAN_PER; ++q) {
+        int64_t idx = base + q;
+        if (idx < n) out[idx] = (int32_t)(excl + loc[q]);
+    }
+    if (tid == SCAN_NT - 1) blk[blockIdx.x] = sh[tid];
+}
+
+// single block: exclusive scan of the block totals, total -> blk[nb]
+__global__ void __launch_bounds__(SCAN_NT) k_scan_top(int64_t *blk, int64_t nb) {
+    __shared__ int64_t sh[SCAN_NT];
+    __shared__ int64_t carry;
+    int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_NT) {
+        int64_t idx = b0 + tid;
+        int64_t v = (idx < nb) ? blk[idx] : 0;
+        sh[tid] = v;
+        __syncthreads();
+        for (int o = 1; o < SCAN_NT; o <<= 1) {
+            int64_t t = (tid >= o) ? sh[tid - o] : 0;
+            __syncthreads();
+            sh[tid] += t;
+            __syncthreads();
+        }
+        int64_t c = carry;
+        if (idx < nb) blk[idx] = c + sh[tid] - v;
+        __syncthreads();
+        if (tid == SCAN_NT - 1) carry = c + sh[tid];
+        __syncthreads();
+    }
+    if (tid == 0) blk[nb] = carry;
+}
+
+__global__ void k_scan_add(int32_t *out, int64_t n, const int64_t *blk) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] += (int32_t)blk[idx / SCAN_CH];
+}
+
+// exclusive scan of n counts into out[0..n) and the total into *total_dev (int64)
+static hipError_t scan_counts(const int32_t *in, int32_t *out, int64_t n, int64_t *blk, hipStream_t s) {
+    int64_t nb = (n + SCAN_CH - 1) / SCAN_CH;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(SCAN_NT), 0, s, in, out, n, blk);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_NT), 0, s, blk, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, blk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// triangle bucket grid for the closest-point search
+// ---------------------------------------------------------------------------------------
+
+struct BucketGrid {
+    double bmin[3], bsize[3];
+    int nb[3];
+};
+
+__device__ __forceinline__ int bucket_coord(double x, double bmin, double bsize, int nb) {
+    double q = floor((x - bmin) / bsize);
+    int b = (q < 0.0) ? 0 : (q >= (double)nb ? nb - 1 : (int)q);
+    return b;
+}
+
+__device__ __forceinline__ void tri_bbox(const double *V, const int32_t *T, int64_t t, double lo[3], double hi[3]) {
+    const int32_t a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
+    for (int d = 0; d < 3; ++d) {
+        double x = V[3 * a + d], y = V[3 * b + d], z = V[3 * c + d];
+        lo[d] = fmin(x, fmin(y, z));
+        hi[d] = fmax(x, fmax(y, z));
+    }
+}
+
+__global__ void k_bucket_pass(const double *__restrict__ V, const int32_t *__restrict__ T, int64_t nt, BucketGrid G,
+                              int32_t *cnt, const int32_t *off, int32_t *fill, int32_t *ent, int64_t cap,
+                              int64_t *overflow) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    double lo[3], hi[3];
+    tri_bbox(V, T, t, lo, hi);
+    int b0[3], b1[3];
+    for (int d = 0; d < 3; ++d) {
+        b0[d] = bucket_coord(lo[d], G.bmin[d], G.bsize[d], G.nb[d]);
+        b1[d] = bucket_coord(hi[d], G.bmin[d], G.bsize[d], G.nb[d]);
+    }
+    for (int z = b0[2]; z <= b1[2]; ++z)
+        for (int y = b0[1]; y <= b1[1]; ++y)
+            for (int x = b0[0]; x <= b1[0]; ++x) {
+                int b = (z * G.nb[1] + y) * G.nb[0] + x;
+                if (!ent) {
+                    atomicAdd(&cnt[b], 1);
+                } else {
+                    int slot = atomicAdd(&fill[b], 1);
+                    int64_t pos = (int64_t)off[b] + slot;
+                    if (pos < cap) ent[pos] = (int32_t)t;
+                    else atomicAdd((unsigned long long *)overflow, 1ull);
+                }
+            }
+}
+
+hipError_t launch_buckets(ibm_grid *g, hipStream_t s) {
+    BucketGrid G;
+    for (int d = 0; d < 3; ++d) {
+        G.bmin[d] = g->bmin[d];
+        G.bsize[d] = g->bsize[d];
+        G.nb[d] = g->nb[d];
+    }
+    int64_t nbk = (int64_t)g->nb[0] * g->nb[1] * g->nb[2];
+    hipError_t e = hipMemsetAsync(g->bucket_cnt, 0, sizeof(int32_t) * (nbk + 1), s);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(g->col_fill, 0, sizeof(int32_t) * (nbk + 1), s);
+    if (e != hipSuccess) return e;
+    unsigned nblk = (unsigned)((g->nt + 255) / 256);
+    e = hipMemsetAsync(g->counters + 6, 0, sizeof(int64_t), s);
+    if (e != hipSuccess) return e;
+    const int64_t cap = 8 * g->nt_max + 16;
+    hipLaunchKernelGGL(k_bucket_pass, dim3(nblk), dim3(256), 0, s, g->verts, g->tris, g->nt, G, g->bucket_cnt,
+                       nullptr, nullptr, nullptr, cap, g->counters + 6);
+    e = scan_counts(g->bucket_cnt, g->bucket_off, nbk + 1, (int64_t *)g->blk_cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_pass, dim3(nblk), dim3(256), 0, s, g->verts, g->tris, g->nt, G, nullptr,
+                       g->bucket_off, g->col_fill, g->bucket_ent, cap, g->counters + 6);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// classification (Section 2.2: ray tracing).  z-rays through every column centre.
+// ---------------------------------------------------------------------------------------
+
+// Edge function of the undirected edge {u,v}, evaluated from its lower vertex index so the
+// two triangles sharing the edge see exactly opposite values; > 0 when (px,py) lies left
+// of the directed edge u->v.
+__device__ __forceinline__ double edge_fn(const double *V, int32_t u, int32_t v, double px, double py) {
+    int32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    double ax = V[3 * lo], ay = V[3 * lo + 1], bx = V[3 * hi], by = V[3 * hi + 1];
+    double e = (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+    return (u == lo) ? e : -e;
+}
+
+// a point exactly on an edge of a counter-clockwise triangle belongs to it when the edge is
+// a left edge (pointing down) or a top edge (horizontal, pointing left)
+__device__ __forceinline__ bool owns_edge(const double *V, int32_t u, int32_t v) {
+    double dx = V[3 * v] - V[3 * u], dy = V[3 * v + 1] - V[3 * u + 1];
+    return (dy < 0.0) || (dy == 0.0 && dx < 0.0);
+}
+
+__device__ __forceinline__ bool ray_hits(const double *V, const int32_t *tri, double px, double py, double *z) {
+    int32_t a = tri[0], b = tri[1], c = tri[2];
+    double area = edge_fn(V, a, b, V[3 * c], V[3 * c + 1]);
+    if (area == 0.0) return false;
+    if (area < 0.0) {
+        int32_t t = b;
+        b = c;
+        c = t;
+    }
+    double wab = edge_fn(V, a, b, px, py);
+    double wbc = edge_fn(V, b, c, px, py);
+    double wca = edge_fn(V, c, a, px, py);
+    bool in = ((wab > 0.0) || (wab == 0.0 && owns_edge(V, a, b))) && ((wbc > 0.0) || (wbc == 0.0 && owns_edge(V, b, c))) &&
+              ((wca > 0.0) || (wca == 0.0 && owns_edge(V, c, a)));
+    if (!in) return false;
+    // barycentric z: each vertex weighted by the edge function of the opposite edge
+    double num = wbc * V[3 * a + 2] + wca * V[3 * b + 2];
+    num = num + wab * V[3 * c + 2];
+    double den = wbc + wca;
+    den = den + wab;
+    *z = num / den;
+    return true;
+}
+
+// one wave per triangle, lanes stride over the columns inside its xy bounding box
+__global__ void __launch_bounds__(64) k_col_pass(const double *__restrict__ V, const int32_t *__restrict__ T, int64_t nt,
+                                                 const double *__restrict__ xc, const double *__restrict__ yc, int nx,
+                                                 int ny, int32_t *cnt, const int32_t *off, int32_t *fill, double *zs,
+                                                 int64_t cap, int64_t *overflow) {
+    int64_t t = blockIdx.x;
+    if (t >= nt) return;
+    const int32_t *tri = T + 3 * t;
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (int q = 0; q < 3; ++q) {
+        double x = V[3 * tri[q]], y = V[3 * tri[q] + 1];
+        xmin = fmin(xmin, x);
+        xmax = fmax(xmax, x);
+        ymin = fmin(ymin, y);
+        ymax = fmax(ymax, y);
+    }
+    int i0 = lower_idx(xc, nx, xmin), i1 = upper_idx(xc, nx, xmax);
+    int j0 = lower_idx(yc, ny, ymin), j1 = upper_idx(yc, ny, ymax);
+    if (i1 < i0 || j1 < j0) return;
+    int64_t ni = i1 - i0 + 1, ncols = ni * (int64_t)(j1 - j0 + 1);
+    for (int64_t q = threadIdx.x; q < ncols; q += 64) {
+        int i = i0 + (int)(q % ni), j = j0 + (int)(q / ni);
+        double z;
+        if (!ray_hits(V, tri, xc[i], yc[j], &z)) continue;
+        int64_t col = (int64_t)j * nx + i;
+        if (!zs) {
+            atomicAdd(&cnt[col], 1);
+        } else {
+            int slot = atomicAdd(&fill[col], 1);
+            int64_t pos = (int64_t)off[col] + slot;
+            if (pos < cap) zs[pos] = z;
+            else atomicAdd((unsigned long long *)overflow, 1ull);
+        }
+    }
+}
+
+// per column: sort the crossings, mark cells strictly between crossing pairs as solid (1)
+__global__ void k_col_resolve(const int32_t *__restrict__ off, double *zs, const double *__restrict__ zc, int nx,
+                              int ny, int nz, uint8_t *type, int64_t *odd, int64_t cap) {
+    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= (int64_t)nx * ny) return;
+    if ((int64_t)off[(int64_t)nx * ny] > cap) return;  // overflowed: the host reports it
+    int64_t b = off[col];
+    int n = off[col + 1] - off[col];
+    double *z = zs + b;
+    for (int a = 1; a < n; ++a) {  // insertion sort (few crossings per column)
+        double v = z[a];
+        int q = a - 1;
+        while (q >= 0 && z[q] > v) {
+            z[q + 1] = z[q];
+            --q;
+        }
+        z[q + 1] = v;
+    }
+    if (n & 1) {
+        atomicAdd((unsigned long long *)odd, 1ull);
+        n -= 1;
+    }
+    const int64_t plane = (int64_t)nx * ny;
+    for (int k = 0; k < nz; ++k) {
+        double zk = zc[k];
+        uint8_t solid = 0;
+        for (int m = 0; m < n; m += 2)
+            if (zk > z[m] && zk < z[m + 1]) {
+                solid = 1;
+                break;
+            }
+        type[(int64_t)k * plane + col] = solid;
+    }
+}
+
+// ghost = solid with a fluid cell among its in-range 26 neighbours; dead = other solid.
+// Solid cells hold 1 on entry; rewriting them to 1 or 2 keeps "solid" readable.
+__global__ void k_mark_ghosts(uint8_t *type, int nx, int ny, int nz, int64_t *counters) {
+    __shared__ double sh[8];
+    int64_t N = (int64_t)nx * ny * nz;
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long cf = 0, cg = 0, cd = 0;
+    if (id < N) {
+        uint8_t t = type[id];
+        if (t == 0) {
+            cf = 1;
+        } else {
+            int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+            bool fl = false;
+            for (int dk = -1; dk <= 1 && !fl; ++dk)
+                for (int dj = -1; dj <= 1 && !fl; ++dj)
+                    for (int di = -1; di <= 1 && !fl; ++di) {
+                        int ii = i + di, jj = j + dj, kk = k + dk;
+                        if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                        if (type[((int64_t)kk * ny + jj) * nx + ii] == 0) fl = true;
+                    }
+            type[id] = fl ? T_GHOST : T_DEAD;
+            if (fl) cg = 1;
+            else cd = 1;
+        }
+    }
+    (void)sh;
+    cf = wave_sum_ll(cf);
+    cg = wave_sum_ll(cg);
+    cd = wave_sum_ll(cd);
+    if ((threadIdx.x & 63) == 0) {
+        if (cf) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)cf);
+        if (cg) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)cg);
+        if (cd) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)cd);
+    }
+}
+
+// compaction of the ghost cells in increasing linear order
+constexpr int CMP_NT = 256, CMP_PER = 16, CMP_CH = CMP_NT * CMP_PER;
+
+__global__ void __launch_bounds__(CMP_NT) k_ghost_count(const uint8_t *__restrict__ type, int64_t N, int32_t *blkc) {
+    __shared__ double sh[CMP_NT / 64];
+    int tid = threadIdx.x;
+    int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)tid * CMP_PER;
+    int c = 0;
+    for (int q = 0; q < CMP_PER; ++q) {
+        int64_t id = base + q;
+        if (id < N && type[id] == T_GHOST) ++c;
+    }
+    double s = block_sum<CMP_NT>((double)c, sh, tid);
+    if (tid == 0) blkc[blockIdx.x] = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(CMP_NT) k_ghost_write(const uint8_t *__restrict__ type, int64_t N,
+                                                        const int32_t *blkoff, int32_t *gcell, int64_t gmax) {
+    __shared__ int sh[CMP_NT];
+    int tid = threadIdx.x;
+    int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)tid * CMP_PER;
+    int c = 0;
+    for (int q = 0; q < CMP_PER; ++q) {
+        int64_t id = base + q;
+        if (id < N && type[id] == T_GHOST) ++c;
+    }
+    sh[tid] = c;
+    __syncthreads();
+    for (int o = 1; o < CMP_NT; o <<= 1) {
+        int v = (tid >= o) ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += v;
+        __syncthreads();
+    }
+    int64_t pos = (int64_t)blkoff[blockIdx.x] + sh[tid] - c;
+    for (int q = 0; q < CMP_PER; ++q) {
+        int64_t id = base + q;
+        if (id < N && type[id] == T_GHOST) {
+            if (pos < gmax) gcell[pos] = (int32_t)id;
+            ++pos;
+        }
+    }
+}
+
+hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const int64_t ncol = (int64_t)nx * ny, N = g->N;
+    hipError_t e;
+    e = hipMemsetAsync(g->counters, 0, sizeof(int64_t) * 8, s);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(g->col_cnt, 0, sizeof(int32_t) * (ncol + 1), s);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(g->col_fill, 0, sizeof(int32_t) * (ncol + 1), s);
+    if (e != hipSuccess) return e;
+    if (g->nt > 0) {
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)g->nt), dim3(64), 0, s, g->verts, g->tris, g->nt, g->c0[0],
+                           g->c0[1], nx, ny, g->col_cnt, nullptr, nullptr, nullptr, (int64_t)0, nullptr);
+    }
+    e = scan_counts(g->col_cnt, g->col_off, ncol + 1, (int64_t *)g->blk_cnt, s);
+    if (e != hipSuccess) return e;
+    if (g->nt > 0) {
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)g->nt), dim3(64), 0, s, g->verts, g->tris, g->nt, g->c0[0],
+                           g->c0[1], nx, ny, nullptr, g->col_off, g->col_fill, g->crossings, g->cross_cap,
+                           g->counters + 4);
+    }
+    hipLaunchKernelGGL(k_col_resolve, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
+                       g->c0[2], nx, ny, nz, g->type, g->counters + 3, g->cross_cap);
+    hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g->type, nx, ny, nz,
+                       g->counters);
+    int64_t nb = (N + CMP_CH - 1) / CMP_CH;
+    int32_t *blkc = g->col_cnt;  // reuse: ncol+1 >= nb is guaranteed by the layout
+    int32_t *blko = g->col_fill;
+    hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blkc);
+    e = scan_counts(blkc, blko, nb, (int64_t *)g->blk_cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ghost_write, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blko, g->g_cell,
+                       g->ghost_max);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t hc[8];
+    e = hipMemcpyAsync(hc, g->counters, sizeof(hc), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    counts[0] = hc[0];
+    counts[1] = hc[1];
+    counts[2] = hc[2];
+    counts[3] = hc[3] + (hc[4] ? (int64_t)1 << 40 : 0);  // odd columns; overflow flagged high
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------
+// body intercept: closest point of the mesh (Ericson, Real-Time Collision Detection, 2005,
+// section 5.1.5: Voronoi-region test per triangle), argmin with lowest triangle index
+// ---------------------------------------------------------------------------------------
+
+__device__ void closest_on_triangle(const double p[3], const double a[3], const double b[3], const double c[3],
+                                    double q[3]) {
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    for (int d = 0; d < 3; ++d) {
+        ab[d] = b[d] - a[d];
+        ac[d] = c[d] - a[d];
+        ap[d] = p[d] - a[d];
+    }
+    double d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+    double d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        for (int d = 0; d < 3; ++d) q[d] = a[d];
+        return;
+    }
+    for (int d = 0; d < 3; ++d) bp[d] = p[d] - b[d];
+    double d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
+    double d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
+    if (d3 >= 0.0 && d4 <= d3) {
+        for (int d = 0; d < 3; ++d) q[d] = b[d];
+        return;
+    }
+    double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        double v = d1 / (d1 - d3);
+        for (int d = 0; d < 3; ++d) q[d] = a[d] + v * ab[d];
+        return;
+    }
+    for (int d = 0; d < 3; ++d) cp[d] = p[d] - c[d];
+    double d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
+    double d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
+    if (d6 >= 0.0 && d5 <= d6) {
+        for (int d = 0; d < 3; ++d) q[d] = c[d];
+        return;
+    }
+    double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        double w = d2 / (d2 - d6);
+        for (int d = 0; d < 3; ++d) q[d] = a[d] + w * ac[d];
+        return;
+    }
+    double va = d3 * d6 - d5 * d4;
+    if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+        double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        for (int d = 0; d < 3; ++d) q[d] = b[d] + w * (c[d] - b[d]);
+        return;
+    }
+    double denom = 1.0 / ((va + vb) + vc);
+    double v = vb * denom, w = vc * denom;
+    for (int d = 0; d < 3; ++d) q[d] = (a[d] + ab[d] * v) + ac[d] * w;
+}
+
+__device__ __forceinline__ void consider_tri(const double *V, const int32_t *T, int32_t t, const double x[3],
+                                             double &best, int32_t &bt, double bq[3]) {
+    const int32_t *tri = T + 3 * (int64_t)t;
+    double a[3], b[3], c[3], q[3];
+    for (int d = 0; d < 3; ++d) {
+        a[d] = V[3 * tri[0] + d];
+        b[d] = V[3 * tri[1] + d];
+        c[d] = V[3 * tri[2] + d];
+    }
+    closest_on_triangle(x, a, b, c, q);
+    double dx = q[0] - x[0], dy = q[1] - x[1], dz = q[2] - x[2];
+    double d2 = dx * dx + dy * dy + dz * dz;
+    if (d2 < best || (d2 == best && t < bt)) {
+        best = d2;
+        bt = t;
+        bq[0] = q[0];
+        bq[1] = q[1];
+        bq[2] = q[2];
+    }
+}
+
+__global__ void k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, int nz,
+                          const double *__restrict__ xc, const double *__restrict__ yc, const double *__restrict__ zc,
+                          const double *__restrict__ V, const int32_t *__restrict__ T, int64_t nt,
+                          const int32_t *__restrict__ boff, const int32_t *__restrict__ bent, BucketGrid G, double *gbi,
+                          int32_t *gtri) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    int64_t id = gcell[g];
+    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    double x[3] = {xc[i], yc[j], zc[k]};
+    const bool two_d = (nz == 1);
+    // the surface crosses the segment to any fluid neighbour: search within the largest
+    // centre distance to the 26 neighbours
+    double rx = fmax(i > 0 ? x[0] - xc[i - 1] : 0.0, i < nx - 1 ? xc[i + 1] - x[0] : 0.0);
+    double ry = fmax(j > 0 ? x[1] - yc[j - 1] : 0.0, j < ny - 1 ? yc[j + 1] - x[1] : 0.0);
+    double rz = fmax(k > 0 ? x[2] - zc[k - 1] : 0.0, k < nz - 1 ? zc[k + 1] - x[2] : 0.0);
+    if (two_d) rz = 0.0;
+    double r = sqrt(rx * rx + ry * ry + rz * rz);
+    double best = INFINITY, bq[3] = {0.0, 0.0, 0.0};
+    int32_t bt = 0x7fffffff;
+    int b0[3], b1[3];
+    for (int d = 0; d < 3; ++d) {
+        b0[d] = bucket_coord(x[d] - r, G.bmin[d], G.bsize[d], G.nb[d]);
+        b1[d] = bucket_coord(x[d] + r, G.bmin[d], G.bsize[d], G.nb[d]);
+    }
+    for (int bz = b0[2]; bz <= b1[2]; ++bz)
+        for (int by = b0[1]; by <= b1[1]; ++by)
+            for (int bx = b0[0]; bx <= b1[0]; ++bx) {
+                int b = (bz * G.nb[1] + by) * G.nb[0] + bx;
+                for (int q = boff[b]; q < boff[b + 1]; ++q) {
+                    int32_t t = bent[q];
+                    double lo[3], hi[3];
+                    tri_bbox(V, T, t, lo, hi);
+                    bool far = false;
+                    for (int d = 0; d < 3; ++d)
+                        if (lo[d] > x[d] + r || hi[d] < x[d] - r) far = true;
+                    if (far) continue;
+                    consider_tri(V, T, t, x, best, bt, bq);
+                }
+            }
+    if (bt == 0x7fffffff || !(best <= r * r)) {
+        // nothing within the radius: search every triangle
+        best = INFINITY;
+        bt = 0x7fffffff;
+        for (int64_t t = 0; t < nt; ++t) consider_tri(V, T, (int32_t)t, x, best, bt, bq);
+    }
+    if (two_d) bq[2] = x[2];  // prism bodies of a one-cell-thick grid: stay in the cell plane
+    gbi[3 * g] = bq[0];
+    gbi[3 * g + 1] = bq[1];
+    gbi[3 * g + 2] = bq[2];
+    gtri[g] = bt;
+}
+
+// ---------------------------------------------------------------------------------------
+// image point, interpolation box and weights (Eq. 2 and Eq. 3)
+//
+// The weights beta solve V^T beta = b(x_IP) for the trilinear basis b of the box; when the
+// ghost is itself a member its row of V is the normal derivative of the basis at the body
+// intercept.  Here the solution is written in closed form through the trilinear Lagrange
+// basis L_m of the box (dual-basis form, no per-ghost factorisation):
+//     no Neumann row:  beta_m = L_m(IP)
+//     ghost g in box:  beta_g = L_g(IP) / dL_g/dn(BI)
+//                      beta_m = L_m(IP) - dL_m/dn(BI) * beta_g      (m != g)
+// dL_g/dn(BI) < 0 strictly for a mirror image point, so the form is always defined.
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, int nz,
+                          const double *__restrict__ xc, const double *__restrict__ yc, const double *__restrict__ zc,
+                          const double *__restrict__ wx, const double *__restrict__ wy, const double *__restrict__ wz,
+                          const uint8_t *__restrict__ type, const double *__restrict__ V, const int32_t *__restrict__ T,
+                          const double *__restrict__ gbi, const int32_t *__restrict__ gtri, double *gn, double *gip,
+                          double *gdl, int32_t *gst, uint8_t *gmask, double *gbeta, double *gbetag, int32_t *gflags,
+                          int64_t *ndegen) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    int64_t id = gcell[g];
+    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    const bool two_d = (nz == 1);
+    double xg[3] = {xc[i], yc[j], zc[k]};
+    double bi[3] = {gbi[3 * g], gbi[3 * g + 1], gbi[3 * g + 2]};
+    double dv[3] = {bi[0] - xg[0], bi[1] - xg[1], bi[2] - xg[2]};
+    double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    double hloc = fmin(wx[i], wy[j]);
+    if (!two_d) hloc = fmin(hloc, wz[k]);
+    int flags = 0;
+    double n[3];
+    if (dist <= 1e-12 * hloc) {
+        const int32_t *tri = T + 3 * (int64_t)gtri[g];
+        double u[3], v[3];
+        for (int d = 0; d < 3; ++d) {
+            u[d] = V[3 * tri[1] + d] - V[3 * tri[0] + d];
+            v[d] = V[3 * tri[2] + d] - V[3 * tri[0] + d];
+        }
+        double nn[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        if (two_d) nn[2] = 0.0;
+        double ln = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        for (int d = 0; d < 3; ++d) n[d] = nn[d] / ln;
+        flags |= GF_NFALLBACK;
+    } else {
+        for (int d = 0; d < 3; ++d) n[d] = dv[d] / dist;
+    }
+    double ip[3];
+    for (int d = 0; d < 3; ++d) ip[d] = (bi[d] + bi[d]) - xg[d];
+    double dl = dist + dist;
+    for (int d = 0; d < 3; ++d) {
+        gn[3 * g + d] = n[d];
+        gip[3 * g + d] = ip[d];
+    }
+    gdl[g] = dl;
+    int i0 = box_lo(xc, nx, ip[0]);
+    int j0 = box_lo(yc, ny, ip[1]);
+    int k0 = two_d ? 0 : box_lo(zc, nz, ip[2]);
+    double hx = xc[i0 + 1] - xc[i0], hy = yc[j0 + 1] - yc[j0];
+    double hz = two_d ? 1.0 : zc[k0 + 1] - zc[k0];
+    double s[3], bl[3];
+    s[0] = (ip[0] - xc[i0]) / hx;
+    s[1] = (ip[1] - yc[j0]) / hy;
+    s[2] = two_d ? 0.0 : (ip[2] - zc[k0]) / hz;
+    for (int d = 0; d < 3; ++d) {
+        if (s[d] < 0.0) {
+            s[d] = 0.0;
+            flags |= GF_CLAMPED;
+        } else if (s[d] > 1.0) {
+            s[d] = 1.0;
+            flags |= GF_CLAMPED;
+        }
+    }
+    bl[0] = (bi[0] - xc[i0]) / hx;
+    bl[1] = (bi[1] - yc[j0]) / hy;
+    bl[2] = two_d ? 0.0 : (bi[2] - zc[k0]) / hz;
+    const double hs[3] = {hx, hy, hz};
+    const int nm = two_d ? 4 : 8;
+    int32_t mem[8];
+    int nfl = 0, ndead = 0, self = -1;
+    uint8_t gm = 0;
+    for (int m = 0; m < nm; ++m) {
+        int a = m & 1, b = (m >> 1) & 1, c = (m >> 2) & 1;
+        int64_t mid = ((int64_t)(k0 + c) * ny + (j0 + b)) * nx + (i0 + a);
+        mem[m] = (int32_t)mid;
+        uint8_t ty = type[mid];
+        if (ty == T_FLUID) ++nfl;
+        if (ty == T_DEAD) ++ndead;
+        if (mid == id) self = m;
+        else if (ty == T_GHOST) gm |= (uint8_t)(1u << m);
+    }
+    double beta[8];
+    int32_t st[8];
+    for (int m = 0; m < 8; ++m) {
+        beta[m] = 0.0;
+        st[m] = -1;
+    }
+    double bg = 0.0;
+    bool degenerate = (ndead > 0 || nfl == 0);
+    if (!degenerate) {
+        // Lagrange basis at the image point and its normal derivative at the intercept
+        double L[8], dLn[8];
+        for (int m = 0; m < nm; ++m) {
+            int bits[3] = {m & 1, (m >> 1) & 1, (m >> 2) & 1};
+            double fi[3], fb[3];
+            for (int d = 0; d < 3; ++d) {
+                fi[d] = bits[d] ? s[d] : 1.0 - s[d];
+                fb[d] = bits[d] ? bl[d] : 1.0 - bl[d];
+            }
+            if (two_d) {
+                L[m] = fi[0] * fi[1];
+                dLn[m] = n[0] * ((bits[0] ? 1.0 : -1.0) / hs[0]) * fb[1] + n[1] * ((bits[1] ? 1.0 : -1.0) / hs[1]) * fb[0];
+            } else {
+                L[m] = fi[0] * fi[1] * fi[2];
+                dLn[m] = n[0] * ((bits[0] ? 1.0 : -1.0) / hs[0]) * (fb[1] * fb[2]) +
+                         n[1] * ((bits[1] ? 1.0 : -1.0) / hs[1]) * (fb[0] * fb[2]) +
+                         n[2] * ((bits[2] ? 1.0 : -1.0) / hs[2]) * (fb[0] * fb[1]);
+            }
+        }
+        if (self < 0) {
+            for (int m = 0; m < nm; ++m) {
+                beta[m] = L[m];
+                st[m] = mem[m];
+            }
+        } else if (dLn[self] < 0.0) {
+            bg = L[self] / dLn[self];
+            for (int m = 0; m < nm; ++m) {
+                if (m == self) {
+                    beta[m] = bg;
+                    st[m] = -1;
+                } else {
+                    beta[m] = L[m] - dLn[m] * bg;
+                    st[m] = mem[m];
+                }
+            }
+            flags |= GF_SELF;
+        } else {
+            degenerate = true;
+        }
+    }
+    if (degenerate) {
+        flags |= GF_DEGENERATE;
+        gm = 0;
+        bg = 0.0;
+        for (int m = 0; m < 8; ++m) {
+            beta[m] = 0.0;
+            st[m] = -1;
+        }
+        atomicAdd((unsigned long long *)ndegen, 1ull);
+    }
+    for (int m = 0; m < 8; ++m) {
+        gst[8 * g + m] = st[m];
+        gbeta[8 * g + m] = beta[m];
+    }
+    gmask[g] = gm;
+    gbetag[g] = bg;
+    gflags[g] = flags;
+}
+
+__global__ void k_ghost_h(int64_t ng, const double *betag, const double *dl, const double *data, double *h) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    // ghost equation: p_g - sum_{m != g} beta_m p_m = (beta_g - dl) * dp/dn(BI)
+    h[g] = (betag[g] - dl[g]) * data[g];
+}
+
+hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
+    if (g->ng == 0) return hipSuccess;
+    BucketGrid G;
+    for (int d = 0; d < 3; ++d) {
+        G.bmin[d] = g->bmin[d];
+        G.bsize[d] = g->bsize[d];
+        G.nb[d] = g->nb[d];
+    }
+    unsigned nb = (unsigned)((g->ng + 127) / 128);
+    hipLaunchKernelGGL(k_closest, dim3(nb), dim3(128), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
+                       g->c0[2], g->verts, g->tris, g->nt, g->bucket_off, g->bucket_ent, G, g->g_bi, g->g_tri);
+    hipLaunchKernelGGL(k_weights, dim3(nb), dim3(128), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
+                       g->c0[2], g->w0[0], g->w0[1], g->w0[2], g->type, g->verts, g->tris, g->g_bi, g->g_tri, g->g_n,
+                       g->g_ip, g->g_dl, g->g_st, g->g_mask, g->g_beta, g->g_betag, g->g_flags, g->counters + 5);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_h(ibm_grid *g, hipStream_t s) {
+    if (g->ng == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_h, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, g->ng, g->g_betag, g->g_dl,
+                       g->g_data, g->g_h);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// multigrid hierarchy: active masks, staircase transmissibilities, prolongation tables
+// ---------------------------------------------------------------------------------------
+
+struct LevelDims {
+    int n[3];
+    int h[3];  // halved relative to the finer level
+};
+
+// active(C) = any active child; fine level 0 active = fluid
+__global__ void k_coarsen_active(LevelDims F, LevelDims C, const uint8_t *__restrict__ fine_active, bool fine_is_type,
+                                 uint8_t *coarse_active, const double *__restrict__ cw0, const double *__restrict__ cw1,
+                                 const double *__restrict__ cw2, double *partials) {
+    __shared__ double sh[4];
+    int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double vol = 0.0;
+    if (id < NC) {
+        int I = (int)(id % C.n[0]), J = (int)((id / C.n[0]) % C.n[1]), K = (int)(id / ((int64_t)C.n[0] * C.n[1]));
+        int i0 = C.h[0] ? 2 * I : I, i1 = C.h[0] ? 2 * I + 1 : I;
+        int j0 = C.h[1] ? 2 * J : J, j1 = C.h[1] ? 2 * J + 1 : J;
+        int k0 = C.h[2] ? 2 * K : K, k1 = C.h[2] ? 2 * K + 1 : K;
+        uint8_t act = 0;
+        for (int k = k0; k <= k1; ++k)
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) {
+                    uint8_t v = fine_active[((int64_t)k * F.n[1] + j) * F.n[0] + i];
+                    act |= fine_is_type ? (uint8_t)(v == T_FLUID) : v;
+                }
+        coarse_active[id] = act;
+        if (act) vol = (cw0[I] * cw1[J]) * cw2[K];
+    }
+    double s = block_sum<256>(vol, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// level-0 active volume
+__global__ void k_fluid_volume(const uint8_t *__restrict__ type, int nx, int ny, int nz, const double *__restrict__ wx,
+                               const double *__restrict__ wy, const double *__restrict__ wz, double *partials) {
+    __shared__ double sh[4];
+    int64_t N = (int64_t)nx * ny * nz;
+    double vol = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (int64_t)gridDim.x * blockDim.x) {
+        if (type[id] == T_FLUID) {
+            int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+            vol += (wx[i] * wy[j]) * wz[k];
+        }
+    }
+    double s = block_sum<256>(vol, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_sum_partials(const double *partials, int n, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < n; ++q) s += partials[q];
+        *out = s;
+    }
+}
+
+// open child-face area over the coarse centre distance, for each cell's low face along d
+__global__ void k_face_T(LevelDims F, LevelDims C, int d, const uint8_t *__restrict__ fine_active, bool fine_is_type,
+                         const double *__restrict__ fw0, const double *__restrict__ fw1, const double *__restrict__ fw2,
+                         const double *__restrict__ cc, double *T64, float *T32) {
+    int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= NC) return;
+    int Ic[3] = {(int)(id % C.n[0]), (int)((id / C.n[0]) % C.n[1]), (int)(id / ((int64_t)C.n[0] * C.n[1]))};
+    if (Ic[d] == 0) {
+        T64[id] = 0.0;
+        T32[id] = 0.0f;
+        return;
+    }
+    const double *fw[3] = {fw0, fw1, fw2};
+    int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+    int fface = C.h[d] ? 2 * Ic[d] : Ic[d];
+    int a0 = C.h[e1] ? 2 * Ic[e1] : Ic[e1], a1 = C.h[e1] ? 2 * Ic[e1] + 1 : Ic[e1];
+    int b0 = C.h[e2] ? 2 * Ic[e2] : Ic[e2], b1 = C.h[e2] ? 2 * Ic[e2] + 1 : Ic[e2];
+    double area = 0.0;
+    for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) {
+            int lo[3], hi[3];
+            lo[d] = fface - 1;
+            hi[d] = fface;
+            lo[e1] = hi[e1] = a;
+            lo[e2] = hi[e2] = b;
+            uint8_t va = fine_active[((int64_t)lo[2] * F.n[1] + lo[1]) * F.n[0] + lo[0]];
+            uint8_t vb = fine_active[((int64_t)hi[2] * F.n[1] + hi[1]) * F.n[0] + hi[0]];
+            bool oa = fine_is_type ? (va == T_FLUID) : (va != 0);
+            bool ob = fine_is_type ? (vb == T_FLUID) : (vb != 0);
+            if (oa && ob) area += fw[e1][a] * fw[e2][b];
+        }
+    double dist = cc[Ic[d]] - cc[Ic[d] - 1];
+    double t = area / dist;
+    T64[id] = t;
+    T32[id] = (float)t;
+}
+
+// prolongation table of a fine axis: value(i) = (1-t) e[lo] + t e[hi], physical coordinates,
+// clamped at the walls; axes not halved map to themselves
+__global__ void k_prolong_tab(int nf, int nc, int halved, const double *__restrict__ fc, const double *__restrict__ cc,
+                              int *lo, int *hi, double *t) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    if (!halved) {
+        lo[i] = i;
+        hi[i] = i;
+        t[i] = 0.0;
+        return;
+    }
+    int I = i / 2;
+    double x = fc[i], X = cc[I];
+    int Jn = (x < X) ? I - 1 : I + 1;
+    if (Jn < 0 || Jn >= nc) {
+        lo[i] = I;
+        hi[i] = I;
+        t[i] = 0.0;
+        return;
+    }
+    lo[i] = I;
+    hi[i] = Jn;
+    t[i] = (x - X) / (cc[Jn] - X);
+}
+
+hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
+    // level-0 fluid volume
+    hipLaunchKernelGGL(k_fluid_volume, dim3(RED_BLOCKS), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, g->w0[0],
+                       g->w0[1], g->w0[2], g->partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, g->partials, RED_BLOCKS, &g->sc->vol[0]);
+    for (int l = 1; l < g->nlev; ++l) {
+        LevelHost &Fh = g->lev[l - 1], &Ch = g->lev[l];
+        LevelDims F, C;
+        for (int d = 0; d < 3; ++d) {
+            F.n[d] = Fh.n[d];
+            F.h[d] = Fh.halved[d];
+            C.n[d] = Ch.n[d];
+            C.h[d] = Ch.halved[d];
+        }
+        const bool fine_type = (l == 1);
+        const uint8_t *fa = fine_type ? g->type : Fh.active;
+        int64_t NC = Ch.ncell();
+        unsigned nb = (unsigned)((NC + 255) / 256);
+        // the partial sums of this kernel can exceed RED_BLOCKS: sum them directly
+        double *parts = (double *)g->crossings;  // geometry scratch is free after classification
+        hipLaunchKernelGGL(k_coarsen_active, dim3(nb), dim3(256), 0, s, F, C, fa, fine_type, Ch.active, Ch.w64[0],
+                           Ch.w64[1], Ch.w64[2], parts);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, parts, (int)nb, &g->sc->vol[l]);
+        const double *fw0 = (l == 1) ? g->w0[0] : Fh.w64[0];
+        const double *fw1 = (l == 1) ? g->w0[1] : Fh.w64[1];
+        const double *fw2 = (l == 1) ? g->w0[2] : Fh.w64[2];
+        for (int d = 0; d < 3; ++d) {
+            hipLaunchKernelGGL(k_face_T, dim3(nb), dim3(256), 0, s, F, C, d, fa, fine_type, fw0, fw1, fw2, Ch.c64[d],
+                               Ch.T64[d], Ch.T32[d]);
+            const double *fc = (l == 1) ? g->c0[d] : Fh.c64[d];
+            hipLaunchKernelGGL(k_prolong_tab, dim3((Fh.n[d] + 127) / 128), dim3(128), 0, s, Fh.n[d], Ch.n[d],
+                               Ch.halved[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ibm

@@ -1,0 +1,247 @@
+// Internal declarations of the gfx950 ghost-cell IBM projection library.
+//
+// Data layout in HBM (all inside the caller-owned workspace):
+//   level 0 : cell type (uint8), second pressure buffer (FP64), FP32 error / residual
+//             buffers for the mixed-precision path; cell fields are [nz][ny][nx].
+//   metrics : 1D per-axis arrays (centres, widths, centre distances, flux coefficients),
+//             so the 7-point operator of a cell is rebuilt from six scalar loads.
+//   geometry: mesh, a uniform triangle bucket grid (closest-point search), per-column ray
+//             crossings (classification), and the ghost list in structure-of-arrays form.
+//   levels  : per coarse level the error and right-hand side, the active mask and the
+//             staircase transmissibilities of each cell's three low faces, plus the
+//             per-axis prolongation tables.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ibm.h"
+
+namespace ibm {
+
+constexpr uint8_t T_FLUID = 0, T_GHOST = 1, T_DEAD = 2;
+constexpr int GF_DEGENERATE = 1, GF_CLAMPED = 2, GF_NFALLBACK = 4, GF_SELF = 8;
+constexpr int MAX_LEVELS = 24;
+constexpr int RED_BLOCKS = 1024;  // fixed block count of the deterministic reductions
+constexpr int NBUCKET_MAX = 1 << 20;
+
+// ---------------------------------------------------------------------------------------
+// device views
+// ---------------------------------------------------------------------------------------
+
+template <typename T>
+struct AxisCoef {  // per-axis arrays of one level
+    const T *am, *ap;  // level 0: per-volume flux coefficients; unused on coarse levels
+    const T *w;        // widths
+};
+
+template <typename T>
+struct Fine {  // level-0 operator view in precision T
+    int nx, ny, nz;
+    const T *axm, *axp, *aym, *ayp, *azm, *azp;
+    const T *wx, *wy, *wz;
+    const uint8_t *type;
+};
+
+template <typename T>
+struct Coarse {  // coarse-level view in precision T
+    int n[3];
+    const T *w[3];        // widths
+    const uint8_t *active;
+    const T *Tl[3];       // transmissibility of each cell's low face (integrated form)
+    T *e, *R;
+    const double *mu;     // compatibility shift per unit volume (device scalar)
+};
+
+struct ProlongTab {  // fine index -> (lo, hi, weight of hi) per axis
+    const int *lo[3], *hi[3];
+    const double *t[3];
+    int halved[3];
+};
+
+struct GhostView {
+    int64_t ng;
+    const int32_t *cell;
+    const int32_t *st;      // 8 per ghost, -1 = unused / own Neumann slot
+    const uint8_t *gmask;   // bit m: member m is a ghost cell
+    const double *beta;     // 8 per ghost
+    const double *h;        // right-hand side of the ghost equation
+    const int32_t *flags;
+};
+
+// reduction scratch shared by the solver kernels (device)
+struct Scalars {
+    double lambda;      // current uniform source shift
+    double delta;       // lambda_{k+1} - lambda_k (mixed path: FP64)
+    float delta32;      // same, FP32 (inner right-hand side shift)
+    float pad0;
+    double norm;        // ||r - lambda||_2 after the last norm pass
+    double rel;         // norm / ref
+    double ref;         // reference norm ||f - Vmean(f)||
+    double vmean;       // scratch mean
+    double div_max;
+    int bad;            // non-finite seen
+    int pad1;
+    double mu[MAX_LEVELS];
+    double vol[MAX_LEVELS];   // summed volume of the active cells of each level
+};
+
+// ---------------------------------------------------------------------------------------
+// host-side state
+// ---------------------------------------------------------------------------------------
+
+struct LevelHost {
+    int n[3];
+    int halved[3];
+    std::vector<double> f[3], c[3], w[3];
+    int64_t ncell() const { return (int64_t)n[0] * n[1] * n[2]; }
+    // device
+    uint8_t *active = nullptr;
+    double *T64[3] = {nullptr, nullptr, nullptr};
+    float *T32[3] = {nullptr, nullptr, nullptr};
+    double *w64[3] = {nullptr, nullptr, nullptr};
+    float *w32[3] = {nullptr, nullptr, nullptr};
+    double *c64[3] = {nullptr, nullptr, nullptr};
+    double *e64 = nullptr, *R64 = nullptr;
+    float *e32 = nullptr, *R32 = nullptr;
+    // prolongation tables of THIS level from the next coarser one
+    int *plo[3] = {nullptr, nullptr, nullptr}, *phi[3] = {nullptr, nullptr, nullptr};
+    double *pt[3] = {nullptr, nullptr, nullptr};
+    double vol_active = 0.0;  // device-computed, copied back at hierarchy build
+};
+
+enum Stage { ST_CREATED = 0, ST_BOUND = 1, ST_GEOMETRY = 2, ST_CLASSIFIED = 3, ST_STENCILS = 4 };
+
+struct SolveState {  // in-flight solve of the step API
+    bool active = false, done = true;
+    const double *rhs = nullptr;
+    double *p_user = nullptr;
+    ibm_solve_opts o{};
+    hipStream_t stream = nullptr;
+    int cycles = 0, status = 0;
+    int pending = 0;            // cycles enqueued since the last poll read
+    double r0 = 0.0;
+    hipEvent_t ev = nullptr;
+    bool ev_pending = false;
+    int cur = 0;                // which buffer holds the iterate (0 = user p, 1 = workspace)
+    bool finishing = false;     // gauge enqueued, waiting for its event
+    double t0 = 0.0;
+};
+
+// optional per-launch timing of the level-0 smoother (HIP events on the launch stream)
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    std::vector<int> kind;       // per pair: 0 FP64 sweep, 1 FP32 sweep
+    int used = 0;
+    double ms[2] = {0.0, 0.0};
+    long long count[2] = {0, 0};
+};
+
+}  // namespace ibm
+
+struct ibm_grid {
+    int nx, ny, nz;
+    int64_t N;
+    std::vector<double> xf, yf, zf;
+    int stage = ibm::ST_CREATED;
+    std::string err;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t nv_max = 0, nt_max = 0, ghost_max = 0;
+    ibm_precision prec = IBM_FP64;
+    int device = 0;
+    // level-0 device arrays
+    uint8_t *type = nullptr;
+    double *p2 = nullptr;                  // second FP64 pressure buffer
+    double *frhs = nullptr;                // projection right-hand side
+    float *e32a = nullptr, *e32b = nullptr, *r32 = nullptr;
+    double *faces[3] = {nullptr, nullptr, nullptr};
+    double *c0[3] = {nullptr, nullptr, nullptr}, *w0[3] = {nullptr, nullptr, nullptr};
+    double *dc0[3] = {nullptr, nullptr, nullptr};
+    double *am0[3] = {nullptr, nullptr, nullptr}, *ap0[3] = {nullptr, nullptr, nullptr};
+    float *am0f[3] = {nullptr, nullptr, nullptr}, *ap0f[3] = {nullptr, nullptr, nullptr};
+    float *w0f[3] = {nullptr, nullptr, nullptr};
+    // mesh and geometry scratch
+    int64_t nv = 0, nt = 0;
+    double *verts = nullptr;
+    int32_t *tris = nullptr;
+    int32_t *bucket_off = nullptr, *bucket_cnt = nullptr, *bucket_ent = nullptr;
+    int nb[3] = {1, 1, 1};
+    double bmin[3] = {0, 0, 0}, bsize[3] = {1, 1, 1};
+    int32_t *col_cnt = nullptr, *col_off = nullptr, *col_fill = nullptr;
+    double *crossings = nullptr;
+    int64_t cross_cap = 0;
+    int32_t *blk_cnt = nullptr;            // per-block counts for compaction / scans
+    int64_t *counters = nullptr;           // device counters (fluid, ghost, dead, odd, overflow...)
+    // ghosts
+    int64_t ng = 0;
+    int64_t ndegenerate = 0;
+    int32_t *g_cell = nullptr, *g_st = nullptr, *g_flags = nullptr, *g_tri = nullptr;
+    uint8_t *g_mask = nullptr;
+    double *g_bi = nullptr, *g_n = nullptr, *g_ip = nullptr, *g_beta = nullptr, *g_betag = nullptr;
+    double *g_dl = nullptr, *g_h = nullptr, *g_data = nullptr;
+    // multigrid
+    int nlev = 0;
+    ibm::LevelHost lev[ibm::MAX_LEVELS];
+    double *partials = nullptr;            // RED_BLOCKS * 4 doubles
+    ibm::Scalars *sc = nullptr;            // device scalars
+    ibm::Scalars *sc_host = nullptr;       // pinned host mirror
+    int64_t nfluid = 0, nghost_cells = 0, ndead = 0;
+    double vol_fluid = 0.0;
+    ibm::SolveState ss;
+    ibm::Prof prof;
+};
+
+namespace ibm {
+
+// workspace planner: computes offsets (base == nullptr -> sizing only)
+struct Plan {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+        return p;
+    }
+};
+
+// hierarchy plan on the host (dims + coarse faces), same rule for sizing and binding
+void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                 LevelHost *lev, int *nlev);
+size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t gmax,
+              ibm_precision prec, LevelHost *lev, int nlev);
+
+// kernel launchers (geometry.hip)
+hipError_t launch_metrics(ibm_grid *g, hipStream_t s);
+hipError_t launch_buckets(ibm_grid *g, hipStream_t s);
+hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]);
+hipError_t launch_stencils(ibm_grid *g, hipStream_t s);
+hipError_t launch_ghost_h(ibm_grid *g, hipStream_t s);
+hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s);
+
+// solver launchers (solver.hip)
+hipError_t sweep0_f64(ibm_grid *g, const double *pin, double *pout, const double *f, const double *lambda,
+                      hipStream_t s);
+hipError_t refresh_f64(ibm_grid *g, const double *src_ghost, double *dst, hipStream_t s);
+hipError_t apply0_f64(ibm_grid *g, const double *p, double *out, hipStream_t s);
+hipError_t vcycle_f64(ibm_grid *g, double **bufs, int *cur, const double *f, hipStream_t s, const ibm_solve_opts *o);
+hipError_t vcycle_mixed(ibm_grid *g, double **bufs, int *cur, const double *f, hipStream_t s,
+                        const ibm_solve_opts *o);
+hipError_t norm_pass(ibm_grid *g, const double *p, const double *f, hipStream_t s, bool write_r32, bool first);
+hipError_t ref_norm_pass(ibm_grid *g, const double *f, hipStream_t s);
+hipError_t gauge_pass(ibm_grid *g, const double *pcur, double *pdst, hipStream_t s);
+hipError_t rhs_pass(ibm_grid *g, const double *u, const double *v, const double *w, double dt, double *f,
+                    hipStream_t s);
+hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt,
+                        hipStream_t s);
+hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s);
+hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipStream_t s);
+
+}  // namespace ibm

@@ -1,0 +1,968 @@
+// Pressure Poisson solve (paper Section 2.1: pressure equation of the fractional step,
+// solved iteratively; multigrid and red-black Gauss-Seidel are among the solvers the paper
+// evaluated) and the projection passes: divergence right-hand side, velocity correction,
+// gauge.  Ghost equations (Section 2.2, Eq. 2) are refreshed after every fine-level sweep.
+//
+// Fine level (level 0) work is out of place between two pressure buffers; every pass reads
+// one buffer and writes the other, so no pass ever reads a value another thread of the same
+// pass writes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_util.hpp"
+#include "ibm_impl.hpp"
+
+namespace ibm {
+
+// =======================================================================================
+// fused red-black Gauss-Seidel sweep on level 0
+//
+// One sweep updates every red fluid cell ((i+j+k) even) from the old values, then every
+// black fluid cell from the new red values:
+//     p_c = (sum_f a_f p_nb - (f_c - lambda)) / sum_f a_f
+// Here both colours are done in one pass: each workgroup owns a tile of TX x TY columns
+// and a chunk of z-planes and marches upward; at step k it forms the red values of plane
+// k+1 (from old planes k, k+1, k+2) and then the black values of plane k (from the red
+// values of planes k-1, k, k+1).  In-plane neighbours come from LDS; a ring of one column
+// around the tile recomputes red values redundantly, a second ring only loads old values.
+// Each cell's new value is computed with the same operations in the same order as the
+// two-pass definition, so the result is bitwise identical to it.
+// Traffic per cell: read p, f, type; write p (25 B in FP64, 13 B in FP32).
+// =======================================================================================
+
+template <typename T, int BX, int BY>
+__global__ void __launch_bounds__(BX *BY)
+    k_rbgs_fused(Fine<T> F, const T *__restrict__ pin, T *__restrict__ pout, const T *__restrict__ f,
+                 const T *__restrict__ lamp, int ntx, int nty, int kc, int ntiles) {
+    constexpr int TX = BX - 4, TY = BY - 4;
+    __shared__ T oldp[2][BY][BX + 1];
+    __shared__ T redp[BY][BX + 1];
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs; give every
+    // XCD a contiguous range of tiles so neighbouring tiles share one L2
+    const int per = gridDim.x >> 3;
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (logical >= ntiles) return;
+    int tile = logical;
+    const int txi = tile % ntx;
+    tile /= ntx;
+    const int tyi = tile % nty;
+    const int chunk = tile / nty;
+    const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
+    const int i = txi * TX - 2 + tx, j = tyi * TY - 2 + ty;
+    const bool indom = (i >= 0 && i < F.nx && j >= 0 && j < F.ny);
+    const bool ring1 = indom && tx >= 1 && tx < BX - 1 && ty >= 1 && ty < BY - 1;
+    const bool inner = indom && tx >= 2 && tx < BX - 2 && ty >= 2 && ty < BY - 2;
+    const int nz = F.nz;
+    const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
+    const int64_t plane = (int64_t)F.nx * F.ny;
+    const int64_t col = indom ? (int64_t)j * F.nx + i : 0;
+    T axm = 0, axp = 0, aym = 0, ayp = 0;
+    if (indom) {
+        axm = F.axm[i];
+        axp = F.axp[i];
+        aym = F.aym[j];
+        ayp = F.ayp[j];
+    }
+    const T lam = *lamp;
+    auto ld_old = [&](int k) -> T { return (indom && k >= 0 && k < nz) ? pin[(int64_t)k * plane + col] : T(0); };
+
+    T om = ld_old(k0 - 2), oc = ld_old(k0 - 1), op = ld_old(k0);
+    // value of this column at plane q after the red half-sweep
+    auto post_red = [&](int q, T &pr, T &fq, uint8_t &tq) {
+        T(*ob)[BX + 1] = oldp[q & 1];
+        ob[ty][tx] = oc;
+        __syncthreads();
+        const bool inq = indom && q >= 0 && q < nz;
+        tq = inq ? F.type[(int64_t)q * plane + col] : T_DEAD;
+        fq = inq ? f[(int64_t)q * plane + col] : T(0);
+        pr = oc;
+        if (ring1 && inq && tq == T_FLUID && ((i + j + q) & 1) == 0) {
+            const T azm = F.azm[q], azp = F.azp[q];
+            T s = 0;
+            s = s + axm * ob[ty][tx - 1];
+            s = s + axp * ob[ty][tx + 1];
+            s = s + aym * ob[ty - 1][tx];
+            s = s + ayp * ob[ty + 1][tx];
+            s = s + azm * om;
+            s = s + azp * op;
+            T d = axm + axp;
+            d = d + aym;
+            d = d + ayp;
+            d = d + azm;
+            d = d + azp;
+            pr = (s - (fq - lam)) / d;
+        }
+    };
+    T prA, prB, prC, fB, fC, fdum;
+    uint8_t tB, tC, tdum;
+    post_red(k0 - 1, prA, fdum, tdum);
+    om = oc;
+    oc = op;
+    op = ld_old(k0 + 1);
+    post_red(k0, prB, fB, tB);
+    om = oc;
+    oc = op;
+    op = ld_old(k0 + 2);
+    for (int k = k0; k < k1; ++k) {
+        post_red(k + 1, prC, fC, tC);
+        om = oc;
+        oc = op;
+        op = ld_old(k + 3);
+        redp[ty][tx] = prB;
+        __syncthreads();
+        if (inner) {
+            T out = prB;
+            if (tB == T_FLUID && ((i + j + k) & 1) == 1) {
+                const T azm = F.azm[k], azp = F.azp[k];
+                T s = 0;
+                s = s + axm * redp[ty][tx - 1];
+                s = s + axp * redp[ty][tx + 1];
+                s = s + aym * redp[ty - 1][tx];
+                s = s + ayp * redp[ty + 1][tx];
+                s = s + azm * prA;
+                s = s + azp * prC;
+                T d = axm + axp;
+                d = d + aym;
+                d = d + ayp;
+                d = d + azm;
+                d = d + azp;
+                out = (s - (fB - lam)) / d;
+            }
+            pout[(int64_t)k * plane + col] = out;
+        }
+        prA = prB;
+        prB = prC;
+        fB = fC;
+        tB = tC;
+    }
+}
+
+constexpr int SW_BX = 64, SW_BY = 16;
+
+template <typename T>
+static hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
+    constexpr int TX = SW_BX - 4, TY = SW_BY - 4;
+    int ntx = (F.nx + TX - 1) / TX, nty = (F.ny + TY - 1) / TY;
+    int64_t per_slab = (int64_t)ntx * nty;
+    // chunk the z range so the launch holds enough workgroups for 256 CUs
+    int nchunk = (int)((2048 + per_slab - 1) / per_slab);
+    if (nchunk > F.nz) nchunk = F.nz;
+    if (nchunk < 1) nchunk = 1;
+    int kc = (F.nz + nchunk - 1) / nchunk;
+    if (kc < 8 && F.nz >= 8) kc = 8;
+    nchunk = (F.nz + kc - 1) / kc;
+    int ntiles = (int)(per_slab * nchunk);
+    int grid = ((ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_rbgs_fused<T, SW_BX, SW_BY>), dim3(grid), dim3(SW_BX * SW_BY), 0, s, F, pin, pout, f, lam,
+                       ntx, nty, kc, ntiles);
+    return hipGetLastError();
+}
+
+// =======================================================================================
+// ghost refresh: p_g = sum_{m != g} beta_m p_m + h_g from one snapshot (Jacobi over ghosts)
+// fluid members are read from dst (already updated), ghost members from src_ghost (the
+// values before this pass); degenerate ghosts take the mean of their fluid 26-neighbours.
+// Weights are FP64; the FP32 error equation is homogeneous (h = 0).
+// =======================================================================================
+
+template <typename T>
+__global__ void k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T *dst, int nx, int ny, int nz,
+                                const uint8_t *__restrict__ type, int homogeneous) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G.ng) return;
+    const int64_t cell = G.cell[g];
+    double v;
+    if (G.flags[g] & GF_DEGENERATE) {
+        int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((int64_t)nx * ny));
+        double s = 0.0;
+        int n = 0;
+        for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    int ii = i + di, jj = j + dj, kk = k + dk;
+                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                    int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
+                    if (type[q] == T_FLUID) {
+                        s += (double)dst[q];
+                        ++n;
+                    }
+                }
+        v = n ? s / n : 0.0;
+    } else {
+        const int32_t *st = G.st + 8 * g;
+        const double *beta = G.beta + 8 * g;
+        const unsigned gm = G.gmask[g];
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int32_t q = st[m];
+            if (q >= 0) {
+                const T pv = ((gm >> m) & 1u) ? src_ghost[q] : dst[q];
+                s = s + beta[m] * (double)pv;
+            }
+        }
+        v = homogeneous ? s : s + G.h[g];
+    }
+    dst[cell] = (T)v;
+}
+
+static GhostView ghost_view(ibm_grid *g) {
+    GhostView G;
+    G.ng = g->ng;
+    G.cell = g->g_cell;
+    G.st = g->g_st;
+    G.gmask = g->g_mask;
+    G.beta = g->g_beta;
+    G.h = g->g_h;
+    G.flags = g->g_flags;
+    return G;
+}
+
+template <typename T>
+static hipError_t launch_refresh(ibm_grid *g, const T *src_ghost, T *dst, int homogeneous, hipStream_t s) {
+    if (g->ng == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_refresh<T>, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, ghost_view(g),
+                       src_ghost, dst, g->nx, g->ny, g->nz, g->type, homogeneous);
+    return hipGetLastError();
+}
+
+// =======================================================================================
+// fine-level operator view helpers
+// =======================================================================================
+
+static Fine<double> fine64(ibm_grid *g) {
+    Fine<double> F;
+    F.nx = g->nx;
+    F.ny = g->ny;
+    F.nz = g->nz;
+    F.axm = g->am0[0];
+    F.axp = g->ap0[0];
+    F.aym = g->am0[1];
+    F.ayp = g->ap0[1];
+    F.azm = g->am0[2];
+    F.azp = g->ap0[2];
+    F.wx = g->w0[0];
+    F.wy = g->w0[1];
+    F.wz = g->w0[2];
+    F.type = g->type;
+    return F;
+}
+static Fine<float> fine32(ibm_grid *g) {
+    Fine<float> F;
+    F.nx = g->nx;
+    F.ny = g->ny;
+    F.nz = g->nz;
+    F.axm = g->am0f[0];
+    F.axp = g->ap0f[0];
+    F.aym = g->am0f[1];
+    F.ayp = g->ap0f[1];
+    F.azm = g->am0f[2];
+    F.azp = g->ap0f[2];
+    F.wx = g->w0f[0];
+    F.wy = g->w0f[1];
+    F.wz = g->w0f[2];
+    F.type = g->type;
+    return F;
+}
+template <typename T>
+static Coarse<T> coarse_view(ibm_grid *g, int l);
+template <>
+Coarse<double> coarse_view<double>(ibm_grid *g, int l) {
+    LevelHost &L = g->lev[l];
+    Coarse<double> C;
+    for (int d = 0; d < 3; ++d) {
+        C.n[d] = L.n[d];
+        C.w[d] = L.w64[d];
+        C.Tl[d] = L.T64[d];
+    }
+    C.active = L.active;
+    C.e = L.e64;
+    C.R = L.R64;
+    C.mu = &g->sc->mu[l];
+    return C;
+}
+template <>
+Coarse<float> coarse_view<float>(ibm_grid *g, int l) {
+    LevelHost &L = g->lev[l];
+    Coarse<float> C;
+    for (int d = 0; d < 3; ++d) {
+        C.n[d] = L.n[d];
+        C.w[d] = L.w32[d];
+        C.Tl[d] = L.T32[d];
+    }
+    C.active = L.active;
+    C.e = L.e32;
+    C.R = L.R32;
+    C.mu = &g->sc->mu[l];
+    return C;
+}
+static ProlongTab prolong_tab(ibm_grid *g, int l) {  // table of level l from level l+1
+    ProlongTab P;
+    for (int d = 0; d < 3; ++d) {
+        P.lo[d] = g->lev[l].plo[d];
+        P.hi[d] = g->lev[l].phi[d];
+        P.t[d] = g->lev[l].pt[d];
+        P.halved[d] = g->lev[l + 1].halved[d];
+    }
+    return P;
+}
+
+template <typename T>
+__device__ __forceinline__ void fine_stencil(const Fine<T> &F, const T *__restrict__ p, int i, int j, int k, int64_t id,
+                                             T &num, T &diag) {
+    const int64_t sy = F.nx, sz = (int64_t)F.nx * F.ny;
+    const T axm = F.axm[i], axp = F.axp[i], aym = F.aym[j], ayp = F.ayp[j], azm = F.azm[k], azp = F.azp[k];
+    T s = 0;
+    s = s + (i > 0 ? axm * p[id - 1] : T(0));
+    s = s + (i < F.nx - 1 ? axp * p[id + 1] : T(0));
+    s = s + (j > 0 ? aym * p[id - sy] : T(0));
+    s = s + (j < F.ny - 1 ? ayp * p[id + sy] : T(0));
+    s = s + (k > 0 ? azm * p[id - sz] : T(0));
+    s = s + (k < F.nz - 1 ? azp * p[id + sz] : T(0));
+    T d = axm + axp;
+    d = d + aym;
+    d = d + ayp;
+    d = d + azm;
+    d = d + azp;
+    num = s;
+    diag = d;
+}
+
+template <typename T>
+__device__ __forceinline__ void coarse_stencil(const Coarse<T> &L, const T *__restrict__ e, int I, int J, int K,
+                                               int64_t id, T &num, T &diag) {
+    const int64_t sy = L.n[0], sz = (int64_t)L.n[0] * L.n[1];
+    const T txm = L.Tl[0][id], txp = (I < L.n[0] - 1) ? L.Tl[0][id + 1] : T(0);
+    const T tym = L.Tl[1][id], typ = (J < L.n[1] - 1) ? L.Tl[1][id + sy] : T(0);
+    const T tzm = L.Tl[2][id], tzp = (K < L.n[2] - 1) ? L.Tl[2][id + sz] : T(0);
+    T s = 0;
+    s = s + (I > 0 ? txm * e[id - 1] : T(0));
+    s = s + (I < L.n[0] - 1 ? txp * e[id + 1] : T(0));
+    s = s + (J > 0 ? tym * e[id - sy] : T(0));
+    s = s + (J < L.n[1] - 1 ? typ * e[id + sy] : T(0));
+    s = s + (K > 0 ? tzm * e[id - sz] : T(0));
+    s = s + (K < L.n[2] - 1 ? tzp * e[id + sz] : T(0));
+    T d = txm + txp;
+    d = d + tym;
+    d = d + typ;
+    d = d + tzm;
+    d = d + tzp;
+    num = s;
+    diag = d;
+}
+
+// =======================================================================================
+// residual + restriction, fused with block partial sums of the coarse right-hand side
+// =======================================================================================
+
+struct Halv {
+    int h[3];
+};
+
+// level 0 -> 1: R_1(C) = sum over fluid children of V_c r_c, r = (f - lambda) - S p
+template <typename T>
+__global__ void k_resrestrict0(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
+                               Coarse<T> C, Halv H, double *partials) {
+    __shared__ double sh[4];
+    const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double Rsum = 0.0;
+    if (cid < NC) {
+        const T lam = *lamp;
+        int I = (int)(cid % C.n[0]), J = (int)((cid / C.n[0]) % C.n[1]), K = (int)(cid / ((int64_t)C.n[0] * C.n[1]));
+        int i0 = H.h[0] ? 2 * I : I, i1 = H.h[0] ? 2 * I + 1 : I;
+        int j0 = H.h[1] ? 2 * J : J, j1 = H.h[1] ? 2 * J + 1 : J;
+        int k0 = H.h[2] ? 2 * K : K, k1 = H.h[2] ? 2 * K + 1 : K;
+        T R = 0;
+        for (int k = k0; k <= k1; ++k)
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) {
+                    const int64_t id = ((int64_t)k * F.ny + j) * F.nx + i;
+                    if (F.type[id] != T_FLUID) continue;
+                    T num, diag;
+                    fine_stencil(F, p, i, j, k, id, num, diag);
+                    const T r = (f[id] - lam) - (num - diag * p[id]);
+                    const T vol = (F.wx[i] * F.wy[j]) * F.wz[k];
+                    R += vol * r;
+                }
+        C.R[cid] = R;
+        C.e[cid] = T(0);
+        Rsum = (double)R;
+    }
+    double s = block_sum<256>(Rsum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// level l -> l+1 (l >= 1): R_{l+1}(C) = sum over active children of r, r = (R - V mu) - S e
+template <typename T>
+__global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partials) {
+    __shared__ double sh[4];
+    const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double Rsum = 0.0;
+    if (cid < NC) {
+        const T mu = (T)(*L.mu);
+        int I = (int)(cid % C.n[0]), J = (int)((cid / C.n[0]) % C.n[1]), K = (int)(cid / ((int64_t)C.n[0] * C.n[1]));
+        int i0 = H.h[0] ? 2 * I : I, i1 = H.h[0] ? 2 * I + 1 : I;
+        int j0 = H.h[1] ? 2 * J : J, j1 = H.h[1] ? 2 * J + 1 : J;
+        int k0 = H.h[2] ? 2 * K : K, k1 = H.h[2] ? 2 * K + 1 : K;
+        T R = 0;
+        for (int k = k0; k <= k1; ++k)
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) {
+                    const int64_t id = ((int64_t)k * L.n[1] + j) * L.n[0] + i;
+                    if (!L.active[id]) continue;
+                    T num, diag;
+                    coarse_stencil(L, L.e, i, j, k, id, num, diag);
+                    const T vol = (L.w[0][i] * L.w[1][j]) * L.w[2][k];
+                    R += (L.R[id] - vol * mu) - (num - diag * L.e[id]);
+                }
+        C.R[cid] = R;
+        C.e[cid] = T(0);
+        Rsum = (double)R;
+    }
+    double s = block_sum<256>(Rsum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// mu = sum(partials) / vol  (fixed order)
+__global__ void k_finalize_mu(const double *partials, int n, const double *vol, double *mu) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) s += partials[q];
+    s = block_sum<256>(s, sh, threadIdx.x);
+    if (threadIdx.x == 0) *mu = (*vol > 0.0) ? s / *vol : 0.0;
+}
+
+// =======================================================================================
+// coarse levels: red-black GS on  sum_F T_F (e_NB - e_C) = R_C - V_C mu
+// =======================================================================================
+
+template <typename T>
+__global__ void k_sweepC(Coarse<T> L, int colour) {
+    const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= NC) return;
+    int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+    if (((I + J + K) & 1) != colour || !L.active[id]) return;
+    T num, diag;
+    coarse_stencil(L, L.e, I, J, K, id, num, diag);
+    if (diag > T(0)) {
+        const T vol = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+        L.e[id] = (num - (L.R[id] - vol * (T)(*L.mu))) / diag;
+    }
+}
+
+// coarsest level in one workgroup: e = 0 (set by the restriction), n sweeps, then removal
+// of the volume-weighted mean over the active cells
+template <typename T>
+__global__ void __launch_bounds__(1024) k_coarsest(Coarse<T> L, int nsweeps, const double *vol) {
+    __shared__ double sh[16];
+    const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
+    const T mu = (T)(*L.mu);
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t id = threadIdx.x; id < NC; id += 1024) {
+                int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+                if (((I + J + K) & 1) != colour || !L.active[id]) continue;
+                T num, diag;
+                coarse_stencil(L, L.e, I, J, K, id, num, diag);
+                if (diag > T(0)) {
+                    const T v = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+                    L.e[id] = (num - (L.R[id] - v * mu)) / diag;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double acc = 0.0;
+    for (int64_t id = threadIdx.x; id < NC; id += 1024) {
+        if (!L.active[id]) continue;
+        int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+        acc += (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)L.e[id];
+    }
+    __shared__ double mean;
+    double tot = block_sum<1024>(acc, sh, threadIdx.x);
+    if (threadIdx.x == 0) mean = (*vol > 0.0) ? tot / *vol : 0.0;
+    __syncthreads();
+    const T m = (T)mean;
+    for (int64_t id = threadIdx.x; id < NC; id += 1024)
+        if (L.active[id]) L.e[id] -= m;
+}
+
+// prolongation with correction on a coarse level l from l+1: e_l += P e_{l+1} on active
+// cells (trilinear in physical coordinates, or the parent's value when a contributing
+// coarse cell is inactive)
+template <typename T>
+__device__ __forceinline__ double prolong_value(const Coarse<T> &C, const ProlongTab &P, int i, int j, int k) {
+    const int ix[2] = {P.lo[0][i], P.hi[0][i]}, iy[2] = {P.lo[1][j], P.hi[1][j]}, iz[2] = {P.lo[2][k], P.hi[2][k]};
+    const double tx = P.t[0][i], ty = P.t[1][j], tz = P.t[2][k];
+    const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+    const int nx_ = (ix[0] == ix[1]) ? 1 : 2, ny_ = (iy[0] == iy[1]) ? 1 : 2, nz_ = (iz[0] == iz[1]) ? 1 : 2;
+    bool all = true;
+    double s = 0.0;
+    for (int c = 0; c < nz_; ++c)
+        for (int b = 0; b < ny_; ++b)
+            for (int a = 0; a < nx_; ++a) {
+                const int64_t cid = ((int64_t)iz[c] * C.n[1] + iy[b]) * C.n[0] + ix[a];
+                if (!C.active[cid]) all = false;
+                s += (wx[a] * wy[b]) * wz[c] * (double)C.e[cid];
+            }
+    if (!all) {
+        const int pi = P.halved[0] ? i / 2 : i, pj = P.halved[1] ? j / 2 : j, pk = P.halved[2] ? k / 2 : k;
+        s = (double)C.e[((int64_t)pk * C.n[1] + pj) * C.n[0] + pi];
+    }
+    return s;
+}
+
+template <typename T>
+__global__ void k_prolongC(Coarse<T> L, Coarse<T> C, ProlongTab P) {
+    const int64_t N = (int64_t)L.n[0] * L.n[1] * L.n[2];
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N || !L.active[id]) return;
+    int i = (int)(id % L.n[0]), j = (int)((id / L.n[0]) % L.n[1]), k = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+    L.e[id] = (T)((double)L.e[id] + prolong_value(C, P, i, j, k));
+}
+
+// level 0: pnext = pcur + P e_1 on fluid cells (ghosts are refreshed afterwards)
+template <typename T>
+__global__ void k_prolong0(Fine<T> F, const T *__restrict__ pcur, T *pnext, Coarse<T> C, ProlongTab P) {
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N || F.type[id] != T_FLUID) return;
+    int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+    pnext[id] = (T)((double)pcur[id] + prolong_value(C, P, i, j, k));
+}
+
+// =======================================================================================
+// residual norm on level 0 with the lambda update
+//   r = f - S p (fluid rows);  a = r - lambda_k;  partials of sum V a, sum a^2, sum a
+//   lambda_{k+1} = lambda_k + delta, delta = sum V a / sum V
+//   ||r - lambda_{k+1}||^2 = sum a^2 - 2 delta sum a + delta^2 n_fluid
+// WRITE_R32: also store the FP32 right-hand side a for the mixed-precision inner cycle
+// =======================================================================================
+
+constexpr int NORM_NT = 256;
+
+template <bool WRITE_R32>
+__global__ void __launch_bounds__(NORM_NT) k_norm0(Fine<double> F, const double *__restrict__ p,
+                                                   const double *__restrict__ f, const double *__restrict__ lamp,
+                                                   float *r32, double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const double lam = *lamp;
+    double sv = 0.0, s2 = 0.0, s1 = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) {
+            if (WRITE_R32) r32[id] = 0.0f;
+            continue;
+        }
+        int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        double num, diag;
+        fine_stencil(F, p, i, j, k, id, num, diag);
+        const double r = f[id] - (num - diag * p[id]);
+        const double a = r - lam;
+        sv += ((F.wx[i] * F.wy[j]) * F.wz[k]) * a;
+        s2 += a * a;
+        s1 += a;
+        if (WRITE_R32) r32[id] = (float)a;
+    }
+    double t;
+    t = block_sum<NORM_NT>(sv, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[3 * blockIdx.x] = t;
+    t = block_sum<NORM_NT>(s2, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[3 * blockIdx.x + 1] = t;
+    t = block_sum<NORM_NT>(s1, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[3 * blockIdx.x + 2] = t;
+}
+
+__global__ void k_norm_finalize(const double *partials, int nb, Scalars *sc, double nfluid, int set_ref) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) {
+        a += partials[3 * q];
+        b += partials[3 * q + 1];
+        c += partials[3 * q + 2];
+    }
+    a = block_sum<256>(a, sh, threadIdx.x);
+    b = block_sum<256>(b, sh, threadIdx.x);
+    c = block_sum<256>(c, sh, threadIdx.x);
+    if (threadIdx.x == 0) {
+        const double delta = a / sc->vol[0];
+        double q2 = b - 2.0 * delta * c + delta * delta * nfluid;
+        if (q2 < 0.0) q2 = 0.0;
+        const double nrm = sqrt(q2);
+        sc->lambda = sc->lambda + delta;
+        sc->delta = delta;
+        sc->delta32 = (float)delta;
+        sc->norm = nrm;
+        if (set_ref) sc->ref = nrm;
+        sc->rel = (sc->ref > 0.0) ? nrm / sc->ref : 0.0;
+        if (!isfinite(nrm) || !isfinite(sc->lambda)) sc->bad = 1;
+    }
+}
+
+// reference norm ||f - Vmean(f)|| over fluid cells (two passes: mean, then deviations)
+__global__ void __launch_bounds__(NORM_NT) k_fsum(Fine<double> F, const double *__restrict__ f, const double *meanp,
+                                                  double *partials, int pass) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const double mean = pass ? *meanp : 0.0;
+    double s = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) continue;
+        if (pass == 0) {
+            int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+            s += ((F.wx[i] * F.wy[j]) * F.wz[k]) * f[id];
+        } else {
+            const double d = f[id] - mean;
+            s += d * d;
+        }
+    }
+    double t = block_sum<NORM_NT>(s, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void k_fsum_finalize(const double *partials, int nb, Scalars *sc, int pass) {
+    __shared__ double sh[4];
+    double a = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) a += partials[q];
+    a = block_sum<256>(a, sh, threadIdx.x);
+    if (threadIdx.x == 0) {
+        if (pass == 0) sc->vmean = a / sc->vol[0];
+        else sc->ref = sqrt(a);
+    }
+}
+
+// volume-weighted mean of p over fluid cells, then pdst = pcur - mean (fluid, ghost), 0 (dead)
+__global__ void __launch_bounds__(NORM_NT) k_psum(Fine<double> F, const double *__restrict__ p, double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    double s = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) continue;
+        int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        s += ((F.wx[i] * F.wy[j]) * F.wz[k]) * p[id];
+    }
+    double t = block_sum<NORM_NT>(s, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void k_shift(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ pcur, double *pdst,
+                        const Scalars *sc) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    const double m = sc->vmean;
+    pdst[id] = (type[id] == T_DEAD) ? 0.0 : pcur[id] - m;
+}
+
+// =======================================================================================
+// launchers
+// =======================================================================================
+
+hipError_t sweep0_f64(ibm_grid *g, const double *pin, double *pout, const double *f, const double *lambda,
+                      hipStream_t s) {
+    return launch_sweep<double>(fine64(g), pin, pout, f, lambda, s);
+}
+
+hipError_t refresh_f64(ibm_grid *g, const double *src_ghost, double *dst, hipStream_t s) {
+    return launch_refresh<double>(g, src_ghost, dst, 0, s);
+}
+
+template <typename T>
+__global__ void k_apply0(Fine<T> F, const T *__restrict__ p, T *out) {
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    if (F.type[id] != T_FLUID) {
+        out[id] = T(0);
+        return;
+    }
+    int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+    T num, diag;
+    fine_stencil(F, p, i, j, k, id, num, diag);
+    out[id] = num - diag * p[id];
+}
+
+hipError_t apply0_f64(ibm_grid *g, const double *p, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply0<double>, dim3((unsigned)((g->N + 255) / 256)), dim3(256), 0, s, fine64(g), p, out);
+    return hipGetLastError();
+}
+
+static int nblk(int64_t n, int nt = 256) { return (int)((n + nt - 1) / nt); }
+
+template <typename T>
+struct FineOf;
+template <>
+struct FineOf<double> {
+    static Fine<double> get(ibm_grid *g) { return fine64(g); }
+};
+template <>
+struct FineOf<float> {
+    static Fine<float> get(ibm_grid *g) { return fine32(g); }
+};
+
+// one V(nu1, nu2) cycle in precision T on level 0.
+// bufs[0..1]: the two level-0 buffers, *cur: index of the current iterate.
+// rhs: level-0 right-hand side; lam: device scalar shift of the right-hand side;
+// homogeneous: ghost equations without right-hand side (error equation).
+// level-0 sweep, bracketed by timing events when profiling is on
+template <typename T>
+static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *pout, const T *rhs, const T *lam,
+                              hipStream_t s) {
+    Prof &P = g->prof;
+    const bool rec = P.on && P.used + 2 <= (int)P.ev.size();
+    hipError_t e;
+    if (rec && (e = hipEventRecord(P.ev[P.used], s)) != hipSuccess) return e;
+    if ((e = launch_sweep<T>(F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
+    if (rec) {
+        if ((e = hipEventRecord(P.ev[P.used + 1], s)) != hipSuccess) return e;
+        P.kind[P.used / 2] = (sizeof(T) == 8) ? 0 : 1;
+        P.used += 2;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, int homogeneous,
+                              const ibm_solve_opts *o, hipStream_t s) {
+    const Fine<T> F = FineOf<T>::get(g);
+    hipError_t e;
+    for (int q = 0; q < o->nu1; ++q) {
+        T *pin = bufs[*cur], *pout = bufs[1 - *cur];
+        if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
+        if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+        *cur = 1 - *cur;
+    }
+    if (g->nlev > 1) {
+        {
+            Coarse<T> C1 = coarse_view<T>(g, 1);
+            Halv H;
+            for (int d = 0; d < 3; ++d) H.h[d] = g->lev[1].halved[d];
+            int nb = nblk(g->lev[1].ncell());
+            hipLaunchKernelGGL(k_resrestrict0<T>, dim3(nb), dim3(256), 0, s, F, bufs[*cur], rhs, lam, C1, H,
+                               g->partials);
+            hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nb, &g->sc->vol[1],
+                               &g->sc->mu[1]);
+        }
+        const int Lc = g->nlev - 1;
+        for (int l = 1; l < Lc; ++l) {
+            Coarse<T> L = coarse_view<T>(g, l);
+            int nb = nblk(g->lev[l].ncell());
+            for (int q = 0; q < o->nu1; ++q) {
+                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
+                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+            }
+            Coarse<T> C = coarse_view<T>(g, l + 1);
+            Halv H;
+            for (int d = 0; d < 3; ++d) H.h[d] = g->lev[l + 1].halved[d];
+            int nbc = nblk(g->lev[l + 1].ncell());
+            hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, H, g->partials);
+            hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
+                               &g->sc->mu[l + 1]);
+        }
+        hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(1024), 0, s, coarse_view<T>(g, Lc), o->coarsest_sweeps,
+                           &g->sc->vol[Lc]);
+        for (int l = Lc - 1; l >= 1; --l) {
+            Coarse<T> L = coarse_view<T>(g, l);
+            int nb = nblk(g->lev[l].ncell());
+            hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), prolong_tab(g, l));
+            for (int q = 0; q < o->nu2; ++q) {
+                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
+                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+            }
+        }
+        {
+            T *pin = bufs[*cur], *pout = bufs[1 - *cur];
+            hipLaunchKernelGGL(k_prolong0<T>, dim3(nblk(g->N)), dim3(256), 0, s, F, pin, pout, coarse_view<T>(g, 1),
+                               prolong_tab(g, 0));
+            if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+            *cur = 1 - *cur;
+        }
+    }
+    for (int q = 0; q < o->nu2; ++q) {
+        T *pin = bufs[*cur], *pout = bufs[1 - *cur];
+        if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
+        if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+        *cur = 1 - *cur;
+    }
+    return hipGetLastError();
+}
+
+hipError_t vcycle_f64(ibm_grid *g, double **bufs, int *cur, const double *f, hipStream_t s, const ibm_solve_opts *o) {
+    return vcycle_impl<double>(g, bufs, cur, f, &g->sc->lambda, 0, o, s);
+}
+
+// e32 := 0 (dead cells too), so the inner cycle starts from a zero correction
+__global__ void k_zero32(float *a, float *b, int64_t N) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    a[id] = 0.0f;
+    b[id] = 0.0f;
+}
+
+// p_next = p_cur + e on fluid cells (FP64 update of the refinement step)
+__global__ void k_add_correction(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ pcur,
+                                 const float *__restrict__ e, double *pnext) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N || type[id] != T_FLUID) return;
+    pnext[id] = pcur[id] + (double)e[id];
+}
+
+// one mixed-precision refinement step: the FP32 right-hand side r32 = r - lambda_k was
+// written by the preceding FP64 norm pass and delta32 = lambda_{k+1} - lambda_k; solve
+// S e = r32 - delta with one FP32 V-cycle from e = 0, then p += e and an FP64 ghost refresh
+hipError_t vcycle_mixed(ibm_grid *g, double **bufs, int *cur, const double *f, hipStream_t s,
+                        const ibm_solve_opts *o) {
+    (void)f;
+    hipError_t e;
+    hipLaunchKernelGGL(k_zero32, dim3(nblk(g->N)), dim3(256), 0, s, g->e32a, g->e32b, g->N);
+    float *eb[2] = {g->e32a, g->e32b};
+    int ecur = 0;
+    if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->delta32, 1, o, s)) != hipSuccess) return e;
+    double *pin = bufs[*cur], *pout = bufs[1 - *cur];
+    hipLaunchKernelGGL(k_add_correction, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->N, pin, eb[ecur], pout);
+    if ((e = launch_refresh<double>(g, pin, pout, 0, s)) != hipSuccess) return e;
+    *cur = 1 - *cur;
+    return hipGetLastError();
+}
+
+hipError_t norm_pass(ibm_grid *g, const double *p, const double *f, hipStream_t s, bool write_r32, bool first) {
+    if (write_r32)
+        hipLaunchKernelGGL(k_norm0<true>, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), p, f, &g->sc->lambda, g->r32,
+                           g->partials);
+    else
+        hipLaunchKernelGGL(k_norm0<false>, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), p, f, &g->sc->lambda,
+                           (float *)nullptr, g->partials);
+    hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc, (double)g->nfluid,
+                       0);
+    (void)first;
+    return hipGetLastError();
+}
+
+hipError_t ref_norm_pass(ibm_grid *g, const double *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_fsum, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), f, &g->sc->vmean, g->partials, 0);
+    hipLaunchKernelGGL(k_fsum_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc, 0);
+    hipLaunchKernelGGL(k_fsum, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), f, &g->sc->vmean, g->partials, 1);
+    hipLaunchKernelGGL(k_fsum_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc, 1);
+    return hipGetLastError();
+}
+
+hipError_t gauge_pass(ibm_grid *g, const double *pcur, double *pdst, hipStream_t s) {
+    hipLaunchKernelGGL(k_psum, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), pcur, g->partials);
+    hipLaunchKernelGGL(k_fsum_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc, 0);
+    hipLaunchKernelGGL(k_shift, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->N, pcur, pdst, g->sc);
+    return hipGetLastError();
+}
+
+// start of a solve: both buffers hold the initial iterate on fluid and ghost cells (zero
+// unless a guess is given) and 0 on dead cells; then the ghosts of p2 are refreshed
+__global__ void k_init(const uint8_t *__restrict__ type, int64_t N, double *p, double *p2, int use_guess) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    double v = (type[id] == T_DEAD || !use_guess) ? 0.0 : p[id];
+    p[id] = v;
+    p2[id] = v;
+}
+
+hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->N, p, p2, use_guess);
+    return launch_refresh<double>(g, p, p2, 0, s);
+}
+
+// =======================================================================================
+// projection: divergence right-hand side and velocity correction (MAC faces)
+// =======================================================================================
+
+__global__ void k_rhs(Fine<double> F, const double *__restrict__ u, const double *__restrict__ v,
+                      const double *__restrict__ w, double dt, double *f) {
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    if (F.type[id] != T_FLUID) {
+        f[id] = 0.0;
+        return;
+    }
+    const int nx = F.nx, ny = F.ny;
+    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    const int64_t iu = ((int64_t)k * ny + j) * (nx + 1) + i;
+    const int64_t iv = ((int64_t)k * (ny + 1) + j) * nx + i;
+    const int64_t iw = ((int64_t)k * ny + j) * nx + i;
+    double div = (u[iu + 1] - u[iu]) / F.wx[i];
+    div = div + (v[iv + nx] - v[iv]) / F.wy[j];
+    div = div + (w[iw + (int64_t)nx * ny] - w[iw]) / F.wz[k];
+    f[id] = div / dt;
+}
+
+hipError_t rhs_pass(ibm_grid *g, const double *u, const double *v, const double *w, double dt, double *f,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs, dim3(nblk(g->N)), dim3(256), 0, s, fine64(g), u, v, w, dt, f);
+    return hipGetLastError();
+}
+
+// u_f -= dt (p_nb - p_c)/d_f on interior faces with at least one fluid cell; axis d
+__global__ void k_correct(const uint8_t *__restrict__ type, int nx, int ny, int nz, int d,
+                          const double *__restrict__ dc, const double *__restrict__ p, double dt, double *u) {
+    // faces along d: index space with n_d + 1 entries along d
+    const int fx = nx + (d == 0), fy = ny + (d == 1), fz = nz + (d == 2);
+    const int64_t NF = (int64_t)fx * fy * fz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= NF) return;
+    int i = (int)(id % fx), j = (int)((id / fx) % fy), k = (int)(id / ((int64_t)fx * fy));
+    int q = (d == 0) ? i : (d == 1) ? j : k;
+    int n = (d == 0) ? nx : (d == 1) ? ny : nz;
+    if (q == 0 || q == n) return;  // domain walls
+    const int64_t b = ((int64_t)k * ny + j) * nx + i;
+    const int64_t a = b - ((d == 0) ? 1 : (d == 1) ? (int64_t)nx : (int64_t)nx * ny);
+    if (type[a] != T_FLUID && type[b] != T_FLUID) return;
+    u[id] -= dt * (p[b] - p[a]) / dc[q];
+}
+
+hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt, hipStream_t s) {
+    double *arr[3] = {u, v, w};
+    for (int d = 0; d < 3; ++d) {
+        int64_t NF = (int64_t)(g->nx + (d == 0)) * (g->ny + (d == 1)) * (g->nz + (d == 2));
+        hipLaunchKernelGGL(k_correct, dim3(nblk(NF)), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, d, g->dc0[d], p, dt,
+                           arr[d]);
+    }
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(NORM_NT) k_divmax(Fine<double> F, const double *__restrict__ u,
+                                                    const double *__restrict__ v, const double *__restrict__ w,
+                                                    double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    const int nx = F.nx, ny = F.ny;
+    double m = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) continue;
+        int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+        const int64_t iu = ((int64_t)k * ny + j) * (nx + 1) + i;
+        const int64_t iv = ((int64_t)k * (ny + 1) + j) * nx + i;
+        const int64_t iw = ((int64_t)k * ny + j) * nx + i;
+        double div = (u[iu + 1] - u[iu]) / F.wx[i];
+        div = div + (v[iv + nx] - v[iv]) / F.wy[j];
+        div = div + (w[iw + (int64_t)nx * ny] - w[iw]) / F.wz[k];
+        m = fmax(m, fabs(div));
+    }
+    double t = block_max<NORM_NT>(m, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void k_max_finalize(const double *partials, int nb, Scalars *sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double m = 0.0;
+        for (int q = 0; q < nb; ++q) m = fmax(m, partials[q]);
+        sc->div_max = m;
+    }
+}
+
+hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s) {
+    hipLaunchKernelGGL(k_divmax, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), u, v, w, g->partials);
+    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(64), 0, s, g->partials, RED_BLOCKS, g->sc);
+    return hipGetLastError();
+}
+
+}  // namespace ibm

@@ -1,0 +1,374 @@
+"""Thin ctypes binding of the HIP library (include/ibm.h).  Argument marshalling only.
+
+PyTorch provides the device memory (one workspace tensor per grid) and the streams; every
+step of the method runs in the library's kernels.  Importing this module raises if the
+built library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibm.so")
+
+IBM_OK, IBM_NOT_CONVERGED = 0, 1
+IBM_E_ARG, IBM_E_STATE, IBM_E_GEOMETRY, IBM_E_NOMEM, IBM_E_DEVICE, IBM_E_NUMERIC = -1, -2, -3, -4, -5, -6
+IBM_FP64, IBM_MIXED = 0, 1
+_STATUS = {0: "IBM_OK", 1: "IBM_NOT_CONVERGED", -1: "IBM_E_ARG", -2: "IBM_E_STATE", -3: "IBM_E_GEOMETRY",
+           -4: "IBM_E_NOMEM", -5: "IBM_E_DEVICE", -6: "IBM_E_NUMERIC"}
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("coarsest_sweeps", C.c_int), ("precision", C.c_int), ("use_initial_guess", C.c_int),
+                ("fixed_cycles", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("rel_residual", C.c_double), ("ghost_residual_max", C.c_double),
+                ("lambda_", C.c_double), ("div_max", C.c_double), ("t_setup", C.c_double),
+                ("t_solve", C.c_double), ("t_correct", C.c_double)]
+
+
+@dataclass
+class Stats:
+    status: int
+    cycles: int
+    rel_residual: float
+    lam: float
+    div_max: float
+    t_solve: float
+    t_correct: float
+
+
+class IBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libibm.so is not built (run `python -m paper_2505_17287_amd.build`)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+        L.ibm_default_opts.argtypes = [C.POINTER(SolveOpts)]
+        L.ibm_create_grid.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.POINTER(vp)]
+        L.ibm_workspace_bytes.restype = C.c_size_t
+        L.ibm_workspace_bytes.argtypes = [C.c_int, C.c_int, C.c_int, i64, i64, i64, C.c_int]
+        L.ibm_grid_workspace_bytes.restype = C.c_size_t
+        L.ibm_grid_workspace_bytes.argtypes = [vp, i64, i64, i64, C.c_int]
+        L.ibm_bind_workspace.argtypes = [vp, vp, C.c_size_t, i64, i64, i64, C.c_int, vp]
+        L.ibm_set_geometry.argtypes = [vp, dp, i64, vp, i64, vp]
+        L.ibm_classify.argtypes = [vp, vp, vp]
+        L.ibm_build_ghost_stencils.argtypes = [vp, vp, vp]
+        L.ibm_get_ghosts.argtypes = [vp, vp] + [vp] * 7
+        L.ibm_set_neumann_data.argtypes = [vp, vp, vp]
+        L.ibm_get_cell_types.argtypes = [vp, vp, vp]
+        L.ibm_poisson_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+        L.ibm_project.argtypes = [vp, vp, vp, vp, C.c_double, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+        L.ibm_solve_begin.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp]
+        L.ibm_solve_step.argtypes = [vp, C.c_int]
+        L.ibm_solve_poll.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(SolveStats)]
+        L.ibm_get_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
+        L.ibm_debug_sweep.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp]
+        L.ibm_debug_apply.argtypes = [vp, vp, vp, vp]
+        L.ibm_set_profiling.argtypes = [vp, C.c_int]
+        L.ibm_get_profile.argtypes = [vp, vp, vp, vp, vp]
+        L.ibm_set_profiling.restype = C.c_int
+        L.ibm_get_profile.restype = C.c_int
+        L.ibm_destroy_grid.argtypes = [vp]
+        L.ibm_last_error.restype = C.c_char_p
+        L.ibm_last_error.argtypes = [vp]
+        for name in ("ibm_create_grid", "ibm_bind_workspace", "ibm_set_geometry", "ibm_classify",
+                     "ibm_build_ghost_stencils", "ibm_get_ghosts", "ibm_set_neumann_data", "ibm_get_cell_types",
+                     "ibm_poisson_solve", "ibm_project", "ibm_solve_begin", "ibm_solve_step", "ibm_solve_poll",
+                     "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def declared_symbols(header=None):
+    """Names of the functions declared in include/ibm.h."""
+    import re
+    header = header or os.path.join(os.path.dirname(_HERE), "include", "ibm.h")
+    txt = open(header).read()
+    return sorted(set(re.findall(r"\b(ibm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, precision="fp64",
+              use_initial_guess=False, fixed_cycles=0):
+    o = SolveOpts()
+    lib().ibm_default_opts(C.byref(o))
+    o.rel_tol = rel_tol
+    o.max_cycles = max_cycles
+    o.nu1, o.nu2, o.coarsest_sweeps = nu1, nu2, coarsest_sweeps
+    o.precision = IBM_MIXED if precision in ("mixed", IBM_MIXED) else IBM_FP64
+    o.use_initial_guess = int(bool(use_initial_guess))
+    o.fixed_cycles = fixed_cycles
+    return o
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _tptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def estimate_max_ghosts(xf, yf, zf, verts, tris):
+    """Capacity for the ghost list: four cells per finest-cell face of surface, plus slack."""
+    v = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tris)
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1).sum()
+    h = [np.min(np.diff(f)) for f in (xf, yf, zf)]
+    if len(zf) == 2:  # one cell thick: count per unit of the z extent inside the cell
+        hmin = min(h[0], h[1])
+        est = 4.0 * area * (h[2] / 2.0) / (hmin * hmin)
+    else:
+        hmin = min(h)
+        est = 4.0 * area / (hmin * hmin)
+    n = (len(xf) - 1) * (len(yf) - 1) * (len(zf) - 1)
+    return int(min(n, est + 4096))
+
+
+class Grid:
+    """One problem: grid + body + workspace (a torch uint8 tensor on the device)."""
+
+    def __init__(self, xf, yf, zf, precision="fp64", device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.xf = np.ascontiguousarray(xf, dtype=np.float64)
+        self.yf = np.ascontiguousarray(yf, dtype=np.float64)
+        self.zf = np.ascontiguousarray(zf, dtype=np.float64)
+        self.nx, self.ny, self.nz = len(self.xf) - 1, len(self.yf) - 1, len(self.zf) - 1
+        self.prec = IBM_MIXED if precision in ("mixed", IBM_MIXED) else IBM_FP64
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(lib().ibm_create_grid(self.nx, self.ny, self.nz, _dp(self.xf), _dp(self.yf), _dp(self.zf),
+                                          C.byref(h)), None)
+        self._h = h
+        self.ws = None
+        self.ng = 0
+
+    # -- helpers -------------------------------------------------------------------------
+    def _check(self, code, h=True):
+        if code < 0:
+            msg = lib().ibm_last_error(self._h if h else None)
+            raise IBMError(code, msg.decode() if msg else "")
+        return code
+
+    def _s(self):
+        return _stream_ptr(self.stream)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibm_destroy_grid(self._h)
+            self._h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ---------------------------------------------------------------------------
+    def workspace_bytes(self, nv_max, nt_max, max_ghosts):
+        return int(lib().ibm_grid_workspace_bytes(self._h, nv_max, nt_max, max_ghosts, self.prec))
+
+    def bind(self, nv_max, nt_max, max_ghosts):
+        torch = self.torch
+        nbytes = self.workspace_bytes(nv_max, nt_max, max_ghosts)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws
+        self._ws_ptr = ws.data_ptr() + off
+        self._caps = (nv_max, nt_max, max_ghosts)
+        with torch.cuda.device(self.device):
+            self._check(lib().ibm_bind_workspace(self._h, C.c_void_p(self._ws_ptr), nbytes, nv_max, nt_max, max_ghosts,
+                                                 self.prec, self._s()))
+        return nbytes
+
+    def set_geometry(self, verts, tris, max_ghosts=None):
+        self.verts = np.ascontiguousarray(verts, dtype=np.float64)
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32)
+        nv, nt = len(self.verts), len(self.tris)
+        if max_ghosts is None:
+            max_ghosts = estimate_max_ghosts(self.xf, self.yf, self.zf, self.verts, self.tris)
+        if self.ws is None or self._caps[0] < nv or self._caps[1] < nt or self._caps[2] < max_ghosts:
+            self.bind(nv, nt, max_ghosts)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_set_geometry(self._h, _dp(self.verts), nv, C.c_void_p(self.tris.ctypes.data), nt,
+                                               self._s()))
+
+    def classify(self):
+        counts = np.zeros(3, dtype=np.int64)
+        with self.torch.cuda.device(self.device):
+            code = lib().ibm_classify(self._h, self._s(), C.c_void_p(counts.ctypes.data))
+            if code == IBM_E_NOMEM and counts[1] > self._caps[2]:
+                # more ghost cells than estimated: rebind with the exact count and redo
+                self.bind(self._caps[0], self._caps[1], int(counts[1]) + 1024)
+                self._check(lib().ibm_set_geometry(self._h, _dp(self.verts), len(self.verts),
+                                                   C.c_void_p(self.tris.ctypes.data), len(self.tris), self._s()))
+                code = lib().ibm_classify(self._h, self._s(), C.c_void_p(counts.ctypes.data))
+            self._check(code)
+        return counts
+
+    def build_ghost_stencils(self):
+        n = np.zeros(1, dtype=np.int64)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_build_ghost_stencils(self._h, self._s(), C.c_void_p(n.ctypes.data)))
+        self.ng = int(n[0])
+        return self.ng
+
+    def setup(self, verts, tris):
+        self.set_geometry(verts, tris)
+        counts = self.classify()
+        self.build_ghost_stencils()
+        return counts
+
+    def ghosts(self):
+        ng = self.ng
+        d = dict(cell=np.empty(ng, np.int32), bi=np.empty((ng, 3)), n=np.empty((ng, 3)), ip=np.empty((ng, 3)),
+                 stencil=np.empty((ng, 8), np.int32), beta=np.empty((ng, 8)), flags=np.empty(ng, np.int32))
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_get_ghosts(self._h, self._s(), *[C.c_void_p(d[k].ctypes.data) for k in
+                                                                    ("cell", "bi", "n", "ip", "stencil", "beta", "flags")]))
+        return d
+
+    def set_neumann_data(self, dpdn=None):
+        arr = None if dpdn is None else np.ascontiguousarray(dpdn, dtype=np.float64)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_set_neumann_data(self._h, None if arr is None else C.c_void_p(arr.ctypes.data),
+                                                   self._s()))
+
+    def cell_types(self):
+        t = self.torch.empty(self.shape, dtype=self.torch.uint8, device=self.device)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_get_cell_types(self._h, _tptr(t), self._s()))
+        return t
+
+    def levels(self):
+        n = C.c_int()
+        dims = np.zeros(3 * 32, dtype=np.int32)
+        self._check(lib().ibm_get_levels(self._h, C.byref(n), C.c_void_p(dims.ctypes.data)))
+        return [tuple(int(x) for x in dims[3 * l:3 * l + 3]) for l in range(n.value)]
+
+    # -- solve ---------------------------------------------------------------------------
+    def _field(self, a, name):
+        torch = self.torch
+        if not (isinstance(a, torch.Tensor) and a.dtype == torch.float64 and a.is_contiguous()
+                and a.device == self.device):
+            raise TypeError("%s must be a contiguous float64 tensor on %s" % (name, self.device))
+        return a
+
+    def poisson_solve(self, rhs, p=None, **kw):
+        torch = self.torch
+        self._field(rhs, "rhs")
+        if tuple(rhs.shape) != self.shape:
+            raise ValueError("rhs shape %s != %s" % (tuple(rhs.shape), self.shape))
+        if p is None:
+            p = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._field(p, "p")
+        o = make_opts(**kw)
+        st = SolveStats()
+        with torch.cuda.device(self.device):
+            code = self._check(lib().ibm_poisson_solve(self._h, _tptr(rhs), _tptr(p), C.byref(o), C.byref(st),
+                                                       self._s()))
+        return p, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+
+    def project(self, u, v, w, dt=1.0, p=None, **kw):
+        torch = self.torch
+        for a, nm, shp in ((u, "u", (self.nz, self.ny, self.nx + 1)), (v, "v", (self.nz, self.ny + 1, self.nx)),
+                           (w, "w", (self.nz + 1, self.ny, self.nx))):
+            self._field(a, nm)
+            if tuple(a.shape) != shp:
+                raise ValueError("%s shape %s != %s" % (nm, tuple(a.shape), shp))
+        if p is None:
+            p = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._field(p, "p")
+        o = make_opts(**kw)
+        st = SolveStats()
+        with torch.cuda.device(self.device):
+            code = self._check(lib().ibm_project(self._h, _tptr(u), _tptr(v), _tptr(w), float(dt), _tptr(p), C.byref(o),
+                                                 C.byref(st), self._s()))
+        return p, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+
+    # non-blocking step API (serving)
+    def solve_begin(self, rhs, p, **kw):
+        self._field(rhs, "rhs")
+        self._field(p, "p")
+        self._opts = make_opts(**kw)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_solve_begin(self._h, _tptr(rhs), _tptr(p), C.byref(self._opts), self._s()))
+
+    def solve_step(self, n=1):
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_solve_step(self._h, n))
+
+    def solve_poll(self):
+        done = C.c_int()
+        st = SolveStats()
+        code = self._check(lib().ibm_solve_poll(self._h, C.byref(done), C.byref(st)))
+        return done.value, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+
+    # smoother timing
+    def set_profiling(self, on=True):
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_set_profiling(self._h, int(bool(on))))
+
+    def profile(self):
+        vals = np.zeros(2, dtype=np.float64)
+        cnts = np.zeros(2, dtype=np.int64)
+        self._check(lib().ibm_get_profile(self._h, C.c_void_p(vals.ctypes.data), C.c_void_p(cnts.ctypes.data),
+                                          C.c_void_p(vals.ctypes.data + 8), C.c_void_p(cnts.ctypes.data + 8)))
+        return dict(ms_fp64=float(vals[0]), n_fp64=int(cnts[0]), ms_fp32=float(vals[1]), n_fp32=int(cnts[1]))
+
+    # kernel-level hooks
+    def debug_sweep(self, p, rhs, lam=0.0, n=1, refresh=False):
+        self._field(p, "p")
+        self._field(rhs, "rhs")
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_debug_sweep(self._h, _tptr(p), _tptr(rhs), float(lam), int(n), int(refresh),
+                                              self._s()))
+        return p
+
+    def debug_apply(self, p):
+        out = self.torch.empty_like(p)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_debug_apply(self._h, _tptr(self._field(p, "p")), _tptr(out), self._s()))
+        return out
+
+
+def grid_from_workload(wl, precision="fp64", device="cuda:0", stream=None):
+    g = Grid(wl.xf, wl.yf, wl.zf, precision=precision, device=device, stream=stream)
+    counts = g.setup(wl.verts, wl.tris)
+    return g, counts
+
+
+def upload_velocity(wl, device="cuda:0"):
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in wl.velocity())

@@ -1,0 +1,81 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function include/ibm.h
+declares, and its host-only entry points validate their arguments."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2505_17287_amd import ibm
+
+
+def test_library_exports_every_declared_symbol():
+    L = ibm.lib()
+    names = ibm.declared_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _create(nx, ny, nz, xf=None, yf=None, zf=None):
+    xf = np.linspace(0, 1, nx + 1) if xf is None else xf
+    yf = np.linspace(0, 1, ny + 1) if yf is None else yf
+    zf = np.linspace(0, 1, nz + 1) if zf is None else zf
+    h = C.c_void_p()
+    code = ibm.lib().ibm_create_grid(nx, ny, nz, ibm._dp(np.ascontiguousarray(xf, float)),
+                                     ibm._dp(np.ascontiguousarray(yf, float)), ibm._dp(np.ascontiguousarray(zf, float)),
+                                     C.byref(h))
+    return code, h
+
+
+def test_create_grid_validates_arguments():
+    L = ibm.lib()
+    code, h = _create(8, 8, 8)
+    assert code == ibm.IBM_OK and h.value
+    L.ibm_destroy_grid(h)
+    assert _create(1, 8, 8)[0] == ibm.IBM_E_ARG
+    bad = np.linspace(0, 1, 9)
+    bad[3] = bad[2]
+    assert _create(8, 8, 8, xf=bad)[0] == ibm.IBM_E_ARG
+    nan = np.linspace(0, 1, 9)
+    nan[5] = np.nan
+    assert _create(8, 8, 8, zf=nan)[0] == ibm.IBM_E_ARG
+    assert b"strictly increasing" in L.ibm_last_error(None)
+
+
+def test_workspace_bound_covers_every_plan():
+    """The handle-free size is an upper bound of the exact size for stretched grids."""
+    from paper_2505_17287_amd import inputs as I
+    L = ibm.lib()
+    for wl in (I.wing(64, 32, 32), I.multibody(48, n_bodies=1, level=1), I.cylinder2d(64)):
+        nx, ny, nz = wl.shape
+        code, h = _create(nx, ny, nz, wl.xf, wl.yf, wl.zf)
+        assert code == 0
+        for prec in (ibm.IBM_FP64, ibm.IBM_MIXED):
+            exact = L.ibm_grid_workspace_bytes(h, 1000, 2000, 5000, prec)
+            bound = L.ibm_workspace_bytes(nx, ny, nz, 1000, 2000, 5000, prec)
+            assert 0 < exact <= bound
+        L.ibm_destroy_grid(h)
+
+
+def test_levels_follow_semicoarsening_rule():
+    """Level plan of the library equals the oracle's (same rule, independent code)."""
+    from oracle import OracleProblem
+    from paper_2505_17287_amd import inputs as I
+    L = ibm.lib()
+    for wl in (I.wing(64, 32, 32), I.multibody(48, n_bodies=1, level=1), I.cylinder2d(64)):
+        nx, ny, nz = wl.shape
+        code, h = _create(nx, ny, nz, wl.xf, wl.yf, wl.zf)
+        n = C.c_int()
+        dims = np.zeros(96, np.int32)
+        assert L.ibm_get_levels(h, C.byref(n), C.c_void_p(dims.ctypes.data)) == 0
+        P = OracleProblem(wl.xf, wl.yf, wl.zf)
+        P.classify()
+        ref = [lv["dims"] for lv in P.levels()]
+        got = [tuple(int(x) for x in dims[3 * l:3 * l + 3]) for l in range(n.value)]
+        assert got == ref
+        L.ibm_destroy_grid(h)
+
+
+def test_options_defaults():
+    o = ibm.make_opts()
+    assert o.rel_tol == 1e-10 and o.max_cycles == 200 and (o.nu1, o.nu2, o.coarsest_sweeps) == (2, 2, 64)
