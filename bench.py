@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "vcycle"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -90,19 +91,20 @@ def main():
         u.copy_(u0)
         v.copy_(v0)
         w.copy_(w0)
-        _, st = g.project(u, v, w, dt=1.0, p=p, rel_tol=1e-10, precision=args.precision)
+        _, st = g.project(u, v, w, dt=1.0, p=p, rel_tol=1e-10, precision=args.precision, method=args.method)
         return counts, ng, st
 
     for q in range(args.warmup):
         counts, ng, st = step()
-        log("warmup", q, "cycles", st.cycles, "rel", st.rel_residual, "status", st.status)
+        log("warmup", q, "steps", st.cycles, "vcycles", st.vcycles, "rel", st.rel_residual, "status", st.status)
     torch.cuda.synchronize()
     g.set_profiling(True)
     t0 = time.perf_counter()
-    cyc = []
+    cyc, vcyc = [], []
     for q in range(args.steps):
         counts, ng, st = step()
         cyc.append(st.cycles)
+        vcyc.append(st.vcycles)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = g.profile()
@@ -137,13 +139,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": wl.ncells, "triangles": int(len(wl.tris)),
                    "fluid_ghost_dead": [int(x) for x in counts], "ghosts": int(ng),
-                   "cycles": int(np.median(cyc)), "rel_tol": 1e-10, "precision": args.precision,
+                   "method": args.method, "outer_steps": int(np.median(cyc)), "vcycles": int(np.median(vcyc)),
+                   "rel_tol": 1e-10, "precision": args.precision,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, int(np.median(cyc)))
+        out["cpu_baseline"] = cpu_baseline(wl, int(np.median(vcyc)))
     print(json.dumps(out), flush=True)
 
 

@@ -53,8 +53,18 @@ typedef enum {
 
 typedef enum { IBM_FP64 = 0, IBM_MIXED = 1 } ibm_precision;
 
+/* Outer iteration of the pressure solve.
+   IBM_VCYCLE  : repeated V-cycles (stationary multigrid iteration).
+   IBM_BICGSTAB: BiCGStab (the paper's pressure solver family, Section 2.1) right-
+                 preconditioned by one V-cycle per preconditioner application.  Ghost rows
+                 enter the Krylov operator scaled by the local stencil diagonal, and the
+                 fluid part of every residual is projected to zero volume-weighted mean (the
+                 uniform source shift lambda).  Both methods converge to the same solution. */
+typedef enum { IBM_VCYCLE = 0, IBM_BICGSTAB = 1 } ibm_method;
+
 /* Solver options.  Defaults (ibm_default_opts): rel_tol 1e-10, max_cycles 200, V(2,2),
-   64 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested. */
+   64 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested,
+   BiCGStab outer iteration. */
 typedef struct {
     double rel_tol;          /* stop when ||r'||_2 <= rel_tol * ||f - Vmean(f)||_2 (fluid rows) */
     int max_cycles;          /* V-cycles (FP64) or refinement steps (mixed) */
@@ -63,15 +73,17 @@ typedef struct {
     ibm_precision precision; /* IBM_MIXED: FP32 V-cycle inside FP64 iterative refinement */
     int use_initial_guess;   /* 1: start from the p passed in */
     int fixed_cycles;        /* > 0: run exactly this many cycles, no convergence test */
+    int method;              /* IBM_VCYCLE or IBM_BICGSTAB (default) */
 } ibm_solve_opts;
 
 typedef struct {
-    int cycles;                /* V-cycles / refinement steps performed */
+    int cycles;                /* outer iterations: V-cycles, refinement steps or BiCGStab steps */
     double rel_residual;       /* ||r'||_2 / ||f'||_2 after the last cycle */
     double ghost_residual_max; /* reserved: max ghost-equation residual (0 if not computed) */
     double lambda;             /* uniform source shift making the Neumann system consistent */
     double div_max;            /* projection only: max |D u| over fluid cells after correction */
     double t_setup, t_solve, t_correct; /* seconds (host wall clock around the enqueue+sync) */
+    int vcycles;               /* V-cycles applied (BiCGStab: 2 per step) */
 } ibm_solve_stats;
 
 /* Fill `o` with the defaults listed above. */

@@ -62,6 +62,7 @@ typedef struct {
 typedef struct {
     double rel_tol;
     int max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles;
+    int method; /* 0: V-cycle iteration, 1: BiCGStab preconditioned by one V-cycle */
 } orc_opts;
 
 typedef struct {
@@ -790,8 +791,8 @@ static double fluid_neighbour_mean(const orc_problem *P, const double *p, int64_
 }
 
 /* Ghost values from their implicit equations, all from one snapshot of p (Jacobi over
-   the ghosts):  p_g = sum_{m != g} beta_m p_m + h_g. */
-static void ghost_refresh(const orc_problem *P, double *p) {
+   the ghosts):  p_g = sum_{m != g} beta_m p_m + h_g, with right-hand sides gh. */
+static void ghost_refresh_h(const orc_problem *P, double *p, const double *gh) {
     int64_t ng = P->nghost;
     if (ng == 0) return;
     double *nv = dalloc(ng);
@@ -802,11 +803,13 @@ static void ghost_refresh(const orc_problem *P, double *p) {
         const double *beta = P->gbeta + 8 * g;
         double s = 0.0;
         for (int m = 0; m < 8; ++m) if (st[m] >= 0) s = s + beta[m] * p[st[m]];
-        nv[g] = s + P->gh[g];
+        nv[g] = s + gh[g];
     }
     for (int64_t g = 0; g < ng; ++g) p[P->gcell[g]] = nv[g];
     free(nv);
 }
+
+static void ghost_refresh(const orc_problem *P, double *p) { ghost_refresh_h(P, p, P->gh); }
 
 static double ghost_residual_max(const orc_problem *P, const double *p) {
     double mx = 0.0;
@@ -1142,9 +1145,10 @@ static void residual0_integrated(const orc_problem *P, const double *p, const do
             }
 }
 
-static void vcycle(orc_problem *P, double *p, const double *f, double lambda, const orc_opts *o) {
+/* One V(nu1,nu2) cycle on level 0 for S p = f - lambda with ghost right-hand sides gh. */
+static void vcycle_h(orc_problem *P, double *p, const double *f, double lambda, const double *gh, const orc_opts *o) {
     level_t *L0 = &P->lev[0];
-    for (int s = 0; s < o->nu1; ++s) { sweep0(P, p, f, lambda, 0); ghost_refresh(P, p); }
+    for (int s = 0; s < o->nu1; ++s) { sweep0(P, p, f, lambda, 0); ghost_refresh_h(P, p, gh); }
     if (P->nlev > 1) {
         residual0_integrated(P, p, f, lambda, L0->r);
         restrict_to(L0, &P->lev[1], L0->r);
@@ -1166,9 +1170,13 @@ static void vcycle(orc_problem *P, double *p, const double *f, double lambda, co
             for (int s = 0; s < o->nu2; ++s) sweepC(&P->lev[l]);
         }
         prolong_add(L0, &P->lev[1], p);
-        ghost_refresh(P, p);
+        ghost_refresh_h(P, p, gh);
     }
-    for (int s = 0; s < o->nu2; ++s) { sweep0(P, p, f, lambda, 0); ghost_refresh(P, p); }
+    for (int s = 0; s < o->nu2; ++s) { sweep0(P, p, f, lambda, 0); ghost_refresh_h(P, p, gh); }
+}
+
+static void vcycle(orc_problem *P, double *p, const double *f, double lambda, const orc_opts *o) {
+    vcycle_h(P, p, f, lambda, P->gh, o);
 }
 
 /* r = f - S p on fluid rows; lambda = sum V r / sum V; returns || r - lambda ||_2 */
@@ -1197,6 +1205,153 @@ static double residual_norm(const orc_problem *P, const double *p, const double 
         if (P->type[id] == T_FLUID) { double r = rbuf[id] - lambda; s2 += r * r; }
     *lambda_out = lambda;
     return sqrt(s2);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Krylov acceleration: BiCGStab (van der Vorst 1992; the paper's pressure solver family, */
+/* Section 2.1) right-preconditioned by one V-cycle.                                     */
+/*   unknowns : p on fluid and ghost cells (dead cells stay 0)                            */
+/*   operator : fluid rows (S p)_c; ghost rows s_g (p_g - sum_{m != g} beta_m p_m), with  */
+/*              s_g the diagonal of the flux stencil at the ghost cell, so both kinds of  */
+/*              rows carry the same scale                                                 */
+/*   rhs      : f on fluid rows, s_g h_g on ghost rows                                    */
+/* The fluid part of every residual and operator image is projected to zero volume-       */
+/* weighted mean: that removed mean is the lambda of the V-cycle iteration, so both        */
+/* methods converge to the same discrete solution.                                         */
+/* ------------------------------------------------------------------------------------ */
+
+static double ghost_scale(const orc_problem *P, int64_t id) {
+    int i = (int)(id % P->nx), j = (int)((id / P->nx) % P->ny), k = (int)(id / ((int64_t)P->nx * P->ny));
+    double d = P->axm[i] + P->axp[i];
+    d = d + P->aym[j];
+    d = d + P->ayp[j];
+    d = d + P->azm[k];
+    d = d + P->azp[k];
+    return d;
+}
+
+static void apply_full(const orc_problem *P, const double *y, double *out) {
+    orc_apply_S(P, y, out);
+#pragma omp parallel for
+    for (int64_t g = 0; g < P->nghost; ++g) {
+        int64_t id = P->gcell[g];
+        double target;
+        if (P->gflags[g] & GF_DEGENERATE) target = fluid_neighbour_mean(P, y, id);
+        else {
+            const int32_t *st = P->gst + 8 * g;
+            const double *beta = P->gbeta + 8 * g;
+            double s = 0.0;
+            for (int m = 0; m < 8; ++m) if (st[m] >= 0) s = s + beta[m] * y[st[m]];
+            target = s;
+        }
+        out[id] = ghost_scale(P, id) * (y[id] - target);
+    }
+}
+
+/* remove the volume-weighted mean of the fluid part; returns that mean */
+static double project_fluid_mean(const orc_problem *P, double *v) {
+    const level_t *L0 = &P->lev[0];
+    double s = 0.0;
+    for (int k = 0; k < P->nz; ++k)
+        for (int j = 0; j < P->ny; ++j)
+            for (int i = 0; i < P->nx; ++i) {
+                int64_t id = IDX(P, i, j, k);
+                if (P->type[id] == T_FLUID) s += lvol(L0, i, j, k) * v[id];
+            }
+    double m = s / P->vol_fluid;
+    for (int64_t id = 0; id < P->ncell; ++id) if (P->type[id] == T_FLUID) v[id] -= m;
+    return m;
+}
+
+static double dot_active(const orc_problem *P, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t id = 0; id < P->ncell; ++id) if (P->type[id] != T_DEAD) s += a[id] * b[id];
+    return s;
+}
+
+static double norm_fluid(const orc_problem *P, const double *a) {
+    double s = 0.0;
+    for (int64_t id = 0; id < P->ncell; ++id) if (P->type[id] == T_FLUID) s += a[id] * a[id];
+    return sqrt(s);
+}
+
+/* e = M r: one V-cycle for A e = r from e = 0 (lambda 0, ghost right-hand sides r_g/s_g) */
+static void precondition(orc_problem *P, const double *r, double *e, double *gh, const orc_opts *o) {
+    for (int64_t g = 0; g < P->nghost; ++g) {
+        int64_t id = P->gcell[g];
+        gh[g] = r[id] / ghost_scale(P, id);
+    }
+    memset(e, 0, sizeof(double) * (size_t)P->ncell);
+    ghost_refresh_h(P, e, gh);
+    vcycle_h(P, e, r, 0.0, gh, o);
+}
+
+/* b - A x, projected */
+static void true_residual(orc_problem *P, const double *f, const double *x, double *r) {
+    apply_full(P, x, r);
+    for (int64_t id = 0; id < P->ncell; ++id) {
+        if (P->type[id] == T_FLUID) r[id] = f[id] - r[id];
+        else if (P->type[id] == T_DEAD) r[id] = 0.0;
+    }
+    for (int64_t g = 0; g < P->nghost; ++g) {
+        int64_t id = P->gcell[g];
+        r[id] = ghost_scale(P, id) * P->gh[g] - r[id];
+    }
+    project_fluid_mean(P, r);
+}
+
+/* returns the iteration count; *rel_out = ||r_fluid|| / ref of the true residual */
+static int bicgstab(orc_problem *P, const double *f, double *x, const orc_opts *o, double ref, double *hist,
+                    int hist_len, double *rel_out, int *status) {
+    const int64_t n = P->ncell;
+    double *r = dalloc(n), *rh = dalloc(n), *pd = dalloc(n), *v = dalloc(n), *sv = dalloc(n), *t = dalloc(n);
+    double *y = dalloc(n), *z = dalloc(n), *gh = dalloc(P->nghost);
+    true_residual(P, f, x, r);
+    memcpy(rh, r, sizeof(double) * n);
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    const int nit = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
+    double rel = norm_fluid(P, r) / ref;
+    int it;
+    *status = ORC_OK;
+    for (it = 1; it <= nit; ++it) {
+        double rho = dot_active(P, rh, r);
+        double beta = (it == 1) ? 0.0 : (rho / rho_old) * (alpha / omega);
+        if (rho == 0.0 || !isfinite(beta)) { /* breakdown: restart the shadow residual */
+            memcpy(rh, r, sizeof(double) * n);
+            rho = dot_active(P, rh, r);
+            beta = 0.0;
+        }
+        for (int64_t id = 0; id < n; ++id) pd[id] = r[id] + beta * (pd[id] - omega * v[id]);
+        precondition(P, pd, y, gh, o);
+        apply_full(P, y, v);
+        project_fluid_mean(P, v);
+        alpha = rho / dot_active(P, rh, v);
+        for (int64_t id = 0; id < n; ++id) sv[id] = r[id] - alpha * v[id];
+        precondition(P, sv, z, gh, o);
+        apply_full(P, z, t);
+        project_fluid_mean(P, t);
+        double tt = dot_active(P, t, t);
+        omega = tt > 0.0 ? dot_active(P, t, sv) / tt : 0.0;
+        for (int64_t id = 0; id < n; ++id) {
+            x[id] += alpha * y[id] + omega * z[id];
+            r[id] = sv[id] - omega * t[id];
+        }
+        rho_old = rho;
+        rel = norm_fluid(P, r) / ref;
+        if (hist && it - 1 < hist_len) hist[it - 1] = rel;
+        if (!isfinite(rel)) { *status = ORC_E_NUMERIC; break; }
+        if (o->fixed_cycles <= 0 && rel <= o->rel_tol) {
+            true_residual(P, f, x, r);  /* confirm with the true residual */
+            rel = norm_fluid(P, r) / ref;
+            if (rel <= o->rel_tol) break;
+            memcpy(rh, r, sizeof(double) * n);
+        }
+    }
+    if (it > nit) it = nit;
+    if (*status == ORC_OK && o->fixed_cycles <= 0 && rel > o->rel_tol) *status = ORC_NOT_CONVERGED;
+    free(r); free(rh); free(pd); free(v); free(sv); free(t); free(y); free(z); free(gh);
+    *rel_out = rel;
+    return it;
 }
 
 /* Solve S p = f - lambda (fluid rows) with the ghost equations, V-mean of p over the fluid
@@ -1232,7 +1387,10 @@ int orc_solve(orc_problem *P, const double *f, double *p, const orc_opts *o, orc
     int status = ORC_OK, cyc = 0;
     double rel = ref > 0.0 ? r0 / ref : 0.0;
     st->first_norm = r0;
-    if (ref > 0.0) {
+    if (ref > 0.0 && o->method == 1) {
+        cyc = bicgstab(P, f, p, o, ref, hist, hist_len, &rel, &status);
+        residual_norm(P, p, f, &lambda, rbuf);
+    } else if (ref > 0.0) {
         int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
         for (cyc = 1; cyc <= ncyc; ++cyc) {
             vcycle(P, p, f, lambda, o);

@@ -28,12 +28,14 @@ def build_oracle(force: bool = False) -> str:
 
 class OracleOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("coarsest_sweeps", C.c_int), ("use_initial_guess", C.c_int), ("fixed_cycles", C.c_int)]
+                ("coarsest_sweeps", C.c_int), ("use_initial_guess", C.c_int), ("fixed_cycles", C.c_int),
+                ("method", C.c_int)]
 
     @staticmethod
     def make(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, use_initial_guess=0,
-             fixed_cycles=0):
-        return OracleOpts(rel_tol, max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles)
+             fixed_cycles=0, method="mg"):
+        m = {"mg": 0, "vcycle": 0, "bicgstab": 1}[method] if isinstance(method, str) else int(method)
+        return OracleOpts(rel_tol, max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles, m)
 
 
 class _Stats(C.Structure):

@@ -162,6 +162,9 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     G->g_dl = P.take<double>(gm);
     G->g_h = P.take<double>(gm);
     G->g_data = P.take<double>(gm);
+    G->g_scale = P.take<double>(gm);
+    G->g_rhs = P.take<double>(gm);
+    for (int q = 0; q < 10; ++q) G->kv[q] = P.take<double>(N);
     for (int l = 0; l < nlev; ++l) {
         LevelHost &L = lev[l];
         const int64_t NC = L.ncell();
@@ -207,6 +210,7 @@ void ibm_default_opts(ibm_solve_opts *o) {
     o->precision = IBM_FP64;
     o->use_initial_guess = 0;
     o->fixed_cycles = 0;
+    o->method = IBM_BICGSTAB;
 }
 
 ibm_status ibm_create_grid(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
@@ -418,6 +422,7 @@ ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_
     if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_data, 0, sizeof(double) * g->ng, s), "memset neumann");
     HIP_TRY(launch_ghost_h(g, s), "ghost rhs");
     HIP_TRY(launch_hierarchy(g, s), "hierarchy");
+    HIP_TRY(krylov_setup(g, s), "krylov setup");
     int64_t ndeg = 0;
     HIP_TRY(hipMemcpyAsync(&ndeg, g->counters + 5, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read counters");
     HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s), "read scalars");
@@ -503,6 +508,7 @@ static ibm_status check_opts(ibm_grid *g, const ibm_solve_opts *o) {
     if (o->precision == IBM_MIXED && g->prec != IBM_MIXED)
         return fail(g, IBM_E_STATE, "mixed precision needs a workspace bound with IBM_MIXED");
     if (o->precision != IBM_FP64 && o->precision != IBM_MIXED) return fail(g, IBM_E_ARG, "unknown precision");
+    if (o->method != IBM_VCYCLE && o->method != IBM_BICGSTAB) return fail(g, IBM_E_ARG, "unknown method");
     return IBM_OK;
 }
 
@@ -512,12 +518,22 @@ static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const
     if ((e = hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s)) != hipSuccess) return e;
     if ((e = ref_norm_pass(g, rhs, s)) != hipSuccess) return e;
     if ((e = init_solution(g, p, g->p2, o->use_initial_guess, s)) != hipSuccess) return e;
-    if ((e = norm_pass(g, g->p2, rhs, s, o->precision == IBM_MIXED, true)) != hipSuccess) return e;
+    if (o->method == IBM_BICGSTAB) {
+        if ((e = hipMemsetAsync(g->kv[2], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(g->kv[3], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
+        if ((e = krylov_residual(g, rhs, g->p2, s)) != hipSuccess) return e;
+    } else {
+        if ((e = norm_pass(g, g->p2, rhs, s, o->precision == IBM_MIXED, true)) != hipSuccess) return e;
+    }
     return hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s);
 }
 
 static hipError_t enqueue_cycle(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, int *cur,
                                 hipStream_t s) {
+    if (o->method == IBM_BICGSTAB) {
+        *cur = 1;  // the Krylov iterate lives in the second buffer
+        return krylov_step(g, g->p2, o, s);
+    }
     double *bufs[2] = {p, g->p2};
     hipError_t e;
     if (o->precision == IBM_MIXED) e = vcycle_mixed(g, bufs, cur, rhs, s, o);
@@ -539,12 +555,94 @@ static void prof_collect(ibm_grid *g) {
     P.used = 0;
 }
 
+// BiCGStab driver: x lives in the second pressure buffer, the gauged result goes to p
+static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o,
+                               ibm_solve_stats *st, hipStream_t s) {
+    const double t0 = now_s();
+    double *x = g->p2;
+    HIP_TRY(hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s), "memset scalars");
+    HIP_TRY(ref_norm_pass(g, rhs, s), "reference norm");
+    HIP_TRY(init_solution(g, p, x, o->use_initial_guess, s), "init");
+    HIP_TRY(hipMemsetAsync(g->kv[2], 0, sizeof(double) * g->N, s), "memset");
+    HIP_TRY(hipMemsetAsync(g->kv[3], 0, sizeof(double) * g->N, s), "memset");
+    HIP_TRY(krylov_residual(g, rhs, x, s), "residual");
+    Scalars *hs = g->sc_host;
+    HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (hs->bad) return fail(g, IBM_E_NUMERIC, "non-finite right-hand side or initial guess");
+    const double r0 = hs->norm;
+    if (!(hs->ref > 0.0)) {
+        double ref = r0;
+        HIP_TRY(hipMemcpyAsync(&g->sc->ref, &ref, sizeof(double), hipMemcpyHostToDevice, s), "set ref");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        hs->ref = ref;
+    }
+    ibm_status status = IBM_OK;
+    int it = 0;
+    double rel = hs->ref > 0.0 ? r0 / hs->ref : 0.0;
+    bool have_true = true;  // the scalars describe the true residual of x
+    if (hs->ref > 0.0 && (o->fixed_cycles > 0 || rel > o->rel_tol)) {
+        const int nit = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
+        for (it = 1; it <= nit; ++it) {
+            HIP_TRY(krylov_step(g, x, o, s), "bicgstab step");
+            HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
+            HIP_TRY(hipStreamSynchronize(s), "step sync");
+            if (g->prof.on) prof_collect(g);
+            have_true = false;
+            rel = hs->rel;
+            if (hs->bad || !std::isfinite(hs->norm) || hs->norm > 1e6 * std::max(r0, hs->ref)) {
+                status = IBM_E_NUMERIC;
+                break;
+            }
+            if (o->fixed_cycles > 0) continue;
+            if (rel <= o->rel_tol) {
+                // confirm with the true residual (this also restarts the recurrences)
+                HIP_TRY(krylov_residual(g, rhs, x, s), "true residual");
+                HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
+                HIP_TRY(hipStreamSynchronize(s), "sync");
+                have_true = true;
+                rel = hs->rel;
+                if (rel <= o->rel_tol) break;
+            } else if (hs->rho == 0.0) {
+                HIP_TRY(krylov_restart(g, s), "restart");
+            }
+        }
+        if (it > nit) it = nit;
+        if (status == IBM_OK && o->fixed_cycles <= 0 && rel > o->rel_tol) status = IBM_NOT_CONVERGED;
+    }
+    if (!have_true && status != IBM_E_NUMERIC) {
+        HIP_TRY(krylov_residual(g, rhs, x, s), "final residual");
+        HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        rel = hs->rel;
+    }
+    HIP_TRY(gauge_pass(g, x, p, s), "gauge");
+    HIP_TRY(hipStreamSynchronize(s), "gauge sync");
+    if (st) {
+        st->cycles = it;
+        st->vcycles = 2 * it;
+        st->rel_residual = rel;
+        st->ghost_residual_max = 0.0;
+        st->lambda = hs->lambda;
+        st->div_max = 0.0;
+        st->t_setup = 0.0;
+        st->t_solve = now_s() - t0;
+        st->t_correct = 0.0;
+    }
+    if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite or diverging residual");
+    return status;
+}
+
 static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, ibm_solve_stats *st,
                              hipStream_t s) {
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "solve before ibm_build_ghost_stencils");
     ibm_status cs = check_opts(g, o);
     if (cs != IBM_OK) return cs;
     if (!rhs || !p) return fail(g, IBM_E_ARG, "NULL rhs or p");
+    if (o->method == IBM_BICGSTAB) {
+        HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+        return solve_krylov(g, rhs, p, o, st, s);
+    }
     double t0 = now_s();
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     HIP_TRY(enqueue_begin(g, rhs, p, o, s), "solve begin");
@@ -588,6 +686,7 @@ static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ib
     HIP_TRY(hipStreamSynchronize(s), "gauge sync");
     if (st) {
         st->cycles = cycles;
+        st->vcycles = cycles;
         st->rel_residual = rel;
         st->ghost_residual_max = 0.0;
         st->lambda = hs->lambda;
@@ -658,6 +757,7 @@ ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_
     S.cur = 1;
     S.t0 = now_s();
     S.finishing = false;
+    S.phase = 0;
     if (!S.ev) HIP_TRY(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming), "event");
     HIP_TRY(enqueue_begin(g, rhs, p, o, S.stream), "begin");
     HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
@@ -707,6 +807,7 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
             *done = 1;
             if (st) {
                 st->cycles = S.cycles;
+                st->vcycles = (S.o.method == IBM_BICGSTAB) ? 2 * S.cycles : S.cycles;
                 st->rel_residual = hs->rel;
                 st->ghost_residual_max = 0.0;
                 st->lambda = hs->lambda;
@@ -736,10 +837,24 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
                 S.status = IBM_E_NUMERIC;
                 finish = true;
             } else if (S.o.fixed_cycles <= 0 && hs->rel <= S.o.rel_tol) {
+                if (S.o.method == IBM_BICGSTAB && S.phase == 0) {
+                    // confirm with the true residual before finishing (restarts the recurrences)
+                    HIP_TRY(krylov_residual(g, S.rhs, g->p2, S.stream), "true residual");
+                    HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream),
+                            "read");
+                    HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
+                    S.ev_pending = true;
+                    S.phase = 1;
+                    *done = 0;
+                    return IBM_OK;
+                }
                 finish = true;
             } else if (S.cycles >= ncyc) {
                 if (S.o.fixed_cycles <= 0) S.status = IBM_NOT_CONVERGED;
                 finish = true;
+            } else if (S.o.method == IBM_BICGSTAB) {
+                S.phase = 0;
+                if (hs->rho == 0.0) HIP_TRY(krylov_restart(g, S.stream), "restart");
             }
         }
         if (finish) {

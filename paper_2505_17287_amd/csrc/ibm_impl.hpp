@@ -85,6 +85,11 @@ struct Scalars {
     double div_max;
     int bad;            // non-finite seen
     int pad1;
+    // Krylov (BiCGStab) scalars
+    double rho, rho_old, alpha, omega, beta;
+    double mu_v;        // volume-weighted fluid mean removed from an operator image
+    double zero;        // constant 0 (shift of the preconditioner's right-hand side)
+    float zero32, pad2;
     double mu[MAX_LEVELS];
     double vol[MAX_LEVELS];   // summed volume of the active cells of each level
 };
@@ -128,6 +133,7 @@ struct SolveState {  // in-flight solve of the step API
     bool ev_pending = false;
     int cur = 0;                // which buffer holds the iterate (0 = user p, 1 = workspace)
     bool finishing = false;     // gauge enqueued, waiting for its event
+    int phase = 0;              // BiCGStab: 1 while a true-residual confirmation is in flight
     double t0 = 0.0;
 };
 
@@ -185,6 +191,10 @@ struct ibm_grid {
     uint8_t *g_mask = nullptr;
     double *g_bi = nullptr, *g_n = nullptr, *g_ip = nullptr, *g_beta = nullptr, *g_betag = nullptr;
     double *g_dl = nullptr, *g_h = nullptr, *g_data = nullptr;
+    double *g_scale = nullptr;             // diagonal of the flux stencil at each ghost cell
+    double *g_rhs = nullptr;               // ghost right-hand sides of a preconditioner call
+    // Krylov vectors (FP64, full grid)
+    double *kv[10] = {nullptr};
     // multigrid
     int nlev = 0;
     ibm::LevelHost lev[ibm::MAX_LEVELS];
@@ -243,5 +253,9 @@ hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const doub
                         hipStream_t s);
 hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s);
 hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipStream_t s);
+hipError_t krylov_setup(ibm_grid *g, hipStream_t s);
+hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s);
+hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s);
+hipError_t krylov_restart(ibm_grid *g, hipStream_t s);
 
 }  // namespace ibm

@@ -163,12 +163,12 @@ static hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T 
 // ghost refresh: p_g = sum_{m != g} beta_m p_m + h_g from one snapshot (Jacobi over ghosts)
 // fluid members are read from dst (already updated), ghost members from src_ghost (the
 // values before this pass); degenerate ghosts take the mean of their fluid 26-neighbours.
-// Weights are FP64; the FP32 error equation is homogeneous (h = 0).
+// Weights are FP64; the right-hand sides gh may be absent (homogeneous error equation).
 // =======================================================================================
 
 template <typename T>
 __global__ void k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T *dst, int nx, int ny, int nz,
-                                const uint8_t *__restrict__ type, int homogeneous) {
+                                const uint8_t *__restrict__ type, const double *__restrict__ gh) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G.ng) return;
     const int64_t cell = G.cell[g];
@@ -202,7 +202,7 @@ __global__ void k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T 
                 s = s + beta[m] * (double)pv;
             }
         }
-        v = homogeneous ? s : s + G.h[g];
+        v = gh ? s + gh[g] : s;
     }
     dst[cell] = (T)v;
 }
@@ -220,10 +220,10 @@ static GhostView ghost_view(ibm_grid *g) {
 }
 
 template <typename T>
-static hipError_t launch_refresh(ibm_grid *g, const T *src_ghost, T *dst, int homogeneous, hipStream_t s) {
+static hipError_t launch_refresh(ibm_grid *g, const T *src_ghost, T *dst, const double *gh, hipStream_t s) {
     if (g->ng == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ghost_refresh<T>, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, ghost_view(g),
-                       src_ghost, dst, g->nx, g->ny, g->nz, g->type, homogeneous);
+                       src_ghost, dst, g->nx, g->ny, g->nz, g->type, gh);
     return hipGetLastError();
 }
 
@@ -667,7 +667,7 @@ hipError_t sweep0_f64(ibm_grid *g, const double *pin, double *pout, const double
 }
 
 hipError_t refresh_f64(ibm_grid *g, const double *src_ghost, double *dst, hipStream_t s) {
-    return launch_refresh<double>(g, src_ghost, dst, 0, s);
+    return launch_refresh<double>(g, src_ghost, dst, g->g_h, s);
 }
 
 template <typename T>
@@ -706,7 +706,7 @@ struct FineOf<float> {
 // one V(nu1, nu2) cycle in precision T on level 0.
 // bufs[0..1]: the two level-0 buffers, *cur: index of the current iterate.
 // rhs: level-0 right-hand side; lam: device scalar shift of the right-hand side;
-// homogeneous: ghost equations without right-hand side (error equation).
+// gh: right-hand sides of the ghost equations (nullptr: homogeneous error equation).
 // level-0 sweep, bracketed by timing events when profiling is on
 template <typename T>
 static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *pout, const T *rhs, const T *lam,
@@ -725,14 +725,14 @@ static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *po
 }
 
 template <typename T>
-static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, int homogeneous,
+static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, const double *gh,
                               const ibm_solve_opts *o, hipStream_t s) {
     const Fine<T> F = FineOf<T>::get(g);
     hipError_t e;
     for (int q = 0; q < o->nu1; ++q) {
         T *pin = bufs[*cur], *pout = bufs[1 - *cur];
         if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
-        if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+        if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
         *cur = 1 - *cur;
     }
     if (g->nlev > 1) {
@@ -777,21 +777,21 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             T *pin = bufs[*cur], *pout = bufs[1 - *cur];
             hipLaunchKernelGGL(k_prolong0<T>, dim3(nblk(g->N)), dim3(256), 0, s, F, pin, pout, coarse_view<T>(g, 1),
                                prolong_tab(g, 0));
-            if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+            if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
             *cur = 1 - *cur;
         }
     }
     for (int q = 0; q < o->nu2; ++q) {
         T *pin = bufs[*cur], *pout = bufs[1 - *cur];
         if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
-        if ((e = launch_refresh<T>(g, pin, pout, homogeneous, s)) != hipSuccess) return e;
+        if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
         *cur = 1 - *cur;
     }
     return hipGetLastError();
 }
 
 hipError_t vcycle_f64(ibm_grid *g, double **bufs, int *cur, const double *f, hipStream_t s, const ibm_solve_opts *o) {
-    return vcycle_impl<double>(g, bufs, cur, f, &g->sc->lambda, 0, o, s);
+    return vcycle_impl<double>(g, bufs, cur, f, &g->sc->lambda, g->g_h, o, s);
 }
 
 // e32 := 0 (dead cells too), so the inner cycle starts from a zero correction
@@ -820,10 +820,10 @@ hipError_t vcycle_mixed(ibm_grid *g, double **bufs, int *cur, const double *f, h
     hipLaunchKernelGGL(k_zero32, dim3(nblk(g->N)), dim3(256), 0, s, g->e32a, g->e32b, g->N);
     float *eb[2] = {g->e32a, g->e32b};
     int ecur = 0;
-    if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->delta32, 1, o, s)) != hipSuccess) return e;
+    if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->delta32, nullptr, o, s)) != hipSuccess) return e;
     double *pin = bufs[*cur], *pout = bufs[1 - *cur];
     hipLaunchKernelGGL(k_add_correction, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->N, pin, eb[ecur], pout);
-    if ((e = launch_refresh<double>(g, pin, pout, 0, s)) != hipSuccess) return e;
+    if ((e = launch_refresh<double>(g, pin, pout, g->g_h, s)) != hipSuccess) return e;
     *cur = 1 - *cur;
     return hipGetLastError();
 }
@@ -868,7 +868,7 @@ __global__ void k_init(const uint8_t *__restrict__ type, int64_t N, double *p, d
 
 hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipStream_t s) {
     hipLaunchKernelGGL(k_init, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->N, p, p2, use_guess);
-    return launch_refresh<double>(g, p, p2, 0, s);
+    return launch_refresh<double>(g, p, p2, g->g_h, s);
 }
 
 // =======================================================================================
@@ -962,6 +962,350 @@ __global__ void k_max_finalize(const double *partials, int nb, Scalars *sc) {
 hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s) {
     hipLaunchKernelGGL(k_divmax, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), u, v, w, g->partials);
     hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(64), 0, s, g->partials, RED_BLOCKS, g->sc);
+    return hipGetLastError();
+}
+
+// =======================================================================================
+// BiCGStab (paper Section 2.1: the pressure solver family it uses), right-preconditioned by
+// one V-cycle, on the fluid + ghost unknowns:
+//   A y : fluid rows (S y)_c ; ghost rows s_g (y_g - sum_{m != g} beta_m y_m)
+//   b   : fluid rows f       ; ghost rows s_g h_g
+// s_g = diagonal of the flux stencil at the ghost cell (both row kinds on one scale).  The
+// fluid part of every residual and operator image is projected to zero volume-weighted
+// mean (the uniform source shift lambda of the Neumann problem).  All scalars stay on the
+// device; the host reads back one status block per iteration.
+// =======================================================================================
+
+enum KOp { K_MU = 0, K_ALPHA = 1, K_OMEGA = 2, K_RHO = 3, K_INIT = 4, K_RESTART = 5 };
+
+// ghost scale: the stencil diagonal, summed in the smoother's order
+__global__ void k_ghost_scale(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, const double *axm,
+                              const double *axp, const double *aym, const double *ayp, const double *azm,
+                              const double *azp, double *scale) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int64_t id = gcell[g];
+    const int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    double d = axm[i] + axp[i];
+    d = d + aym[j];
+    d = d + ayp[j];
+    d = d + azm[k];
+    d = d + azp[k];
+    scale[g] = d;
+}
+
+// fluid rows of A y (non-fluid entries 0) with partial sums of sum_fluid V (A y)
+__global__ void __launch_bounds__(NORM_NT) k_apply_fluid(Fine<double> F, const double *__restrict__ y,
+                                                         double *w, double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    double sv = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) {
+            w[id] = 0.0;
+            continue;
+        }
+        const int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        double num, diag;
+        fine_stencil(F, y, i, j, k, id, num, diag);
+        const double a = num - diag * y[id];
+        w[id] = a;
+        sv += ((F.wx[i] * F.wy[j]) * F.wz[k]) * a;
+    }
+    const double t = block_sum<NORM_NT>(sv, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// ghost rows of A y (mode 0) or of b - A y (mode 1: out = s_g h_g - A y)
+__global__ void k_apply_ghost(GhostView G, const double *__restrict__ y, double *out, const double *__restrict__ scale,
+                              int nx, int ny, int nz, const uint8_t *__restrict__ type, int mode) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G.ng) return;
+    const int64_t cell = G.cell[g];
+    double target;
+    if (G.flags[g] & GF_DEGENERATE) {
+        const int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((int64_t)nx * ny));
+        double s = 0.0;
+        int n = 0;
+        for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di, jj = j + dj, kk = k + dk;
+                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                    const int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
+                    if (type[q] == T_FLUID) {
+                        s += y[q];
+                        ++n;
+                    }
+                }
+        target = n ? s / n : 0.0;
+    } else {
+        const int32_t *st = G.st + 8 * g;
+        const double *beta = G.beta + 8 * g;
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (st[m] >= 0) s = s + beta[m] * y[st[m]];
+        target = s;
+    }
+    const double a = scale[g] * (y[cell] - target);
+    out[cell] = mode ? scale[g] * G.h[g] - a : a;
+}
+
+// r = f - (A x) on fluid rows (ghost rows written by k_apply_ghost mode 1), partial V-sums
+__global__ void __launch_bounds__(NORM_NT) k_resid_fluid(Fine<double> F, const double *__restrict__ f,
+                                                         const double *__restrict__ x, double *r, double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
+    double sv = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        if (F.type[id] != T_FLUID) {
+            r[id] = 0.0;
+            continue;
+        }
+        const int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        double num, diag;
+        fine_stencil(F, x, i, j, k, id, num, diag);
+        const double a = f[id] - (num - diag * x[id]);
+        r[id] = a;
+        sv += ((F.wx[i] * F.wy[j]) * F.wz[k]) * a;
+    }
+    const double t = block_sum<NORM_NT>(sv, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// projection of the fluid part (v -= mu_v) fused with the inner products that follow it:
+//   mode 0 (alpha): sum rh.v ;  mode 1 (omega): sum t.s, sum t.t ;
+//   mode 2 (init) : rh = v, sum v.v (all), sum v.v (fluid)
+__global__ void __launch_bounds__(NORM_NT) k_project(const uint8_t *__restrict__ type, int64_t N, double *v,
+                                                     const double *__restrict__ other, double *rh,
+                                                     const Scalars *sc, int mode, double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const double mu = sc->mu_v;
+    double a = 0.0, b = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        const uint8_t t = type[id];
+        if (t == T_DEAD) continue;
+        double x = v[id];
+        if (t == T_FLUID && mode != 3) {
+            x -= mu;
+            v[id] = x;
+        }
+        if (mode == 0) {
+            a += other[id] * x;
+        } else if (mode == 1) {
+            a += x * other[id];
+            b += x * x;
+        } else {
+            rh[id] = x;
+            a += x * x;
+            if (t == T_FLUID) b += x * x;
+        }
+    }
+    double s = block_sum<NORM_NT>(a, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x] = s;
+    s = block_sum<NORM_NT>(b, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = s;
+}
+
+__global__ void k_krylov_finalize(const double *partials, int nb, int stride, Scalars *sc, int op) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) {
+        a += partials[stride * q];
+        if (stride > 1) b += partials[stride * q + 1];
+    }
+    a = block_sum<256>(a, sh, threadIdx.x);
+    b = block_sum<256>(b, sh, threadIdx.x);
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case K_MU: sc->mu_v = a / sc->vol[0]; break;
+        case K_ALPHA: sc->alpha = (a != 0.0) ? sc->rho / a : 0.0; break;
+        case K_OMEGA: sc->omega = (b > 0.0) ? a / b : 0.0; break;
+        case K_RHO:
+        case K_INIT:
+        case K_RESTART: {
+            const double rho_new = a;
+            sc->beta = (op != K_RHO) ? 0.0 : (rho_new / sc->rho) * (sc->alpha / sc->omega);
+            sc->rho_old = sc->rho;
+            sc->rho = rho_new;
+            sc->norm = sqrt(b);
+            sc->rel = (sc->ref > 0.0) ? sc->norm / sc->ref : 0.0;
+            if (!isfinite(sc->norm) || !isfinite(sc->beta)) sc->bad = 1;
+            if (op == K_INIT) sc->lambda = sc->mu_v;  // the removed mean of b - A x
+            break;
+        }
+    }
+}
+
+// pd = r + beta (pd - omega v) on fluid + ghost cells
+__global__ void k_p_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
+                           const double *__restrict__ v, double *pd, const Scalars *sc) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    if (type[id] == T_DEAD) {
+        pd[id] = 0.0;
+        return;
+    }
+    const double beta = sc->beta, omega = sc->omega;
+    pd[id] = r[id] + beta * (pd[id] - omega * v[id]);
+}
+
+// s = r - alpha v
+__global__ void k_s_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
+                           const double *__restrict__ v, double *s, const Scalars *sc) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    s[id] = (type[id] == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id];
+}
+
+// x += alpha y + omega z ; r = s - omega t ; partials of rh.r (all) and r.r (fluid)
+__global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict__ type, int64_t N, double *x,
+                                                       const double *__restrict__ y, const double *__restrict__ z,
+                                                       const double *__restrict__ s, const double *__restrict__ t,
+                                                       double *r, const double *__restrict__ rh, const Scalars *sc,
+                                                       double *partials) {
+    __shared__ double sh[NORM_NT / 64];
+    const double alpha = sc->alpha, omega = sc->omega;
+    double a = 0.0, b = 0.0;
+    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
+        const uint8_t ty = type[id];
+        if (ty == T_DEAD) continue;
+        x[id] = x[id] + alpha * y[id] + omega * z[id];
+        const double rv = s[id] - omega * t[id];
+        r[id] = rv;
+        a += rh[id] * rv;
+        if (ty == T_FLUID) b += rv * rv;
+    }
+    double q = block_sum<NORM_NT>(a, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x] = q;
+    q = block_sum<NORM_NT>(b, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = q;
+}
+
+// preconditioner start: e = 0, ghost right-hand sides gh = r_g / s_g and e_g = gh (the first
+// ghost refresh of a zero field)
+template <typename T>
+__global__ void k_precond_zero(int64_t N, T *ea, T *eb) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    ea[id] = T(0);
+    eb[id] = T(0);
+}
+template <typename T>
+__global__ void k_precond_ghosts(int64_t ng, const int32_t *__restrict__ gcell, const int32_t *__restrict__ flags,
+                                 const double *__restrict__ scale, const double *__restrict__ r, double *gh, T *ea) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int64_t cell = gcell[g];
+    const double h = r[cell] / scale[g];
+    gh[g] = h;
+    // a degenerate ghost takes the mean of its (zero) fluid neighbours
+    ea[cell] = (flags[g] & GF_DEGENERATE) ? T(0) : (T)h;
+}
+// FP32 right-hand side of the mixed preconditioner
+__global__ void k_narrow(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r, float *r32) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    r32[id] = (type[id] == T_FLUID) ? (float)r[id] : 0.0f;
+}
+__global__ void k_widen(const uint8_t *__restrict__ type, int64_t N, const float *__restrict__ e, double *y) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    y[id] = (type[id] == T_DEAD) ? 0.0 : (double)e[id];
+}
+
+// y = M r: one V-cycle from zero on the error equation with right-hand side r (fluid) and
+// ghost right-hand sides r_g / s_g.  FP64: the result lands in one of (ya, yb), returned.
+// Mixed: the cycle runs in FP32 on the workspace's FP32 buffers and is widened into ya.
+static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double *yb, double **out,
+                               const ibm_solve_opts *o, hipStream_t s) {
+    hipError_t e;
+    const unsigned nbN = (unsigned)nblk(g->N), nbG = (unsigned)nblk(g->ng > 0 ? g->ng : 1);
+    if (o->precision == IBM_MIXED) {
+        hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a, g->e32b);
+        hipLaunchKernelGGL(k_narrow, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, g->r32);
+        if (g->ng > 0)
+            hipLaunchKernelGGL(k_precond_ghosts<float>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
+                               g->g_scale, r, g->g_rhs, g->e32a);
+        float *eb[2] = {g->e32a, g->e32b};
+        int ecur = 0;
+        if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
+        *out = ya;
+    } else {
+        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, yb);
+        if (g->ng > 0)
+            hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
+                               g->g_scale, r, g->g_rhs, ya);
+        double *bufs[2] = {ya, yb};
+        int cur = 0;
+        if ((e = vcycle_impl<double>(g, bufs, &cur, r, &g->sc->zero, g->g_rhs, o, s)) != hipSuccess) return e;
+        *out = bufs[cur];
+    }
+    return hipGetLastError();
+}
+
+// w = P A y (fluid mean removed) fused with the inner products of `mode` (see k_project)
+static hipError_t apply_projected(ibm_grid *g, const double *y, double *w, const double *other, double *rh, int mode,
+                                  int op, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_fluid, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), y, w, g->partials);
+    if (g->ng > 0)
+        hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), y, w, g->g_scale, g->nx,
+                           g->ny, g->nz, g->type, 0);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, w, other, rh, g->sc, mode,
+                       g->partials);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, op);
+    return hipGetLastError();
+}
+
+hipError_t krylov_setup(ibm_grid *g, hipStream_t s) {
+    if (g->ng == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_scale, dim3(nblk(g->ng)), dim3(256), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->am0[0],
+                       g->ap0[0], g->am0[1], g->ap0[1], g->am0[2], g->ap0[2], g->g_scale);
+    return hipGetLastError();
+}
+
+// r = P (b - A x), rh = r, rho = rh.r, norm of the fluid part; lambda = removed mean
+hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s) {
+    double *r = g->kv[0], *rh = g->kv[1];
+    hipLaunchKernelGGL(k_resid_fluid, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), f, x, r, g->partials);
+    if (g->ng > 0)
+        hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), x, r, g->g_scale, g->nx,
+                           g->ny, g->nz, g->type, 1);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, r, (const double *)nullptr, rh,
+                       g->sc, 2, g->partials);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_INIT);
+    return hipGetLastError();
+}
+
+// one BiCGStab step on x (kv: r, rh, pd, v, s, t, ya, yb, za, zb)
+hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s) {
+    double *r = g->kv[0], *rh = g->kv[1], *pd = g->kv[2], *v = g->kv[3], *sv = g->kv[4], *t = g->kv[5];
+    double *ya = g->kv[6], *yb = g->kv[7], *za = g->kv[8], *zb = g->kv[9];
+    const unsigned nbN = (unsigned)nblk(g->N);
+    hipError_t e;
+    hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc);
+    double *y = nullptr, *z = nullptr;
+    if ((e = precondition(g, pd, ya, yb, &y, o, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, y, v, rh, nullptr, 0, K_ALPHA, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_s_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, sv, g->sc);
+    if ((e = precondition(g, sv, za, zb, &z, o, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, z, t, sv, nullptr, 1, K_OMEGA, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xr_update, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, x, y, z, sv, t, r, rh, g->sc,
+                       g->partials);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_RHO);
+    return hipGetLastError();
+}
+
+// restart the shadow residual after a breakdown: rh = r, rho = r.r, beta = 0
+hipError_t krylov_restart(ibm_grid *g, hipStream_t s) {
+    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, g->kv[0],
+                       (const double *)nullptr, g->kv[1], g->sc, 3, g->partials);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc,
+                       (int)K_RESTART);
     return hipGetLastError();
 }
 

@@ -25,13 +25,16 @@ _STATUS = {0: "IBM_OK", 1: "IBM_NOT_CONVERGED", -1: "IBM_E_ARG", -2: "IBM_E_STAT
 class SolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_sweeps", C.c_int), ("precision", C.c_int), ("use_initial_guess", C.c_int),
-                ("fixed_cycles", C.c_int)]
+                ("fixed_cycles", C.c_int), ("method", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("rel_residual", C.c_double), ("ghost_residual_max", C.c_double),
                 ("lambda_", C.c_double), ("div_max", C.c_double), ("t_setup", C.c_double),
-                ("t_solve", C.c_double), ("t_correct", C.c_double)]
+                ("t_solve", C.c_double), ("t_correct", C.c_double), ("vcycles", C.c_int)]
+
+
+IBM_VCYCLE, IBM_BICGSTAB = 0, 1
 
 
 @dataclass
@@ -43,6 +46,11 @@ class Stats:
     div_max: float
     t_solve: float
     t_correct: float
+    vcycles: int = 0
+
+
+def _stats(code, st):
+    return Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct, st.vcycles)
 
 
 class IBMError(RuntimeError):
@@ -107,7 +115,7 @@ def declared_symbols(header=None):
 
 
 def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, precision="fp64",
-              use_initial_guess=False, fixed_cycles=0):
+              use_initial_guess=False, fixed_cycles=0, method="bicgstab"):
     o = SolveOpts()
     lib().ibm_default_opts(C.byref(o))
     o.rel_tol = rel_tol
@@ -116,6 +124,7 @@ def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, p
     o.precision = IBM_MIXED if precision in ("mixed", IBM_MIXED) else IBM_FP64
     o.use_initial_guess = int(bool(use_initial_guess))
     o.fixed_cycles = fixed_cycles
+    o.method = {"vcycle": IBM_VCYCLE, "bicgstab": IBM_BICGSTAB}[method] if isinstance(method, str) else int(method)
     return o
 
 
@@ -298,7 +307,7 @@ class Grid:
         with torch.cuda.device(self.device):
             code = self._check(lib().ibm_poisson_solve(self._h, _tptr(rhs), _tptr(p), C.byref(o), C.byref(st),
                                                        self._s()))
-        return p, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+        return p, _stats(code, st)
 
     def project(self, u, v, w, dt=1.0, p=None, **kw):
         torch = self.torch
@@ -315,7 +324,7 @@ class Grid:
         with torch.cuda.device(self.device):
             code = self._check(lib().ibm_project(self._h, _tptr(u), _tptr(v), _tptr(w), float(dt), _tptr(p), C.byref(o),
                                                  C.byref(st), self._s()))
-        return p, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+        return p, _stats(code, st)
 
     # non-blocking step API (serving)
     def solve_begin(self, rhs, p, **kw):
@@ -333,7 +342,7 @@ class Grid:
         done = C.c_int()
         st = SolveStats()
         code = self._check(lib().ibm_solve_poll(self._h, C.byref(done), C.byref(st)))
-        return done.value, Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct)
+        return done.value, _stats(code, st)
 
     # smoother timing
     def set_profiling(self, on=True):

@@ -154,8 +154,9 @@ def dense_bordered_solution(P, f):
     return x[:n].reshape(P.shape), x[n]
 
 
+@pytest.mark.parametrize("method", ["vcycle", "bicgstab"])
 @pytest.mark.parametrize("case", ["sphere3d", "plate3d", "cylinder2d"])
-def test_multigrid_equals_dense_bordered_solve(case):
+def test_multigrid_equals_dense_bordered_solve(case, method):
     if case == "sphere3d":
         wl = I.sphere_small(8, level=3)
     elif case == "plate3d":
@@ -172,7 +173,7 @@ def test_multigrid_equals_dense_bordered_solve(case):
     f = rng.standard_normal(P.shape) * (P.types() == 0)
     # nonzero Neumann data so the ghost right-hand sides are exercised
     P.set_neumann(rng.standard_normal(len(P.ghost_cells())))
-    p, st = P.solve(f, rel_tol=1e-13, max_cycles=200)
+    p, st = P.solve(f, rel_tol=1e-13, max_cycles=200, method=method)
     assert st.status == 0
     pd, lam = dense_bordered_solution(P, f)
     act = P.types() != 2
