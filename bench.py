@@ -55,6 +55,35 @@ def cpu_baseline(wl, cycles_needed, n_sample_cycles=3):
                       % (n_sample_cycles, cycles_needed, t1 - t0, per_cycle)}
 
 
+def probe(args):
+    """Fixed kernel sequence for rocprofv3 counter runs (one launch per kernel of interest):
+    a 512 MiB device-to-device copy (calibration: 512 MiB read + 512 MiB written), then the
+    level-0 fused sweep in FP64 on the workload."""
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+    from paper_2505_17287_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("probe: copy of %d bytes done" % (src.numel() * 8))
+    wl = I.multibody(args.n)
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision="fp64")
+    g.setup(wl.verts, wl.tris)
+    rng = np.random.default_rng(0)
+    p = torch.from_numpy(rng.standard_normal(g.shape)).to(dev)
+    f = torch.from_numpy(rng.standard_normal(g.shape)).to(dev)
+    torch.cuda.synchronize()
+    g.debug_sweep(p, f, lam=0.0, n=4, refresh=False)
+    torch.cuda.synchronize()
+    log("probe: 4 fused FP64 sweeps on %s done" % wl.name)
+    print(json.dumps({"probe": wl.name, "cells": wl.ncells, "copy_bytes": int(src.numel() * 8)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,10 +93,16 @@ def main():
     ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "vcycle"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="kernel probe for hardware counters: a plain device copy of known size for "
+                         "calibration, then 4 fused FP64 sweeps of level 0 on the workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.probe:
+        probe(args)
+        return
 
     import numpy as np
     import torch

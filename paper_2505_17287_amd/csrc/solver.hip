@@ -21,23 +21,72 @@ namespace ibm {
 // One sweep updates every red fluid cell ((i+j+k) even) from the old values, then every
 // black fluid cell from the new red values:
 //     p_c = (sum_f a_f p_nb - (f_c - lambda)) / sum_f a_f
-// Here both colours are done in one pass: each workgroup owns a tile of TX x TY columns
-// and a chunk of z-planes and marches upward; at step k it forms the red values of plane
-// k+1 (from old planes k, k+1, k+2) and then the black values of plane k (from the red
-// values of planes k-1, k, k+1).  In-plane neighbours come from LDS; a ring of one column
-// around the tile recomputes red values redundantly, a second ring only loads old values.
-// Each cell's new value is computed with the same operations in the same order as the
-// two-pass definition, so the result is bitwise identical to it.
-// Traffic per cell: read p, f, type; write p (25 B in FP64, 13 B in FP32).
+// Both colours are done in one out-of-place pass.  A workgroup owns a tile of columns and a
+// chunk of z-planes and marches upward; at step k it forms the red values of plane k+1
+// (from old planes k, k+1, k+2) and the black values of plane k (from the red values of
+// planes k-1, k, k+1).  Each thread owns two adjacent columns, so at every plane it holds
+// exactly one red and one black cell: no lane of a wave idles on the colour test, and the
+// pair moves as one 16-byte access.  In-plane neighbours come from double-buffered LDS
+// (one barrier per plane); a ring of one column around the tile recomputes red values
+// redundantly, a second ring only loads old values.  Each cell's new value is computed with
+// the same operations in the same order as the two-pass definition, so the result is
+// bitwise identical to it.
+// Algorithmic traffic per cell: read p, f, type; write p (25 B in FP64, 13 B in FP32).
 // =======================================================================================
 
-template <typename T, int BX, int BY>
-__global__ void __launch_bounds__(BX *BY)
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+
+template <typename T>
+struct SweepPlane {  // one plane of a thread's two columns
+    T o0, o1, f0, f1;
+    uint8_t t0, t1;
+};
+
+constexpr int SW_KC_MAX = 128;  // longest z chunk of one workgroup
+
+// relaxation value of one cell from its six neighbours (wall terms have zero coefficients)
+template <typename T>
+__device__ __forceinline__ T rb_update(T am, T ap, T bm, T bp, T cm, T cp, T xm, T xp, T ym, T yp, T zm, T zp,
+                                       T fv, T lam) {
+    T s = 0;
+    s = s + am * xm;
+    s = s + ap * xp;
+    s = s + bm * ym;
+    s = s + bp * yp;
+    s = s + cm * zm;
+    s = s + cp * zp;
+    T d = am + ap;
+    d = d + bm;
+    d = d + bp;
+    d = d + cm;
+    d = d + cp;
+    return (s - (fv - lam)) / d;
+}
+
+// VEC: nx is even, so a thread's column pair is 2-element aligned and moves as one access.
+// Every thread issues the same loads for every plane (addresses clamped into the grid,
+// values of cells outside it replaced by zero), which keeps the in-order memory counter
+// exact: the loads of a plane are consumed three planes after they are issued.
+template <typename T, int BXT, int BY, bool VEC>
+__global__ void __launch_bounds__(BXT *BY)
     k_rbgs_fused(Fine<T> F, const T *__restrict__ pin, T *__restrict__ pout, const T *__restrict__ f,
                  const T *__restrict__ lamp, int ntx, int nty, int kc, int ntiles) {
-    constexpr int TX = BX - 4, TY = BY - 4;
-    __shared__ T oldp[2][BY][BX + 1];
-    __shared__ T redp[BY][BX + 1];
+    using V = typename Vec2<T>::type;
+    using PD = SweepPlane<T>;
+    constexpr int NC = 2 * BXT;  // columns of a tile including the 2-column halo
+    constexpr int TXC = NC - 4, TY = BY - 4;
+    __shared__ T so[2][BY][NC + 1];  // old values of the plane whose red values are formed
+    __shared__ T sr[2][BY][NC + 1];  // red-updated values of the plane whose black values are formed
+    __shared__ T saz[2][SW_KC_MAX + 8];  // z coefficients of planes k0-2 .. k1+5
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs; give every
     // XCD a contiguous range of tiles so neighbouring tiles share one L2
     const int per = gridDim.x >> 3;
@@ -48,114 +97,190 @@ __global__ void __launch_bounds__(BX *BY)
     tile /= ntx;
     const int tyi = tile % nty;
     const int chunk = tile / nty;
-    const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-    const int i = txi * TX - 2 + tx, j = tyi * TY - 2 + ty;
-    const bool indom = (i >= 0 && i < F.nx && j >= 0 && j < F.ny);
-    const bool ring1 = indom && tx >= 1 && tx < BX - 1 && ty >= 1 && ty < BY - 1;
-    const bool inner = indom && tx >= 2 && tx < BX - 2 && ty >= 2 && ty < BY - 2;
-    const int nz = F.nz;
+    const int tx = threadIdx.x % BXT, ty = threadIdx.x / BXT;
+    {
+        const int kk = chunk * kc - 2 + (int)threadIdx.x;
+        if ((int)threadIdx.x < kc + 8) {
+            const bool kin = kk >= 0 && kk < F.nz;
+            saz[0][threadIdx.x] = kin ? F.azm[kk] : T(0);
+            saz[1][threadIdx.x] = kin ? F.azp[kk] : T(0);
+        }
+    }
+    const int lc = 2 * tx;              // local column of this thread's first cell
+    const int ia = txi * TXC - 2 + lc;  // global column of the first cell; second = ia + 1
+    const int j = tyi * TY - 2 + ty;
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool rowin = j >= 0 && j < ny;
+    const bool in0 = rowin && ia >= 0 && ia < nx, in1 = rowin && ia + 1 >= 0 && ia + 1 < nx;
+    const int yr = min(ty, BY - 1 - ty);
+    const int xr0 = min(lc, NC - 1 - lc), xr1 = min(lc + 1, NC - 2 - lc);
+    const bool red0 = in0 && yr >= 1 && xr0 >= 1, red1 = in1 && yr >= 1 && xr1 >= 1;
+    const bool blk0 = in0 && yr >= 2 && xr0 >= 2, blk1 = in1 && yr >= 2 && xr1 >= 2;
     const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
-    const int64_t plane = (int64_t)F.nx * F.ny;
-    const int64_t col = indom ? (int64_t)j * F.nx + i : 0;
-    T axm = 0, axp = 0, aym = 0, ayp = 0;
-    if (indom) {
-        axm = F.axm[i];
-        axp = F.axp[i];
-        aym = F.aym[j];
-        ayp = F.ayp[j];
-    }
+    const int64_t plane = (int64_t)nx * ny;
+    // clamped addressing: rows and columns outside the grid read a valid cell, then zero
+    const int jc = min(max(j, 0), ny - 1);
+    const int ic0 = min(max(ia, 0), nx - 1), ic1 = min(max(ia + 1, 0), nx - 1);
+    const int icv = min(max(ia, 0), nx - 2);  // pair start for the vector path (nx even)
+    const int64_t rowoff0 = (int64_t)jc * nx + (VEC ? icv : ic0);
+    const int64_t rowoff1 = (int64_t)jc * nx + ic1;
+    // with nx even a pair lies wholly inside or wholly outside the grid; pairs outside read
+    // a clamped pair and are zeroed
+    const T axm0 = in0 ? F.axm[ic0] : T(0), axp0 = in0 ? F.axp[ic0] : T(0);
+    const T axm1 = in1 ? F.axm[ic1] : T(0), axp1 = in1 ? F.axp[ic1] : T(0);
+    const T aym = rowin ? F.aym[jc] : T(0), ayp = rowin ? F.ayp[jc] : T(0);
     const T lam = *lamp;
-    auto ld_old = [&](int k) -> T { return (indom && k >= 0 && k < nz) ? pin[(int64_t)k * plane + col] : T(0); };
+    const int par = (ia + j) & 1;  // first cell is red at plane q iff (par + q) is even
 
-    T om = ld_old(k0 - 2), oc = ld_old(k0 - 1), op = ld_old(k0);
-    // value of this column at plane q after the red half-sweep
-    auto post_red = [&](int q, T &pr, T &fq, uint8_t &tq) {
-        T(*ob)[BX + 1] = oldp[q & 1];
-        ob[ty][tx] = oc;
-        __syncthreads();
-        const bool inq = indom && q >= 0 && q < nz;
-        tq = inq ? F.type[(int64_t)q * plane + col] : T_DEAD;
-        fq = inq ? f[(int64_t)q * plane + col] : T(0);
-        pr = oc;
-        if (ring1 && inq && tq == T_FLUID && ((i + j + q) & 1) == 0) {
-            const T azm = F.azm[q], azp = F.azp[q];
-            T s = 0;
-            s = s + axm * ob[ty][tx - 1];
-            s = s + axp * ob[ty][tx + 1];
-            s = s + aym * ob[ty - 1][tx];
-            s = s + ayp * ob[ty + 1][tx];
-            s = s + azm * om;
-            s = s + azp * op;
-            T d = axm + axp;
-            d = d + aym;
-            d = d + ayp;
-            d = d + azm;
-            d = d + azp;
-            pr = (s - (fq - lam)) / d;
+    auto load = [=](int k) -> PD {
+        PD d;
+        const bool kin = k >= 0 && k < nz;
+        const int kcl = min(max(k, 0), nz - 1);
+        const int64_t base = (int64_t)kcl * plane;
+        T o0, o1, f0, f1;
+        uint8_t t0, t1;
+        if (VEC) {
+            const V o = *reinterpret_cast<const V *>(pin + base + rowoff0);
+            const V fv = *reinterpret_cast<const V *>(f + base + rowoff0);
+            const uchar2 t = *reinterpret_cast<const uchar2 *>(F.type + base + rowoff0);
+            o0 = o.x;
+            o1 = o.y;
+            f0 = fv.x;
+            f1 = fv.y;
+            t0 = t.x;
+            t1 = t.y;
+        } else {
+            o0 = pin[base + rowoff0];
+            o1 = pin[base + rowoff1];
+            f0 = f[base + rowoff0];
+            f1 = f[base + rowoff1];
+            t0 = F.type[base + rowoff0];
+            t1 = F.type[base + rowoff1];
         }
+        const bool v0 = kin && in0, v1 = kin && in1;
+        d.o0 = v0 ? o0 : T(0);
+        d.o1 = v1 ? o1 : T(0);
+        d.f0 = v0 ? f0 : T(0);
+        d.f1 = v1 ? f1 : T(0);
+        d.t0 = v0 ? t0 : T_DEAD;
+        d.t1 = v1 ? t1 : T_DEAD;
+        return d;
     };
-    T prA, prB, prC, fB, fC, fdum;
-    uint8_t tB, tC, tdum;
-    post_red(k0 - 1, prA, fdum, tdum);
-    om = oc;
-    oc = op;
-    op = ld_old(k0 + 1);
-    post_red(k0, prB, fB, tB);
-    om = oc;
-    oc = op;
-    op = ld_old(k0 + 2);
-    for (int k = k0; k < k1; ++k) {
-        post_red(k + 1, prC, fC, tC);
-        om = oc;
-        oc = op;
-        op = ld_old(k + 3);
-        redp[ty][tx] = prB;
-        __syncthreads();
-        if (inner) {
-            T out = prB;
-            if (tB == T_FLUID && ((i + j + k) & 1) == 1) {
-                const T azm = F.azm[k], azp = F.azp[k];
-                T s = 0;
-                s = s + axm * redp[ty][tx - 1];
-                s = s + axp * redp[ty][tx + 1];
-                s = s + aym * redp[ty - 1][tx];
-                s = s + ayp * redp[ty + 1][tx];
-                s = s + azm * prA;
-                s = s + azp * prC;
-                T d = axm + axp;
-                d = d + aym;
-                d = d + ayp;
-                d = d + azm;
-                d = d + azp;
-                out = (s - (fB - lam)) / d;
-            }
-            pout[(int64_t)k * plane + col] = out;
-        }
-        prA = prB;
-        prB = prC;
-        fB = fC;
-        tB = tC;
+
+    // red-updated values of plane q: M = plane q-1, C = plane q, P = plane q+1, OB = LDS of
+    // the old values of plane q
+#define IBM_RED_PAIR(q, M, C, P, OB, R0, R1)                                                                        \
+    {                                                                                                              \
+        R0 = (C).o0;                                                                                               \
+        R1 = (C).o1;                                                                                               \
+        const bool fr_ = (((par + (q)) & 1) == 0);                                                                 \
+        const bool live_ = fr_ ? (red0 && (C).t0 == T_FLUID) : (red1 && (C).t1 == T_FLUID);                       \
+        if (live_) {                                                                                               \
+            const int l_ = fr_ ? lc : lc + 1;                                                                      \
+            const T v_ = rb_update<T>(fr_ ? axm0 : axm1, fr_ ? axp0 : axp1, aym, ayp, saz[0][(q) - k0 + 2],        \
+                                      saz[1][(q) - k0 + 2], OB[ty][l_ - 1], OB[ty][l_ + 1], OB[ty - 1][l_],        \
+                                      OB[ty + 1][l_],                                                              \
+                                      fr_ ? (M).o0 : (M).o1, fr_ ? (P).o0 : (P).o1, fr_ ? (C).f0 : (C).f1, lam);   \
+            if (fr_) R0 = v_;                                                                                      \
+            else R1 = v_;                                                                                          \
+        }                                                                                                          \
     }
+
+    // one plane step: A = plane k, B = k+1, C = k+2 (D = k+3 stays in flight); afterwards the
+    // slot A receives plane k+4.  Steps past the chunk end compute from clamped data and
+    // store nothing, so every step issues the same loads.
+#define IBM_STEP(A, B, C, k)                                                                                       \
+    {                                                                                                              \
+        so[buf][ty][lc] = (B).o0;                                                                                  \
+        so[buf][ty][lc + 1] = (B).o1;                                                                              \
+        sr[buf][ty][lc] = pb0;                                                                                     \
+        sr[buf][ty][lc + 1] = pb1;                                                                                 \
+        __syncthreads();                                                                                           \
+        T pc0, pc1;                                                                                                \
+        IBM_RED_PAIR((k) + 1, A, B, C, so[buf], pc0, pc1);                                                         \
+        T out0 = pb0, out1 = pb1;                                                                                  \
+        {                                                                                                          \
+            const bool fb_ = (((par + (k)) & 1) == 1);                                                             \
+            const bool live_ = fb_ ? (blk0 && (A).t0 == T_FLUID) : (blk1 && (A).t1 == T_FLUID);                   \
+            if (live_) {                                                                                           \
+                const int l_ = fb_ ? lc : lc + 1;                                                                  \
+                const T v_ = rb_update<T>(fb_ ? axm0 : axm1, fb_ ? axp0 : axp1, aym, ayp, saz[0][(k) - k0 + 2],    \
+                                          saz[1][(k) - k0 + 2],                                                    \
+                                          sr[buf][ty][l_ - 1], sr[buf][ty][l_ + 1], sr[buf][ty - 1][l_],           \
+                                          sr[buf][ty + 1][l_], fb_ ? pa0 : pa1, fb_ ? pc0 : pc1,                   \
+                                          fb_ ? (A).f0 : (A).f1, lam);                                             \
+                if (fb_) out0 = v_;                                                                                \
+                else out1 = v_;                                                                                    \
+            }                                                                                                      \
+        }                                                                                                          \
+        const int64_t id_ = (int64_t)(k) * plane + (int64_t)j * nx + ia;                                          \
+        const bool kst_ = (k) < k1;                                                                                \
+        if (VEC && kst_ && blk0 && blk1) {                                                                         \
+            V o_;                                                                                                  \
+            o_.x = out0;                                                                                           \
+            o_.y = out1;                                                                                           \
+            *reinterpret_cast<V *>(pout + id_) = o_;                                                               \
+        } else if (kst_) {                                                                                         \
+            if (blk0) pout[id_] = out0;                                                                            \
+            if (blk1) pout[id_ + 1] = out1;                                                                        \
+        }                                                                                                          \
+        pa0 = pb0;                                                                                                 \
+        pa1 = pb1;                                                                                                 \
+        pb0 = pc0;                                                                                                 \
+        pb1 = pc1;                                                                                                 \
+        buf ^= 1;                                                                                                  \
+        A = load((k) + 4);                                                                                         \
+    }
+
+    PD q0 = load(k0 - 2), q1 = load(k0 - 1), q2 = load(k0), q3 = load(k0 + 1);
+    T pa0, pa1, pb0, pb1;  // red-updated values of planes k-1 and k
+    // prologue: red values of planes k0-1 and k0
+    so[0][ty][lc] = q1.o0;
+    so[0][ty][lc + 1] = q1.o1;
+    __syncthreads();
+    IBM_RED_PAIR(k0 - 1, q0, q1, q2, so[0], pa0, pa1);
+    q0 = load(k0 + 2);
+    so[1][ty][lc] = q2.o0;
+    so[1][ty][lc + 1] = q2.o1;
+    __syncthreads();
+    IBM_RED_PAIR(k0, q1, q2, q3, so[1], pb0, pb1);
+    q1 = load(k0 + 3);
+    int buf = 0;
+    // queue: q2 = plane k, q3 = k+1, q0 = k+2, q1 = k+3; unrolled by the queue depth so the
+    // slots change roles by name and no in-flight load is ever copied
+    for (int k = k0; k < k1; k += 4) {
+        IBM_STEP(q2, q3, q0, k);
+        IBM_STEP(q3, q0, q1, k + 1);
+        IBM_STEP(q0, q1, q2, k + 2);
+        IBM_STEP(q1, q2, q3, k + 3);
+    }
+#undef IBM_STEP
+#undef IBM_RED_PAIR
 }
 
-constexpr int SW_BX = 64, SW_BY = 16;
+constexpr int SW_BXT = 32, SW_BY = 16;
 
 template <typename T>
 static hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
-    constexpr int TX = SW_BX - 4, TY = SW_BY - 4;
-    int ntx = (F.nx + TX - 1) / TX, nty = (F.ny + TY - 1) / TY;
-    int64_t per_slab = (int64_t)ntx * nty;
+    constexpr int TXC = 2 * SW_BXT - 4, TY = SW_BY - 4;
+    const int ntx = (F.nx + TXC - 1) / TXC, nty = (F.ny + TY - 1) / TY;
+    const int64_t per_slab = (int64_t)ntx * nty;
     // chunk the z range so the launch holds enough workgroups for 256 CUs
-    int nchunk = (int)((2048 + per_slab - 1) / per_slab);
+    int nchunk = (int)((1536 + per_slab - 1) / per_slab);
     if (nchunk > F.nz) nchunk = F.nz;
     if (nchunk < 1) nchunk = 1;
     int kc = (F.nz + nchunk - 1) / nchunk;
-    if (kc < 8 && F.nz >= 8) kc = 8;
+    if (kc < 16 && F.nz >= 16) kc = 16;
+    if (kc > SW_KC_MAX) kc = SW_KC_MAX;
     nchunk = (F.nz + kc - 1) / kc;
-    int ntiles = (int)(per_slab * nchunk);
-    int grid = ((ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_rbgs_fused<T, SW_BX, SW_BY>), dim3(grid), dim3(SW_BX * SW_BY), 0, s, F, pin, pout, f, lam,
-                       ntx, nty, kc, ntiles);
+    const int ntiles = (int)(per_slab * nchunk);
+    const int grid = ((ntiles + 7) / 8) * 8;
+    if ((F.nx & 1) == 0)
+        hipLaunchKernelGGL((k_rbgs_fused<T, SW_BXT, SW_BY, true>), dim3(grid), dim3(SW_BXT * SW_BY), 0, s, F, pin,
+                           pout, f, lam, ntx, nty, kc, ntiles);
+    else
+        hipLaunchKernelGGL((k_rbgs_fused<T, SW_BXT, SW_BY, false>), dim3(grid), dim3(SW_BXT * SW_BY), 0, s, F, pin,
+                           pout, f, lam, ntx, nty, kc, ntiles);
     return hipGetLastError();
 }
 
@@ -459,8 +584,63 @@ __global__ void k_sweepC(Coarse<T> L, int colour) {
 template <typename T>
 __global__ void __launch_bounds__(1024) k_coarsest(Coarse<T> L, int nsweeps, const double *vol) {
     __shared__ double sh[16];
+    __shared__ T es[1024];
     const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
     const T mu = (T)(*L.mu);
+    if (NC <= 1024) {
+        // one cell per thread: coefficients in registers, the iterate in LDS
+        const int id = threadIdx.x;
+        const bool live = id < NC;
+        int I = 0, J = 0, K = 0;
+        T txm = 0, txp = 0, tym = 0, typ = 0, tzm = 0, tzp = 0, rhs = 0, d = 0;
+        bool act = false;
+        const int sy = L.n[0], sz = L.n[0] * L.n[1];
+        if (live) {
+            I = id % L.n[0];
+            J = (id / L.n[0]) % L.n[1];
+            K = id / sz;
+            act = L.active[id] != 0;
+            txm = L.Tl[0][id];
+            txp = (I < L.n[0] - 1) ? L.Tl[0][id + 1] : T(0);
+            tym = L.Tl[1][id];
+            typ = (J < L.n[1] - 1) ? L.Tl[1][id + sy] : T(0);
+            tzm = L.Tl[2][id];
+            tzp = (K < L.n[2] - 1) ? L.Tl[2][id + sz] : T(0);
+            const T v = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+            rhs = L.R[id] - v * mu;
+            d = txm + txp;
+            d = d + tym;
+            d = d + typ;
+            d = d + tzm;
+            d = d + tzp;
+            es[id] = L.e[id];
+        }
+        __syncthreads();
+        const int colour = (I + J + K) & 1;
+        for (int s = 0; s < nsweeps; ++s) {
+            for (int c = 0; c < 2; ++c) {
+                if (live && act && colour == c && d > T(0)) {
+                    T num = 0;
+                    num = num + (I > 0 ? txm * es[id - 1] : T(0));
+                    num = num + (I < L.n[0] - 1 ? txp * es[id + 1] : T(0));
+                    num = num + (J > 0 ? tym * es[id - sy] : T(0));
+                    num = num + (J < L.n[1] - 1 ? typ * es[id + sy] : T(0));
+                    num = num + (K > 0 ? tzm * es[id - sz] : T(0));
+                    num = num + (K < L.n[2] - 1 ? tzp * es[id + sz] : T(0));
+                    es[id] = (num - rhs) / d;
+                }
+                __syncthreads();
+            }
+        }
+        double acc = 0.0;
+        if (live && act) acc = (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)es[id];
+        __shared__ double mean_s;
+        const double tot = block_sum<1024>(acc, sh, threadIdx.x);
+        if (threadIdx.x == 0) mean_s = (*vol > 0.0) ? tot / *vol : 0.0;
+        __syncthreads();
+        if (live) L.e[id] = act ? es[id] - (T)mean_s : es[id];
+        return;
+    }
     for (int s = 0; s < nsweeps; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             for (int64_t id = threadIdx.x; id < NC; id += 1024) {
@@ -1184,13 +1364,14 @@ __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict
 }
 
 // preconditioner start: e = 0, ghost right-hand sides gh = r_g / s_g and e_g = gh (the first
-// ghost refresh of a zero field)
+// ghost refresh of a zero field).  The second buffer only needs clearing when no
+// pre-smoothing sweep (which writes every cell of it) comes first.
 template <typename T>
 __global__ void k_precond_zero(int64_t N, T *ea, T *eb) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
     ea[id] = T(0);
-    eb[id] = T(0);
+    if (eb) eb[id] = T(0);
 }
 template <typename T>
 __global__ void k_precond_ghosts(int64_t ng, const int32_t *__restrict__ gcell, const int32_t *__restrict__ flags,
@@ -1223,7 +1404,8 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
     hipError_t e;
     const unsigned nbN = (unsigned)nblk(g->N), nbG = (unsigned)nblk(g->ng > 0 ? g->ng : 1);
     if (o->precision == IBM_MIXED) {
-        hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a, g->e32b);
+        hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a,
+                           o->nu1 > 0 ? (float *)nullptr : g->e32b);
         hipLaunchKernelGGL(k_narrow, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, g->r32);
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<float>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
@@ -1234,7 +1416,8 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
         hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
         *out = ya;
     } else {
-        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, yb);
+        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya,
+                           o->nu1 > 0 ? (double *)nullptr : yb);
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
                                g->g_scale, r, g->g_rhs, ya);
