@@ -20,6 +20,28 @@ sys.path.insert(0, ROOT)
 
 SWEEP_BYTES = {"fp64": 25.0, "fp32": 13.0}  # algorithmic bytes per cell of one fused sweep
 HBM_PEAK_GBS = 8000.0
+SWEEP_SRC = os.path.join(ROOT, "paper_2505_17287_amd", "csrc", "sweep.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rbgs_fused_fp64_multibody256_pmc.txt")
+
+
+def recorded_traffic(workload):
+    """HBM bytes per launch of the FP64 fused sweep from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by its plain-copy calibration factor), or None
+    when the summary is missing, is for another workload, or was taken on a different
+    version of the kernel source."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(("#", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != src or kv.get("workload") != workload:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -84,6 +106,92 @@ def probe(args):
     print(json.dumps({"probe": wl.name, "cells": wl.ncells, "copy_bytes": int(src.numel() * 8)}), flush=True)
 
 
+def mixed_form(wl, u0, v0, w0, args):
+    """The same projection with FP32 V-cycles inside FP64 BiCGStab: projections/s and the
+    FP32 fine sweep's algorithmic bandwidth."""
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+
+    dev = u0.device
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision="mixed")
+    g.set_geometry(wl.verts, wl.tris)
+    u, v, w = u0.clone(), v0.clone(), w0.clone()
+    p = torch.empty(g.shape, dtype=torch.float64, device=dev)
+
+    def step():
+        g.classify()
+        g.build_ghost_stencils()
+        u.copy_(u0)
+        v.copy_(v0)
+        w.copy_(w0)
+        return g.project(u, v, w, dt=1.0, p=p, rel_tol=1e-10, precision="mixed", method=args.method)[1]
+
+    steps = max(1, min(args.steps, 5))
+    step()
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    t0 = time.perf_counter()
+    sts = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    prof = g.profile()
+    g.set_profiling(False)
+    avg = prof["ms_fp32"] / max(prof["n_fp32"], 1)
+    ach = SWEEP_BYTES["fp32"] * wl.ncells / (avg * 1e-3) / 1e9
+    g.close()
+    return {"value": round(1000.0 / ms, 3), "unit": "projections/s", "ms_per_step": round(ms, 3), "steps": steps,
+            "dtype": "f32+f64", "outer_steps": int(np.median([s.cycles for s in sts])),
+            "vcycles": int(np.median([s.vcycles for s in sts])),
+            "max_rel_residual": max(s.rel_residual for s in sts),
+            "sweep_fp32": {"achieved_GBs": round(ach, 1), "avg_launch_ms": round(avg, 5),
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "launches_timed": prof["n_fp32"]}}
+
+
+def serving_form(args):
+    """Continuous batching of whole projections (grids 64^3..256^3, 1-4 bodies) against the
+    same requests served one at a time in plain FP64: saturation throughput, then p50/p99
+    latency at Poisson arrival rates of 0.5, 0.9 and 1.5 x the sequential capacity."""
+    from paper_2505_17287_amd import serve
+
+    R = args.serve_requests
+    log("serving: generating %d requests" % R)
+    base = serve.make_trace(R, qps=None)
+    warm = []
+    for n in (64, 128, 192, 256):
+        warm += [q for q in base if q.shape[0] == n][:1]
+    seq = serve.Server(slots=1, precision="fp64")
+    srv = serve.Server(slots=args.serve_slots, precision="mixed")
+    try:
+        seq.run(warm)
+        for _ in range(args.serve_slots):
+            srv.run(warm)
+        out = {"requests": R, "sizes": [64, 128, 192, 256], "slots": args.serve_slots,
+               "budget_GB": srv.budget / 2 ** 30, "served_precision": "mixed", "baseline": "one at a time, fp64"}
+        r, mk = seq.run(base)
+        out["sequential_fp64_saturation"] = serve.summarize(r, mk)
+        mu = out["sequential_fp64_saturation"]["solves_per_s"]
+        r, mk = srv.run(base)
+        out["served_saturation"] = serve.summarize(r, mk)
+        sweep = []
+        for x in (0.5, 0.9, 1.5):
+            tr = serve.make_trace(0, qps=x * mu, requests=base)
+            rs, mks = srv.run(tr)
+            rq, mkq = seq.run(tr)
+            sweep.append({"qps": round(x * mu, 3), "load_vs_seq_capacity": x,
+                          "served": serve.summarize(rs, mks), "sequential_fp64": serve.summarize(rq, mkq)})
+            log("serving qps %.2f: served p50 %.1f p99 %.1f ms, sequential p50 %.1f p99 %.1f ms"
+                % (x * mu, sweep[-1]["served"]["p50_ms"], sweep[-1]["served"]["p99_ms"],
+                   sweep[-1]["sequential_fp64"]["p50_ms"], sweep[-1]["sequential_fp64"]["p99_ms"]))
+        out["qps_sweep"] = sweep
+        out["resident_GB"] = round((srv.resident_bytes() + seq.resident_bytes()) / 2 ** 30, 2)
+        return out
+    finally:
+        seq.close()
+        srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +201,11 @@ def main():
     ap.add_argument("--method", default="bicgstab", choices=["bicgstab", "vcycle"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and serving forms (headline FP64 line only)")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests per serving run (sizes 64^3..256^3, 1-4 bodies each)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for hardware counters: a plain device copy of known size for "
                          "calibration, then 4 fused FP64 sweeps of level 0 on the workload")
@@ -156,7 +269,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_rbgs_fused<%s>" % ("double" if kind == "fp64" else "float"),
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(wl.name) if kind == "fp64" else None,
                 "avg_launch_ms": round(avg_ms, 5), "launches_timed": int(n_sw),
                 "bytes_per_launch": bytes_per_launch}
     out = {
@@ -179,6 +293,9 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
+    if not args.no_forms:
+        out["forms"] = {"mixed": mixed_form(wl, u0, v0, w0, args),
+                        "serving": serving_form(args)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, int(np.median(vcyc)))

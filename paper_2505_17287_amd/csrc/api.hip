@@ -190,7 +190,8 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
             }
         }
     }
-    G->partials = P.take<double>(std::max<int64_t>(4 * RED_BLOCKS, N / 256 + 1024));
+    G->partials = P.take<double>(std::max<int64_t>(std::max<int64_t>(4 * RED_BLOCKS, N / 256 + 1024),
+                                                   zmarch_partials_max(nx, ny, nz)));
     G->sc = P.take<Scalars>(1);
     return P.off + 256;
 }

@@ -2,9 +2,22 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 namespace ibm {
+
+// Compute units of the current device (queried once per device; 256 on MI355X).
+inline int device_cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -47,6 +60,15 @@ __device__ __forceinline__ double block_max(double v, double *sh, int tid) {
     }
     __syncthreads();
     return r;
+}
+
+// (i, j, k) of the flat index id = (k ny + j) nx + i.  Grids hold fewer than 2^31 cells,
+// so 32-bit unsigned arithmetic is exact (and far cheaper than 64-bit division).
+__device__ __forceinline__ void unflatten(int64_t id, int nx, int ny, int &i, int &j, int &k) {
+    const uint32_t u = (uint32_t)id, row = u / (uint32_t)nx;
+    i = (int)(u - row * (uint32_t)nx);
+    k = (int)(row / (uint32_t)ny);
+    j = (int)(row - (uint32_t)k * (uint32_t)ny);
 }
 
 // largest i in [0, n-2] with c[i] <= x (0 if x < c[0]); n >= 2

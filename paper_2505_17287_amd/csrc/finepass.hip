@@ -1,0 +1,383 @@
+// Fine-level (level 0) stencil passes of the multigrid cycle and of the Krylov operator,
+// written as z-marches (paper Section 2.1: the pressure equation on a non-uniform Cartesian
+// grid, solved with multigrid):
+//   - residual + restriction to level 1 with block partials of the restricted sum,
+//   - trilinear prolongation of the level-1 correction (injection where a contributor is
+//     inactive),
+//   - the operator S y on fluid rows with block partials of sum V (S y).
+//
+// A workgroup owns a tile of 64 x 4 columns and a chunk of z-planes; each thread owns one
+// column and marches upward.  Per-column metrics and prolongation tables are loaded once;
+// per-plane ones are uniform across the workgroup (scalar loads); the centre values of the
+// planes below and above stay in registers.  Every load of a plane is independent of the
+// others, so a plane costs one memory round trip, and there is no data-dependent branch
+// before the loads.  Chunks start at even planes, so a halved z pair never straddles two
+// workgroups.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_util.hpp"
+#include "ibm_impl.hpp"
+
+namespace ibm {
+
+namespace {
+
+constexpr int ZM_TX = 64, ZM_TY = 4, ZM_NT = ZM_TX * ZM_TY;
+
+struct ZTiles {
+    int ntx, nty, kc, ntiles, grid;
+};
+
+// Tile the grid so that about eight workgroups per CU are launched (all resident at once).
+ZTiles ztiles(int nx, int ny, int nz) {
+    ZTiles t;
+    t.ntx = (nx + ZM_TX - 1) / ZM_TX;
+    t.nty = (ny + ZM_TY - 1) / ZM_TY;
+    const int64_t per_slab = (int64_t)t.ntx * t.nty;
+    int nchunk = (int)std::max<int64_t>(1, (int64_t)8 * device_cu_count() / per_slab);
+    nchunk = std::min(nchunk, std::max(1, nz / 2));
+    int kc = (nz + nchunk - 1) / nchunk;
+    kc += kc & 1;  // even chunk starts
+    nchunk = (nz + kc - 1) / kc;
+    t.kc = kc;
+    t.ntiles = (int)(per_slab * nchunk);
+    t.grid = ((t.ntiles + 7) / 8) * 8;
+    return t;
+}
+
+struct ZPos {
+    bool live;  // the workgroup has a tile
+    int i, j, k0, k1, lane, wave;
+};
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so each XCD
+// receives a contiguous range of tiles and neighbouring tiles share one L2.
+__device__ __forceinline__ ZPos zpos(const ZTiles &t, int nz) {
+    ZPos z;
+    const int per = gridDim.x >> 3;
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    z.live = logical < t.ntiles;
+    int tile = logical;
+    const int txi = tile % t.ntx;
+    tile /= t.ntx;
+    const int tyi = tile % t.nty;
+    const int chunk = tile / t.nty;
+    z.lane = (int)threadIdx.x & (ZM_TX - 1);
+    z.wave = (int)threadIdx.x / ZM_TX;
+    z.i = txi * ZM_TX + z.lane;
+    z.j = tyi * ZM_TY + z.wave;
+    z.k0 = chunk * t.kc;
+    z.k1 = min(nz, z.k0 + t.kc);
+    return z;
+}
+
+// sum of a_f y_nb over the six faces and the diagonal, in the order of the two-pass
+// definition (wall terms contribute nothing)
+template <typename T>
+__device__ __forceinline__ void zm_stencil(T axm, T axp, T aym, T ayp, T azm, T azp, bool hx0, bool hx1, bool hy0,
+                                           bool hy1, bool hz0, bool hz1, T xm, T xp, T ym, T yp, T zm, T zp, T &num,
+                                           T &diag) {
+    T s = 0;
+    s = s + (hx0 ? axm * xm : T(0));
+    s = s + (hx1 ? axp * xp : T(0));
+    s = s + (hy0 ? aym * ym : T(0));
+    s = s + (hy1 ? ayp * yp : T(0));
+    s = s + (hz0 ? azm * zm : T(0));
+    s = s + (hz1 ? azp * zp : T(0));
+    T d = axm + axp;
+    d = d + aym;
+    d = d + ayp;
+    d = d + azm;
+    d = d + azp;
+    num = s;
+    diag = d;
+}
+
+template <int NT>
+__device__ __forceinline__ void zm_block_sum_store(double v, double *partials) {
+    __shared__ double sh[NT / 64];
+    const double s = block_sum<NT>(v, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ---- residual + restriction --------------------------------------------------------------
+// R_1(C) = sum over fluid children c of V_c r_c with r = (f - lambda) - S p; e_1 = 0;
+// partials[block] = sum of the R_1 written by the block.  The loads of plane k+1 are issued
+// before plane k is computed (two plane slots, alternating by name).
+template <typename T>
+struct RPlane {
+    T pp, xm, xp, ym, yp, fv;  // p(k+1) at the column, in-plane neighbours of plane k, f(k)
+    T azm, azp, wz;            // z metrics of plane k (prefetched with the plane)
+    uint8_t ty;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(ZM_NT)
+    k_restrict0_zm(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
+                   Coarse<T> C, int hx, int hy, int hz, ZTiles t, double *partials) {
+    __shared__ T srow[ZM_TY][ZM_TX];
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const T axm = F.axm[ic], axp = F.axp[ic], aym = F.aym[jc], ayp = F.ayp[jc];
+    const T vxy = F.wx[ic] * F.wy[jc];
+    const T lam = *lamp;
+    const bool writer = in && (!hx || (z.lane & 1) == 0) && (!hy || (z.wave & 1) == 0);
+    const int I = hx ? ic >> 1 : ic, J = hy ? jc >> 1 : jc;
+    auto ld = [=](int k) -> RPlane<T> {
+        RPlane<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = p[base + (kk < nz - 1 ? plane : 0)];
+        d.xm = p[base + dxm];
+        d.xp = p[base + dxp];
+        d.ym = p[base + dym];
+        d.yp = p[base + dyp];
+        d.fv = f[base];
+        d.ty = F.type[base];
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        d.wz = F.wz[kk];
+        return d;
+    };
+    T pm = (z.k0 > 0) ? p[(int64_t)(z.k0 - 1) * plane + rowoff] : T(0);
+    T pc = p[(int64_t)z.k0 * plane + rowoff];
+    T acc = 0;
+    double psum = 0.0;
+    // one plane: k >= k1 (the odd tail of the last chunk) computes from clamped data and
+    // writes nothing; the barriers stay uniform across the workgroup
+#define IBM_RESTRICT_PLANE(D, kk)                                                                                 \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        T num, diag;                                                                                               \
+        zm_stencil<T>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,        \
+                      (D).xp, (D).ym, (D).yp, pm, (D).pp, num, diag);                                              \
+        const T r = ((D).fv - lam) - (num - diag * pc);                                                           \
+        T v = (in && k_ < z.k1 && (D).ty == T_FLUID) ? (vxy * (D).wz) * r : T(0);                                 \
+        if (hx) v = v + __shfl_xor(v, 1, 64);                                                                      \
+        if (hy) {                                                                                                  \
+            srow[z.wave][z.lane] = v;                                                                              \
+            __syncthreads();                                                                                       \
+            v = v + srow[z.wave ^ 1][z.lane];                                                                      \
+            __syncthreads();                                                                                       \
+        }                                                                                                          \
+        acc = (hz && (k_ & 1)) ? acc + v : v;                                                                      \
+        if ((!hz || (k_ & 1)) && writer && k_ < z.k1) {                                                            \
+            const int K_ = hz ? k_ >> 1 : k_;                                                                      \
+            const int64_t cid = ((int64_t)K_ * C.n[1] + J) * C.n[0] + I;                                           \
+            C.R[cid] = acc;                                                                                        \
+            C.e[cid] = T(0);                                                                                       \
+            psum += (double)acc;                                                                                   \
+        }                                                                                                          \
+        pm = pc;                                                                                                   \
+        pc = (D).pp;                                                                                               \
+    }
+    RPlane<T> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_RESTRICT_PLANE(qa, k);
+        qa = ld(k + 2);
+        IBM_RESTRICT_PLANE(qb, k + 1);
+    }
+#undef IBM_RESTRICT_PLANE
+    zm_block_sum_store<ZM_NT>(psum, partials);
+}
+
+// ---- prolongation ------------------------------------------------------------------------
+// pnext = pcur + P e_1 on fluid cells (ghost cells are refreshed afterwards).  The loads of
+// plane k+1 (its z table entry, fine values and the coarse contributors) are issued before
+// plane k is computed.
+template <typename T>
+struct PPlane {
+    T pv, e[8];
+    uint8_t ty, act[8];
+    int pk;
+    double tz;
+    bool twoz;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(ZM_NT)
+    k_prolong0_zm(Fine<T> F, const T *__restrict__ pcur, T *__restrict__ pnext, Coarse<T> C, ProlongTab P,
+                  ZTiles t) {
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) return;
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const int ix[2] = {P.lo[0][ic], P.hi[0][ic]}, iy[2] = {P.lo[1][jc], P.hi[1][jc]};
+    const double tx = P.t[0][ic], ty = P.t[1][jc];
+    const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty};
+    const bool twox = ix[0] != ix[1], twoy = iy[0] != iy[1];
+    const int pi = P.halved[0] ? ic / 2 : ic, pj = P.halved[1] ? jc / 2 : jc;
+    const int64_t cny = C.n[1], cnx = C.n[0];
+    auto ld = [=](int k) -> PPlane<T> {
+        PPlane<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        const int iz[2] = {P.lo[2][kk], P.hi[2][kk]};
+        d.tz = P.t[2][kk];
+        d.twoz = iz[0] != iz[1];
+        d.pk = P.halved[2] ? kk / 2 : kk;
+        d.ty = F.type[base];
+        d.pv = pcur[base];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int64_t cid = ((int64_t)iz[c] * cny + iy[b]) * cnx + ix[a];
+                    d.act[4 * c + 2 * b + a] = C.active[cid];
+                    d.e[4 * c + 2 * b + a] = C.e[cid];
+                }
+        return d;
+    };
+#define IBM_PROLONG_PLANE(D, kk)                                                                                  \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        const double wz[2] = {1.0 - (D).tz, (D).tz};                                                               \
+        bool all = true;                                                                                           \
+        double s = 0.0;                                                                                            \
+        _Pragma("unroll") for (int c = 0; c < 2; ++c) _Pragma("unroll") for (int b = 0; b < 2; ++b)                \
+            _Pragma("unroll") for (int a = 0; a < 2; ++a) {                                                        \
+            const bool ok = (a == 0 || twox) && (b == 0 || twoy) && (c == 0 || (D).twoz);                          \
+            const double term = (wx[a] * wy[b]) * wz[c] * (double)(D).e[4 * c + 2 * b + a];                       \
+            if (ok) {                                                                                              \
+                if (!(D).act[4 * c + 2 * b + a]) all = false;                                                      \
+                s += term;                                                                                         \
+            }                                                                                                      \
+        }                                                                                                          \
+        if (in && k_ < z.k1 && (D).ty == T_FLUID) {                                                                \
+            if (!all) s = (double)C.e[((int64_t)(D).pk * cny + pj) * cnx + pi];                                    \
+            pnext[(int64_t)k_ * plane + rowoff] = (T)((double)(D).pv + s);                                         \
+        }                                                                                                          \
+    }
+    PPlane<T> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_PROLONG_PLANE(qa, k);
+        qa = ld(k + 2);
+        IBM_PROLONG_PLANE(qb, k + 1);
+    }
+#undef IBM_PROLONG_PLANE
+}
+
+// ---- Krylov operator ---------------------------------------------------------------------
+// w = S y on fluid rows, 0 elsewhere; partials[block] = sum over the block of V w.  The loads
+// of plane k+1 are issued before plane k is computed.
+__global__ void __launch_bounds__(ZM_NT)
+    k_apply_fluid_zm(Fine<double> F, const double *__restrict__ y, double *__restrict__ w, ZTiles t,
+                     double *partials) {
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const double axm = F.axm[ic], axp = F.axp[ic], aym = F.aym[jc], ayp = F.ayp[jc];
+    const double vxy = F.wx[ic] * F.wy[jc];
+    auto ld = [=](int k) -> RPlane<double> {
+        RPlane<double> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = y[base + (kk < nz - 1 ? plane : 0)];
+        d.xm = y[base + dxm];
+        d.xp = y[base + dxp];
+        d.ym = y[base + dym];
+        d.yp = y[base + dyp];
+        d.ty = F.type[base];
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        d.wz = F.wz[kk];
+        return d;
+    };
+    double ym1 = (z.k0 > 0) ? y[(int64_t)(z.k0 - 1) * plane + rowoff] : 0.0;
+    double yc = y[(int64_t)z.k0 * plane + rowoff];
+    double psum = 0.0;
+#define IBM_APPLY_PLANE(D, kk)                                                                                    \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        double num, diag;                                                                                          \
+        zm_stencil<double>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,  \
+                           (D).xp, (D).ym, (D).yp, ym1, (D).pp, num, diag);                                        \
+        const bool fl = in && (D).ty == T_FLUID;                                                                   \
+        const double a = fl ? num - diag * yc : 0.0;                                                               \
+        if (in && k_ < z.k1) {                                                                                     \
+            w[(int64_t)k_ * plane + rowoff] = a;                                                                   \
+            psum += (vxy * (D).wz) * a;                                                                            \
+        }                                                                                                          \
+        ym1 = yc;                                                                                                  \
+        yc = (D).pp;                                                                                               \
+    }
+    RPlane<double> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_APPLY_PLANE(qa, k);
+        qa = ld(k + 2);
+        IBM_APPLY_PLANE(qb, k + 1);
+    }
+#undef IBM_APPLY_PLANE
+    zm_block_sum_store<ZM_NT>(psum, partials);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
+                            const int halved[3], double *partials, int *nparts, hipStream_t s) {
+    const ZTiles t = ztiles(F.nx, F.ny, F.nz);
+    hipLaunchKernelGGL(k_restrict0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, p, f, lam, C, halved[0], halved[1],
+                       halved[2], t, partials);
+    *nparts = t.grid;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coarse<T> &C, const ProlongTab &P,
+                           hipStream_t s) {
+    const ZTiles t = ztiles(F.nx, F.ny, F.nz);
+    hipLaunchKernelGGL(k_prolong0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
+                              hipStream_t s) {
+    const ZTiles t = ztiles(F.nx, F.ny, F.nz);
+    hipLaunchKernelGGL(k_apply_fluid_zm, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, w, t, partials);
+    *nparts = t.grid;
+    return hipGetLastError();
+}
+
+// upper bound of the workgroup count of any z-march launch, whatever the CU count
+int64_t zmarch_partials_max(int nx, int ny, int nz) {
+    const int64_t per_slab = (int64_t)((nx + ZM_TX - 1) / ZM_TX) * ((ny + ZM_TY - 1) / ZM_TY);
+    return per_slab * std::max(1, nz / 2 + 1) + 8;
+}
+
+template hipError_t launch_restrict0<double>(const Fine<double> &, const double *, const double *, const double *,
+                                             const Coarse<double> &, const int[3], double *, int *, hipStream_t);
+template hipError_t launch_restrict0<float>(const Fine<float> &, const float *, const float *, const float *,
+                                            const Coarse<float> &, const int[3], double *, int *, hipStream_t);
+template hipError_t launch_prolong0<double>(const Fine<double> &, const double *, double *, const Coarse<double> &,
+                                            const ProlongTab &, hipStream_t);
+template hipError_t launch_prolong0<float>(const Fine<float> &, const float *, float *, const Coarse<float> &,
+                                           const ProlongTab &, hipStream_t);
+
+}  // namespace ibm

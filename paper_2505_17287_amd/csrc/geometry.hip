@@ -8,6 +8,7 @@
 // evaluation: classification and intercepts are reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.hpp"
@@ -337,39 +338,47 @@ __global__ void k_col_resolve(const int32_t *__restrict__ off, double *zs, const
 }
 
 // ghost = solid with a fluid cell among its in-range 26 neighbours; dead = other solid.
-// Solid cells hold 1 on entry; rewriting them to 1 or 2 keeps "solid" readable.
-__global__ void k_mark_ghosts(uint8_t *type, int nx, int ny, int nz, int64_t *counters) {
-    __shared__ double sh[8];
-    int64_t N = (int64_t)nx * ny * nz;
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Solid cells hold 1 on entry; rewriting them to 1 or 2 keeps "solid" readable.  A
+// grid-stride loop with block-level counts keeps the counter atomics to one per block.
+constexpr int MARK_NT = 256, MARK_BLOCKS = 2048;
+__global__ void __launch_bounds__(MARK_NT) k_mark_ghosts(uint8_t *type, int nx, int ny, int nz, int64_t *counters) {
+    __shared__ long long sh[3][MARK_NT / 64];
+    const int64_t N = (int64_t)nx * ny * nz;
     long long cf = 0, cg = 0, cd = 0;
-    if (id < N) {
-        uint8_t t = type[id];
+    for (int64_t id = (int64_t)blockIdx.x * MARK_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * MARK_NT) {
+        const uint8_t t = type[id];
         if (t == 0) {
-            cf = 1;
-        } else {
-            int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
-            bool fl = false;
-            for (int dk = -1; dk <= 1 && !fl; ++dk)
-                for (int dj = -1; dj <= 1 && !fl; ++dj)
-                    for (int di = -1; di <= 1 && !fl; ++di) {
-                        int ii = i + di, jj = j + dj, kk = k + dk;
-                        if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
-                        if (type[((int64_t)kk * ny + jj) * nx + ii] == 0) fl = true;
-                    }
-            type[id] = fl ? T_GHOST : T_DEAD;
-            if (fl) cg = 1;
-            else cd = 1;
+            cf += 1;
+            continue;
         }
+        int i, j, k;
+        unflatten(id, nx, ny, i, j, k);
+        bool fl = false;
+        for (int dk = -1; dk <= 1 && !fl; ++dk)
+            for (int dj = -1; dj <= 1 && !fl; ++dj)
+                for (int di = -1; di <= 1 && !fl; ++di) {
+                    const int ii = i + di, jj = j + dj, kk = k + dk;
+                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                    if (type[((int64_t)kk * ny + jj) * nx + ii] == 0) fl = true;
+                }
+        type[id] = fl ? T_GHOST : T_DEAD;
+        if (fl) cg += 1;
+        else cd += 1;
     }
-    (void)sh;
     cf = wave_sum_ll(cf);
     cg = wave_sum_ll(cg);
     cd = wave_sum_ll(cd);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (cf) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)cf);
-        if (cg) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)cg);
-        if (cd) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)cd);
+        sh[0][w] = cf;
+        sh[1][w] = cg;
+        sh[2][w] = cd;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        long long v = 0;
+        for (int q = 0; q < MARK_NT / 64; ++q) v += sh[threadIdx.x][q];
+        if (v) atomicAdd((unsigned long long *)&counters[threadIdx.x], (unsigned long long)v);
     }
 }
 
@@ -440,7 +449,8 @@ hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
     }
     hipLaunchKernelGGL(k_col_resolve, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
                        g->c0[2], nx, ny, nz, g->type, g->counters + 3, g->cross_cap);
-    hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g->type, nx, ny, nz,
+    hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)std::min<int64_t>((N + MARK_NT - 1) / MARK_NT, MARK_BLOCKS)),
+                       dim3(MARK_NT), 0, s, g->type, nx, ny, nz,
                        g->counters);
     int64_t nb = (N + CMP_CH - 1) / CMP_CH;
     int32_t *blkc = g->col_cnt;  // reuse: ncol+1 >= nb is guaranteed by the layout
@@ -549,7 +559,8 @@ __global__ void k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx,
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     int64_t id = gcell[g];
-    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
     double x[3] = {xc[i], yc[j], zc[k]};
     const bool two_d = (nz == 1);
     // the surface crosses the segment to any fluid neighbour: search within the largest
@@ -617,7 +628,8 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     int64_t id = gcell[g];
-    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
     const bool two_d = (nz == 1);
     double xg[3] = {xc[i], yc[j], zc[k]};
     double bi[3] = {gbi[3 * g], gbi[3 * g + 1], gbi[3 * g + 2]};
@@ -803,7 +815,8 @@ __global__ void k_coarsen_active(LevelDims F, LevelDims C, const uint8_t *__rest
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double vol = 0.0;
     if (id < NC) {
-        int I = (int)(id % C.n[0]), J = (int)((id / C.n[0]) % C.n[1]), K = (int)(id / ((int64_t)C.n[0] * C.n[1]));
+        int I, J, K;
+        unflatten(id, C.n[0], C.n[1], I, J, K);
         int i0 = C.h[0] ? 2 * I : I, i1 = C.h[0] ? 2 * I + 1 : I;
         int j0 = C.h[1] ? 2 * J : J, j1 = C.h[1] ? 2 * J + 1 : J;
         int k0 = C.h[2] ? 2 * K : K, k1 = C.h[2] ? 2 * K + 1 : K;
@@ -829,7 +842,8 @@ __global__ void k_fluid_volume(const uint8_t *__restrict__ type, int nx, int ny,
     double vol = 0.0;
     for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (int64_t)gridDim.x * blockDim.x) {
         if (type[id] == T_FLUID) {
-            int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+            int i, j, k;
+            unflatten(id, nx, ny, i, j, k);
             vol += (wx[i] * wy[j]) * wz[k];
         }
     }
@@ -852,7 +866,8 @@ __global__ void k_face_T(LevelDims F, LevelDims C, int d, const uint8_t *__restr
     int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= NC) return;
-    int Ic[3] = {(int)(id % C.n[0]), (int)((id / C.n[0]) % C.n[1]), (int)(id / ((int64_t)C.n[0] * C.n[1]))};
+    int Ic[3];
+    unflatten(id, C.n[0], C.n[1], Ic[0], Ic[1], Ic[2]);
     if (Ic[d] == 0) {
         T64[id] = 0.0;
         T32[id] = 0.0f;

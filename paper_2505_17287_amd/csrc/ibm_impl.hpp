@@ -25,7 +25,7 @@ namespace ibm {
 constexpr uint8_t T_FLUID = 0, T_GHOST = 1, T_DEAD = 2;
 constexpr int GF_DEGENERATE = 1, GF_CLAMPED = 2, GF_NFALLBACK = 4, GF_SELF = 8;
 constexpr int MAX_LEVELS = 24;
-constexpr int RED_BLOCKS = 1024;  // fixed block count of the deterministic reductions
+constexpr int RED_BLOCKS = 4096;  // fixed block count of the deterministic reductions (enough waves to fill every SIMD)
 constexpr int NBUCKET_MAX = 1 << 20;
 
 // ---------------------------------------------------------------------------------------
@@ -56,11 +56,27 @@ struct Coarse {  // coarse-level view in precision T
     const double *mu;     // compatibility shift per unit volume (device scalar)
 };
 
+// fused red-black sweep of level 0 (sweep.hip): pout = one RB-GS sweep of pin
+template <typename T>
+hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s);
+
 struct ProlongTab {  // fine index -> (lo, hi, weight of hi) per axis
     const int *lo[3], *hi[3];
     const double *t[3];
     int halved[3];
 };
+
+// z-march passes of level 0 (finepass.hip).  The reductions write one partial per
+// workgroup; *nparts receives their count (at most zmarch_partials_max).
+template <typename T>
+hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
+                            const int halved[3], double *partials, int *nparts, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coarse<T> &C, const ProlongTab &P,
+                           hipStream_t s);
+hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
+                              hipStream_t s);
+int64_t zmarch_partials_max(int nx, int ny, int nz);
 
 struct GhostView {
     int64_t ng;

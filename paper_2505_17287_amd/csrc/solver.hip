@@ -15,274 +15,6 @@
 
 namespace ibm {
 
-// =======================================================================================
-// fused red-black Gauss-Seidel sweep on level 0
-//
-// One sweep updates every red fluid cell ((i+j+k) even) from the old values, then every
-// black fluid cell from the new red values:
-//     p_c = (sum_f a_f p_nb - (f_c - lambda)) / sum_f a_f
-// Both colours are done in one out-of-place pass.  A workgroup owns a tile of columns and a
-// chunk of z-planes and marches upward; at step k it forms the red values of plane k+1
-// (from old planes k, k+1, k+2) and the black values of plane k (from the red values of
-// planes k-1, k, k+1).  Each thread owns two adjacent columns, so at every plane it holds
-// exactly one red and one black cell: no lane of a wave idles on the colour test, and the
-// pair moves as one 16-byte access.  In-plane neighbours come from double-buffered LDS
-// (one barrier per plane); a ring of one column around the tile recomputes red values
-// redundantly, a second ring only loads old values.  Each cell's new value is computed with
-// the same operations in the same order as the two-pass definition, so the result is
-// bitwise identical to it.
-// Algorithmic traffic per cell: read p, f, type; write p (25 B in FP64, 13 B in FP32).
-// =======================================================================================
-
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-    using type = double2;
-};
-template <>
-struct Vec2<float> {
-    using type = float2;
-};
-
-template <typename T>
-struct SweepPlane {  // one plane of a thread's two columns
-    T o0, o1, f0, f1;
-    uint8_t t0, t1;
-};
-
-constexpr int SW_KC_MAX = 128;  // longest z chunk of one workgroup
-
-// relaxation value of one cell from its six neighbours (wall terms have zero coefficients)
-template <typename T>
-__device__ __forceinline__ T rb_update(T am, T ap, T bm, T bp, T cm, T cp, T xm, T xp, T ym, T yp, T zm, T zp,
-                                       T fv, T lam) {
-    T s = 0;
-    s = s + am * xm;
-    s = s + ap * xp;
-    s = s + bm * ym;
-    s = s + bp * yp;
-    s = s + cm * zm;
-    s = s + cp * zp;
-    T d = am + ap;
-    d = d + bm;
-    d = d + bp;
-    d = d + cm;
-    d = d + cp;
-    return (s - (fv - lam)) / d;
-}
-
-// VEC: nx is even, so a thread's column pair is 2-element aligned and moves as one access.
-// Every thread issues the same loads for every plane (addresses clamped into the grid,
-// values of cells outside it replaced by zero), which keeps the in-order memory counter
-// exact: the loads of a plane are consumed three planes after they are issued.
-template <typename T, int BXT, int BY, bool VEC>
-__global__ void __launch_bounds__(BXT *BY)
-    k_rbgs_fused(Fine<T> F, const T *__restrict__ pin, T *__restrict__ pout, const T *__restrict__ f,
-                 const T *__restrict__ lamp, int ntx, int nty, int kc, int ntiles) {
-    using V = typename Vec2<T>::type;
-    using PD = SweepPlane<T>;
-    constexpr int NC = 2 * BXT;  // columns of a tile including the 2-column halo
-    constexpr int TXC = NC - 4, TY = BY - 4;
-    __shared__ T so[2][BY][NC + 1];  // old values of the plane whose red values are formed
-    __shared__ T sr[2][BY][NC + 1];  // red-updated values of the plane whose black values are formed
-    __shared__ T saz[2][SW_KC_MAX + 8];  // z coefficients of planes k0-2 .. k1+5
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs; give every
-    // XCD a contiguous range of tiles so neighbouring tiles share one L2
-    const int per = gridDim.x >> 3;
-    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (logical >= ntiles) return;
-    int tile = logical;
-    const int txi = tile % ntx;
-    tile /= ntx;
-    const int tyi = tile % nty;
-    const int chunk = tile / nty;
-    const int tx = threadIdx.x % BXT, ty = threadIdx.x / BXT;
-    {
-        const int kk = chunk * kc - 2 + (int)threadIdx.x;
-        if ((int)threadIdx.x < kc + 8) {
-            const bool kin = kk >= 0 && kk < F.nz;
-            saz[0][threadIdx.x] = kin ? F.azm[kk] : T(0);
-            saz[1][threadIdx.x] = kin ? F.azp[kk] : T(0);
-        }
-    }
-    const int lc = 2 * tx;              // local column of this thread's first cell
-    const int ia = txi * TXC - 2 + lc;  // global column of the first cell; second = ia + 1
-    const int j = tyi * TY - 2 + ty;
-    const int nx = F.nx, ny = F.ny, nz = F.nz;
-    const bool rowin = j >= 0 && j < ny;
-    const bool in0 = rowin && ia >= 0 && ia < nx, in1 = rowin && ia + 1 >= 0 && ia + 1 < nx;
-    const int yr = min(ty, BY - 1 - ty);
-    const int xr0 = min(lc, NC - 1 - lc), xr1 = min(lc + 1, NC - 2 - lc);
-    const bool red0 = in0 && yr >= 1 && xr0 >= 1, red1 = in1 && yr >= 1 && xr1 >= 1;
-    const bool blk0 = in0 && yr >= 2 && xr0 >= 2, blk1 = in1 && yr >= 2 && xr1 >= 2;
-    const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
-    const int64_t plane = (int64_t)nx * ny;
-    // clamped addressing: rows and columns outside the grid read a valid cell, then zero
-    const int jc = min(max(j, 0), ny - 1);
-    const int ic0 = min(max(ia, 0), nx - 1), ic1 = min(max(ia + 1, 0), nx - 1);
-    const int icv = min(max(ia, 0), nx - 2);  // pair start for the vector path (nx even)
-    const int64_t rowoff0 = (int64_t)jc * nx + (VEC ? icv : ic0);
-    const int64_t rowoff1 = (int64_t)jc * nx + ic1;
-    // with nx even a pair lies wholly inside or wholly outside the grid; pairs outside read
-    // a clamped pair and are zeroed
-    const T axm0 = in0 ? F.axm[ic0] : T(0), axp0 = in0 ? F.axp[ic0] : T(0);
-    const T axm1 = in1 ? F.axm[ic1] : T(0), axp1 = in1 ? F.axp[ic1] : T(0);
-    const T aym = rowin ? F.aym[jc] : T(0), ayp = rowin ? F.ayp[jc] : T(0);
-    const T lam = *lamp;
-    const int par = (ia + j) & 1;  // first cell is red at plane q iff (par + q) is even
-
-    auto load = [=](int k) -> PD {
-        PD d;
-        const bool kin = k >= 0 && k < nz;
-        const int kcl = min(max(k, 0), nz - 1);
-        const int64_t base = (int64_t)kcl * plane;
-        T o0, o1, f0, f1;
-        uint8_t t0, t1;
-        if (VEC) {
-            const V o = *reinterpret_cast<const V *>(pin + base + rowoff0);
-            const V fv = *reinterpret_cast<const V *>(f + base + rowoff0);
-            const uchar2 t = *reinterpret_cast<const uchar2 *>(F.type + base + rowoff0);
-            o0 = o.x;
-            o1 = o.y;
-            f0 = fv.x;
-            f1 = fv.y;
-            t0 = t.x;
-            t1 = t.y;
-        } else {
-            o0 = pin[base + rowoff0];
-            o1 = pin[base + rowoff1];
-            f0 = f[base + rowoff0];
-            f1 = f[base + rowoff1];
-            t0 = F.type[base + rowoff0];
-            t1 = F.type[base + rowoff1];
-        }
-        const bool v0 = kin && in0, v1 = kin && in1;
-        d.o0 = v0 ? o0 : T(0);
-        d.o1 = v1 ? o1 : T(0);
-        d.f0 = v0 ? f0 : T(0);
-        d.f1 = v1 ? f1 : T(0);
-        d.t0 = v0 ? t0 : T_DEAD;
-        d.t1 = v1 ? t1 : T_DEAD;
-        return d;
-    };
-
-    // red-updated values of plane q: M = plane q-1, C = plane q, P = plane q+1, OB = LDS of
-    // the old values of plane q
-#define IBM_RED_PAIR(q, M, C, P, OB, R0, R1)                                                                        \
-    {                                                                                                              \
-        R0 = (C).o0;                                                                                               \
-        R1 = (C).o1;                                                                                               \
-        const bool fr_ = (((par + (q)) & 1) == 0);                                                                 \
-        const bool live_ = fr_ ? (red0 && (C).t0 == T_FLUID) : (red1 && (C).t1 == T_FLUID);                       \
-        if (live_) {                                                                                               \
-            const int l_ = fr_ ? lc : lc + 1;                                                                      \
-            const T v_ = rb_update<T>(fr_ ? axm0 : axm1, fr_ ? axp0 : axp1, aym, ayp, saz[0][(q) - k0 + 2],        \
-                                      saz[1][(q) - k0 + 2], OB[ty][l_ - 1], OB[ty][l_ + 1], OB[ty - 1][l_],        \
-                                      OB[ty + 1][l_],                                                              \
-                                      fr_ ? (M).o0 : (M).o1, fr_ ? (P).o0 : (P).o1, fr_ ? (C).f0 : (C).f1, lam);   \
-            if (fr_) R0 = v_;                                                                                      \
-            else R1 = v_;                                                                                          \
-        }                                                                                                          \
-    }
-
-    // one plane step: A = plane k, B = k+1, C = k+2 (D = k+3 stays in flight); afterwards the
-    // slot A receives plane k+4.  Steps past the chunk end compute from clamped data and
-    // store nothing, so every step issues the same loads.
-#define IBM_STEP(A, B, C, k)                                                                                       \
-    {                                                                                                              \
-        so[buf][ty][lc] = (B).o0;                                                                                  \
-        so[buf][ty][lc + 1] = (B).o1;                                                                              \
-        sr[buf][ty][lc] = pb0;                                                                                     \
-        sr[buf][ty][lc + 1] = pb1;                                                                                 \
-        __syncthreads();                                                                                           \
-        T pc0, pc1;                                                                                                \
-        IBM_RED_PAIR((k) + 1, A, B, C, so[buf], pc0, pc1);                                                         \
-        T out0 = pb0, out1 = pb1;                                                                                  \
-        {                                                                                                          \
-            const bool fb_ = (((par + (k)) & 1) == 1);                                                             \
-            const bool live_ = fb_ ? (blk0 && (A).t0 == T_FLUID) : (blk1 && (A).t1 == T_FLUID);                   \
-            if (live_) {                                                                                           \
-                const int l_ = fb_ ? lc : lc + 1;                                                                  \
-                const T v_ = rb_update<T>(fb_ ? axm0 : axm1, fb_ ? axp0 : axp1, aym, ayp, saz[0][(k) - k0 + 2],    \
-                                          saz[1][(k) - k0 + 2],                                                    \
-                                          sr[buf][ty][l_ - 1], sr[buf][ty][l_ + 1], sr[buf][ty - 1][l_],           \
-                                          sr[buf][ty + 1][l_], fb_ ? pa0 : pa1, fb_ ? pc0 : pc1,                   \
-                                          fb_ ? (A).f0 : (A).f1, lam);                                             \
-                if (fb_) out0 = v_;                                                                                \
-                else out1 = v_;                                                                                    \
-            }                                                                                                      \
-        }                                                                                                          \
-        const int64_t id_ = (int64_t)(k) * plane + (int64_t)j * nx + ia;                                          \
-        const bool kst_ = (k) < k1;                                                                                \
-        if (VEC && kst_ && blk0 && blk1) {                                                                         \
-            V o_;                                                                                                  \
-            o_.x = out0;                                                                                           \
-            o_.y = out1;                                                                                           \
-            *reinterpret_cast<V *>(pout + id_) = o_;                                                               \
-        } else if (kst_) {                                                                                         \
-            if (blk0) pout[id_] = out0;                                                                            \
-            if (blk1) pout[id_ + 1] = out1;                                                                        \
-        }                                                                                                          \
-        pa0 = pb0;                                                                                                 \
-        pa1 = pb1;                                                                                                 \
-        pb0 = pc0;                                                                                                 \
-        pb1 = pc1;                                                                                                 \
-        buf ^= 1;                                                                                                  \
-        A = load((k) + 4);                                                                                         \
-    }
-
-    PD q0 = load(k0 - 2), q1 = load(k0 - 1), q2 = load(k0), q3 = load(k0 + 1);
-    T pa0, pa1, pb0, pb1;  // red-updated values of planes k-1 and k
-    // prologue: red values of planes k0-1 and k0
-    so[0][ty][lc] = q1.o0;
-    so[0][ty][lc + 1] = q1.o1;
-    __syncthreads();
-    IBM_RED_PAIR(k0 - 1, q0, q1, q2, so[0], pa0, pa1);
-    q0 = load(k0 + 2);
-    so[1][ty][lc] = q2.o0;
-    so[1][ty][lc + 1] = q2.o1;
-    __syncthreads();
-    IBM_RED_PAIR(k0, q1, q2, q3, so[1], pb0, pb1);
-    q1 = load(k0 + 3);
-    int buf = 0;
-    // queue: q2 = plane k, q3 = k+1, q0 = k+2, q1 = k+3; unrolled by the queue depth so the
-    // slots change roles by name and no in-flight load is ever copied
-    for (int k = k0; k < k1; k += 4) {
-        IBM_STEP(q2, q3, q0, k);
-        IBM_STEP(q3, q0, q1, k + 1);
-        IBM_STEP(q0, q1, q2, k + 2);
-        IBM_STEP(q1, q2, q3, k + 3);
-    }
-#undef IBM_STEP
-#undef IBM_RED_PAIR
-}
-
-constexpr int SW_BXT = 32, SW_BY = 16;
-
-template <typename T>
-static hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
-    constexpr int TXC = 2 * SW_BXT - 4, TY = SW_BY - 4;
-    const int ntx = (F.nx + TXC - 1) / TXC, nty = (F.ny + TY - 1) / TY;
-    const int64_t per_slab = (int64_t)ntx * nty;
-    // chunk the z range so the launch holds enough workgroups for 256 CUs
-    int nchunk = (int)((1536 + per_slab - 1) / per_slab);
-    if (nchunk > F.nz) nchunk = F.nz;
-    if (nchunk < 1) nchunk = 1;
-    int kc = (F.nz + nchunk - 1) / nchunk;
-    if (kc < 16 && F.nz >= 16) kc = 16;
-    if (kc > SW_KC_MAX) kc = SW_KC_MAX;
-    nchunk = (F.nz + kc - 1) / kc;
-    const int ntiles = (int)(per_slab * nchunk);
-    const int grid = ((ntiles + 7) / 8) * 8;
-    if ((F.nx & 1) == 0)
-        hipLaunchKernelGGL((k_rbgs_fused<T, SW_BXT, SW_BY, true>), dim3(grid), dim3(SW_BXT * SW_BY), 0, s, F, pin,
-                           pout, f, lam, ntx, nty, kc, ntiles);
-    else
-        hipLaunchKernelGGL((k_rbgs_fused<T, SW_BXT, SW_BY, false>), dim3(grid), dim3(SW_BXT * SW_BY), 0, s, F, pin,
-                           pout, f, lam, ntx, nty, kc, ntiles);
-    return hipGetLastError();
-}
 
 // =======================================================================================
 // ghost refresh: p_g = sum_{m != g} beta_m p_m + h_g from one snapshot (Jacobi over ghosts)
@@ -299,7 +31,8 @@ __global__ void k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T 
     const int64_t cell = G.cell[g];
     double v;
     if (G.flags[g] & GF_DEGENERATE) {
-        int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((int64_t)nx * ny));
+        int i, j, k;
+        unflatten(cell, nx, ny, i, j, k);
         double s = 0.0;
         int n = 0;
         for (int dk = -1; dk <= 1; ++dk)
@@ -485,40 +218,6 @@ struct Halv {
     int h[3];
 };
 
-// level 0 -> 1: R_1(C) = sum over fluid children of V_c r_c, r = (f - lambda) - S p
-template <typename T>
-__global__ void k_resrestrict0(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
-                               Coarse<T> C, Halv H, double *partials) {
-    __shared__ double sh[4];
-    const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
-    const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double Rsum = 0.0;
-    if (cid < NC) {
-        const T lam = *lamp;
-        int I = (int)(cid % C.n[0]), J = (int)((cid / C.n[0]) % C.n[1]), K = (int)(cid / ((int64_t)C.n[0] * C.n[1]));
-        int i0 = H.h[0] ? 2 * I : I, i1 = H.h[0] ? 2 * I + 1 : I;
-        int j0 = H.h[1] ? 2 * J : J, j1 = H.h[1] ? 2 * J + 1 : J;
-        int k0 = H.h[2] ? 2 * K : K, k1 = H.h[2] ? 2 * K + 1 : K;
-        T R = 0;
-        for (int k = k0; k <= k1; ++k)
-            for (int j = j0; j <= j1; ++j)
-                for (int i = i0; i <= i1; ++i) {
-                    const int64_t id = ((int64_t)k * F.ny + j) * F.nx + i;
-                    if (F.type[id] != T_FLUID) continue;
-                    T num, diag;
-                    fine_stencil(F, p, i, j, k, id, num, diag);
-                    const T r = (f[id] - lam) - (num - diag * p[id]);
-                    const T vol = (F.wx[i] * F.wy[j]) * F.wz[k];
-                    R += vol * r;
-                }
-        C.R[cid] = R;
-        C.e[cid] = T(0);
-        Rsum = (double)R;
-    }
-    double s = block_sum<256>(Rsum, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
 // level l -> l+1 (l >= 1): R_{l+1}(C) = sum over active children of r, r = (R - V mu) - S e
 template <typename T>
 __global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partials) {
@@ -528,20 +227,24 @@ __global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partial
     double Rsum = 0.0;
     if (cid < NC) {
         const T mu = (T)(*L.mu);
-        int I = (int)(cid % C.n[0]), J = (int)((cid / C.n[0]) % C.n[1]), K = (int)(cid / ((int64_t)C.n[0] * C.n[1]));
-        int i0 = H.h[0] ? 2 * I : I, i1 = H.h[0] ? 2 * I + 1 : I;
-        int j0 = H.h[1] ? 2 * J : J, j1 = H.h[1] ? 2 * J + 1 : J;
-        int k0 = H.h[2] ? 2 * K : K, k1 = H.h[2] ? 2 * K + 1 : K;
+        int I, J, K;
+        unflatten(cid, C.n[0], C.n[1], I, J, K);
+        const int i0 = H.h[0] ? 2 * I : I, j0 = H.h[1] ? 2 * J : J, k0 = H.h[2] ? 2 * K : K;
         T R = 0;
-        for (int k = k0; k <= k1; ++k)
-            for (int j = j0; j <= j1; ++j)
-                for (int i = i0; i <= i1; ++i) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const bool ok = (a == 0 || H.h[0]) && (b == 0 || H.h[1]) && (c == 0 || H.h[2]);
+                    const int i = i0 + (H.h[0] ? a : 0), j = j0 + (H.h[1] ? b : 0), k = k0 + (H.h[2] ? c : 0);
                     const int64_t id = ((int64_t)k * L.n[1] + j) * L.n[0] + i;
-                    if (!L.active[id]) continue;
                     T num, diag;
                     coarse_stencil(L, L.e, i, j, k, id, num, diag);
                     const T vol = (L.w[0][i] * L.w[1][j]) * L.w[2][k];
-                    R += (L.R[id] - vol * mu) - (num - diag * L.e[id]);
+                    const T rc = (L.R[id] - vol * mu) - (num - diag * L.e[id]);
+                    if (ok && L.active[id]) R += rc;
                 }
         C.R[cid] = R;
         C.e[cid] = T(0);
@@ -569,7 +272,8 @@ __global__ void k_sweepC(Coarse<T> L, int colour) {
     const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= NC) return;
-    int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+    int I, J, K;
+    unflatten(id, L.n[0], L.n[1], I, J, K);
     if (((I + J + K) & 1) != colour || !L.active[id]) return;
     T num, diag;
     coarse_stencil(L, L.e, I, J, K, id, num, diag);
@@ -644,7 +348,8 @@ __global__ void __launch_bounds__(1024) k_coarsest(Coarse<T> L, int nsweeps, con
     for (int s = 0; s < nsweeps; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             for (int64_t id = threadIdx.x; id < NC; id += 1024) {
-                int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+                int I, J, K;
+                unflatten(id, L.n[0], L.n[1], I, J, K);
                 if (((I + J + K) & 1) != colour || !L.active[id]) continue;
                 T num, diag;
                 coarse_stencil(L, L.e, I, J, K, id, num, diag);
@@ -659,7 +364,8 @@ __global__ void __launch_bounds__(1024) k_coarsest(Coarse<T> L, int nsweeps, con
     double acc = 0.0;
     for (int64_t id = threadIdx.x; id < NC; id += 1024) {
         if (!L.active[id]) continue;
-        int I = (int)(id % L.n[0]), J = (int)((id / L.n[0]) % L.n[1]), K = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+        int I, J, K;
+        unflatten(id, L.n[0], L.n[1], I, J, K);
         acc += (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)L.e[id];
     }
     __shared__ double mean;
@@ -679,15 +385,25 @@ __device__ __forceinline__ double prolong_value(const Coarse<T> &C, const Prolon
     const int ix[2] = {P.lo[0][i], P.hi[0][i]}, iy[2] = {P.lo[1][j], P.hi[1][j]}, iz[2] = {P.lo[2][k], P.hi[2][k]};
     const double tx = P.t[0][i], ty = P.t[1][j], tz = P.t[2][k];
     const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
-    const int nx_ = (ix[0] == ix[1]) ? 1 : 2, ny_ = (iy[0] == iy[1]) ? 1 : 2, nz_ = (iz[0] == iz[1]) ? 1 : 2;
+    const bool two[3] = {ix[0] != ix[1], iy[0] != iy[1], iz[0] != iz[1]};
     bool all = true;
     double s = 0.0;
-    for (int c = 0; c < nz_; ++c)
-        for (int b = 0; b < ny_; ++b)
-            for (int a = 0; a < nx_; ++a) {
+    // fixed 2x2x2 loop (a second contributor that coincides with the first is skipped),
+    // unrolled so that all coarse loads are issued together
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const bool ok = (a == 0 || two[0]) && (b == 0 || two[1]) && (c == 0 || two[2]);
                 const int64_t cid = ((int64_t)iz[c] * C.n[1] + iy[b]) * C.n[0] + ix[a];
-                if (!C.active[cid]) all = false;
-                s += (wx[a] * wy[b]) * wz[c] * (double)C.e[cid];
+                const bool act = C.active[cid] != 0;
+                const double term = (wx[a] * wy[b]) * wz[c] * (double)C.e[cid];
+                if (ok) {
+                    if (!act) all = false;
+                    s += term;
+                }
             }
     if (!all) {
         const int pi = P.halved[0] ? i / 2 : i, pj = P.halved[1] ? j / 2 : j, pk = P.halved[2] ? k / 2 : k;
@@ -701,18 +417,9 @@ __global__ void k_prolongC(Coarse<T> L, Coarse<T> C, ProlongTab P) {
     const int64_t N = (int64_t)L.n[0] * L.n[1] * L.n[2];
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N || !L.active[id]) return;
-    int i = (int)(id % L.n[0]), j = (int)((id / L.n[0]) % L.n[1]), k = (int)(id / ((int64_t)L.n[0] * L.n[1]));
+    int i, j, k;
+    unflatten(id, L.n[0], L.n[1], i, j, k);
     L.e[id] = (T)((double)L.e[id] + prolong_value(C, P, i, j, k));
-}
-
-// level 0: pnext = pcur + P e_1 on fluid cells (ghosts are refreshed afterwards)
-template <typename T>
-__global__ void k_prolong0(Fine<T> F, const T *__restrict__ pcur, T *pnext, Coarse<T> C, ProlongTab P) {
-    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N || F.type[id] != T_FLUID) return;
-    int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
-    pnext[id] = (T)((double)pcur[id] + prolong_value(C, P, i, j, k));
 }
 
 // =======================================================================================
@@ -738,7 +445,8 @@ __global__ void __launch_bounds__(NORM_NT) k_norm0(Fine<double> F, const double 
             if (WRITE_R32) r32[id] = 0.0f;
             continue;
         }
-        int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        int i, j, k;
+        unflatten(id, F.nx, F.ny, i, j, k);
         double num, diag;
         fine_stencil(F, p, i, j, k, id, num, diag);
         const double r = f[id] - (num - diag * p[id]);
@@ -793,7 +501,8 @@ __global__ void __launch_bounds__(NORM_NT) k_fsum(Fine<double> F, const double *
     for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
         if (F.type[id] != T_FLUID) continue;
         if (pass == 0) {
-            int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+            int i, j, k;
+            unflatten(id, F.nx, F.ny, i, j, k);
             s += ((F.wx[i] * F.wy[j]) * F.wz[k]) * f[id];
         } else {
             const double d = f[id] - mean;
@@ -822,7 +531,8 @@ __global__ void __launch_bounds__(NORM_NT) k_psum(Fine<double> F, const double *
     double s = 0.0;
     for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
         if (F.type[id] != T_FLUID) continue;
-        int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        int i, j, k;
+        unflatten(id, F.nx, F.ny, i, j, k);
         s += ((F.wx[i] * F.wy[j]) * F.wz[k]) * p[id];
     }
     double t = block_sum<NORM_NT>(s, sh, threadIdx.x);
@@ -859,7 +569,8 @@ __global__ void k_apply0(Fine<T> F, const T *__restrict__ p, T *out) {
         out[id] = T(0);
         return;
     }
-    int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+    int i, j, k;
+    unflatten(id, F.nx, F.ny, i, j, k);
     T num, diag;
     fine_stencil(F, p, i, j, k, id, num, diag);
     out[id] = num - diag * p[id];
@@ -918,11 +629,10 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
     if (g->nlev > 1) {
         {
             Coarse<T> C1 = coarse_view<T>(g, 1);
-            Halv H;
-            for (int d = 0; d < 3; ++d) H.h[d] = g->lev[1].halved[d];
-            int nb = nblk(g->lev[1].ncell());
-            hipLaunchKernelGGL(k_resrestrict0<T>, dim3(nb), dim3(256), 0, s, F, bufs[*cur], rhs, lam, C1, H,
-                               g->partials);
+            int nb = 0;
+            if ((e = launch_restrict0<T>(F, bufs[*cur], rhs, lam, C1, g->lev[1].halved, g->partials, &nb, s)) !=
+                hipSuccess)
+                return e;
             hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nb, &g->sc->vol[1],
                                &g->sc->mu[1]);
         }
@@ -955,8 +665,8 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
         }
         {
             T *pin = bufs[*cur], *pout = bufs[1 - *cur];
-            hipLaunchKernelGGL(k_prolong0<T>, dim3(nblk(g->N)), dim3(256), 0, s, F, pin, pout, coarse_view<T>(g, 1),
-                               prolong_tab(g, 0));
+            if ((e = launch_prolong0<T>(F, pin, pout, coarse_view<T>(g, 1), prolong_tab(g, 0), s)) != hipSuccess)
+                return e;
             if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
             *cur = 1 - *cur;
         }
@@ -1065,7 +775,8 @@ __global__ void k_rhs(Fine<double> F, const double *__restrict__ u, const double
         return;
     }
     const int nx = F.nx, ny = F.ny;
-    int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
     const int64_t iu = ((int64_t)k * ny + j) * (nx + 1) + i;
     const int64_t iv = ((int64_t)k * (ny + 1) + j) * nx + i;
     const int64_t iw = ((int64_t)k * ny + j) * nx + i;
@@ -1089,7 +800,8 @@ __global__ void k_correct(const uint8_t *__restrict__ type, int nx, int ny, int 
     const int64_t NF = (int64_t)fx * fy * fz;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= NF) return;
-    int i = (int)(id % fx), j = (int)((id / fx) % fy), k = (int)(id / ((int64_t)fx * fy));
+    int i, j, k;
+    unflatten(id, fx, fy, i, j, k);
     int q = (d == 0) ? i : (d == 1) ? j : k;
     int n = (d == 0) ? nx : (d == 1) ? ny : nz;
     if (q == 0 || q == n) return;  // domain walls
@@ -1118,7 +830,8 @@ __global__ void __launch_bounds__(NORM_NT) k_divmax(Fine<double> F, const double
     double m = 0.0;
     for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
         if (F.type[id] != T_FLUID) continue;
-        int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+        int i, j, k;
+        unflatten(id, nx, ny, i, j, k);
         const int64_t iu = ((int64_t)k * ny + j) * (nx + 1) + i;
         const int64_t iv = ((int64_t)k * (ny + 1) + j) * nx + i;
         const int64_t iw = ((int64_t)k * ny + j) * nx + i;
@@ -1165,35 +878,14 @@ __global__ void k_ghost_scale(int64_t ng, const int32_t *__restrict__ gcell, int
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int64_t id = gcell[g];
-    const int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
     double d = axm[i] + axp[i];
     d = d + aym[j];
     d = d + ayp[j];
     d = d + azm[k];
     d = d + azp[k];
     scale[g] = d;
-}
-
-// fluid rows of A y (non-fluid entries 0) with partial sums of sum_fluid V (A y)
-__global__ void __launch_bounds__(NORM_NT) k_apply_fluid(Fine<double> F, const double *__restrict__ y,
-                                                         double *w, double *partials) {
-    __shared__ double sh[NORM_NT / 64];
-    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
-    double sv = 0.0;
-    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
-        if (F.type[id] != T_FLUID) {
-            w[id] = 0.0;
-            continue;
-        }
-        const int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
-        double num, diag;
-        fine_stencil(F, y, i, j, k, id, num, diag);
-        const double a = num - diag * y[id];
-        w[id] = a;
-        sv += ((F.wx[i] * F.wy[j]) * F.wz[k]) * a;
-    }
-    const double t = block_sum<NORM_NT>(sv, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // ghost rows of A y (mode 0) or of b - A y (mode 1: out = s_g h_g - A y)
@@ -1204,7 +896,8 @@ __global__ void k_apply_ghost(GhostView G, const double *__restrict__ y, double 
     const int64_t cell = G.cell[g];
     double target;
     if (G.flags[g] & GF_DEGENERATE) {
-        const int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((int64_t)nx * ny));
+        int i, j, k;
+        unflatten(cell, nx, ny, i, j, k);
         double s = 0.0;
         int n = 0;
         for (int dk = -1; dk <= 1; ++dk)
@@ -1243,7 +936,8 @@ __global__ void __launch_bounds__(NORM_NT) k_resid_fluid(Fine<double> F, const d
             r[id] = 0.0;
             continue;
         }
-        const int i = (int)(id % F.nx), j = (int)((id / F.nx) % F.ny), k = (int)(id / ((int64_t)F.nx * F.ny));
+        int i, j, k;
+        unflatten(id, F.nx, F.ny, i, j, k);
         double num, diag;
         fine_stencil(F, x, i, j, k, id, num, diag);
         const double a = f[id] - (num - diag * x[id]);
@@ -1432,11 +1126,13 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
 // w = P A y (fluid mean removed) fused with the inner products of `mode` (see k_project)
 static hipError_t apply_projected(ibm_grid *g, const double *y, double *w, const double *other, double *rh, int mode,
                                   int op, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply_fluid, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), y, w, g->partials);
+    int nparts = 0;
+    hipError_t e = launch_apply_fluid(fine64(g), y, w, g->partials, &nparts, s);
+    if (e != hipSuccess) return e;
     if (g->ng > 0)
         hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), y, w, g->g_scale, g->nx,
                            g->ny, g->nz, g->type, 0);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, nparts, 1, g->sc, (int)K_MU);
     hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, w, other, rh, g->sc, mode,
                        g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, op);

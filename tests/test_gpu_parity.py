@@ -34,6 +34,7 @@ CASES = {
     "wing_small": lambda: I.wing(96, 48, 48),
     "spheres48": lambda: I.multibody(48, n_bodies=3, level=3),
     "spheres_ragged": lambda: I.multibody(88, n_bodies=2, level=3),
+    "wing_odd": lambda: I.wing(75, 42, 40),  # odd nx: unpaired column path of the smoother
 }
 
 _cache = {}

@@ -1,0 +1,122 @@
+"""Serving loop: trace generation and admission arithmetic on the CPU; on the GPU, served
+results equal the same requests run alone (bit for bit), match the oracle, and the summed
+footprint of the requests in flight never exceeds the budget."""
+import numpy as np
+import pytest
+
+from paper_2505_17287_amd import inputs as I
+
+SMALL = (32, 48)
+
+
+def test_trace_is_seeded_and_poisson():
+    from paper_2505_17287_amd import serve
+    a = serve.make_trace(6, qps=50.0, sizes=SMALL)
+    b = serve.make_trace(6, qps=50.0, sizes=SMALL)
+    assert [q.name for q in a] == [q.name for q in b]
+    assert [q.arrival for q in a] == [q.arrival for q in b]
+    assert a[0].arrival == 0.0 and all(x.arrival <= y.arrival for x, y in zip(a, a[1:]))
+    sat = serve.make_trace(0, qps=None, requests=a)
+    assert all(q.arrival == 0.0 for q in sat) and [q.rid for q in sat] == [q.rid for q in a]
+    # exponential gaps: the mean of many gaps is close to 1/qps
+    many = serve.make_trace(0, qps=10.0, requests=[a[0]] * 4000)
+    gaps = np.diff([q.arrival for q in many])
+    assert abs(gaps.mean() - 0.1) < 0.01
+
+
+def test_footprint_covers_fields_and_grows_with_size():
+    from paper_2505_17287_amd import serve
+    reqs = serve.make_trace(4, qps=None, sizes=(32, 64))
+    for q in reqs:
+        f64 = serve.footprint(q, "fp64")
+        mixed = serve.footprint(q, "mixed")
+        assert f64 > serve.field_bytes(q) > 0
+        assert mixed > f64
+    small = [q for q in reqs if q.shape[0] == 32]
+    big = [q for q in reqs if q.shape[0] == 64]
+    if small and big:
+        assert serve.footprint(big[0], "fp64") > serve.footprint(small[0], "fp64")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.gpu
+def test_served_equals_alone_bitwise():
+    _torch()
+    from paper_2505_17287_amd import serve
+    trace = serve.make_trace(6, qps=None, sizes=SMALL)
+    print("serving", [q.name for q in trace], flush=True)
+    srv = serve.Server(slots=3, precision="mixed", keep_results=True)
+    try:
+        mixed, _ = srv.run(trace)
+    finally:
+        srv.close()
+    assert len({r.slot for r in mixed}) > 1
+    alone_srv = serve.Server(slots=1, precision="mixed", keep_results=True)
+    try:
+        for q, r in zip(trace, mixed):
+            (a,), _ = alone_srv.run([q])
+            assert r.status == 0 and a.status == 0
+            assert r.cycles == a.cycles
+            assert np.array_equal(r.p, a.p) and np.array_equal(r.u, a.u), q.name
+    finally:
+        alone_srv.close()
+
+
+@pytest.mark.gpu
+def test_served_projection_matches_oracle():
+    torch = _torch()
+    from oracle import OracleProblem
+    from paper_2505_17287_amd import serve
+    (q,) = serve.make_trace(1, qps=None, sizes=(32,))
+    srv = serve.Server(slots=1, precision="fp64", rel_tol=1e-12, keep_results=True)
+    try:
+        (r,), _ = srv.run([q])
+        with torch.cuda.stream(srv.slots[0].stream):
+            u, v, w = (a.cpu().numpy() for a in srv._velocity(q))
+    finally:
+        srv.close()
+    P = OracleProblem(q.xf, q.yf, q.zf)
+    P.set_mesh(q.verts, q.tris)
+    P.classify()
+    P.build_stencils()
+    u1, v1, w1, pr, sr, f = P.project(u, v, w, dt=1.0, rel_tol=1e-12, max_cycles=400)
+    assert r.status == 0
+    assert np.max(np.abs(r.u - u1)) <= 1e-9 * np.max(np.abs(u1))
+    act = P.types() != 2
+    pg = r.p - r.p[act].mean()
+    pr = pr - pr[act].mean()
+    assert np.max(np.abs(pg[act] - pr[act])) <= 1e-9 * np.max(np.abs(pr[act]))
+
+
+@pytest.mark.gpu
+def test_admission_keeps_footprint_within_budget():
+    _torch()
+    from paper_2505_17287_amd import serve
+    trace = serve.make_trace(6, qps=None, sizes=SMALL)
+    fps = {q.rid: serve.footprint(q, "mixed") for q in trace}
+    budget = max(fps.values()) + min(fps.values()) // 2   # room for one large or two small requests at most
+    srv = serve.Server(slots=4, budget_bytes=budget, precision="mixed")
+    try:
+        res, _ = srv.run(trace)
+    finally:
+        srv.close()
+    events = sorted([(r.admitted, fps[r.rid]) for r in res] + [(r.done, -fps[r.rid]) for r in res],
+                    key=lambda e: (e[0], e[1]))
+    live = 0
+    for _, d in events:
+        live += d
+        assert live <= budget
+    assert all(r.status == 0 for r in res)
+    # a request larger than the whole budget is refused before anything runs
+    small = serve.Server(slots=1, budget_bytes=min(fps.values()) - 1, precision="mixed")
+    try:
+        with pytest.raises(ValueError):
+            small.run(trace[:1])
+    finally:
+        small.close()
