@@ -78,9 +78,10 @@ def cpu_baseline(wl, cycles_needed, n_sample_cycles=3):
 
 
 def probe(args):
-    """Fixed kernel sequence for rocprofv3 counter runs (one launch per kernel of interest):
-    a 512 MiB device-to-device copy (calibration: 512 MiB read + 512 MiB written), then the
-    level-0 fused sweep in FP64 on the workload."""
+    """Fixed kernel sequence for rocprofv3 counter runs: a 512 MiB device-to-device copy
+    (calibration: 512 MiB read + 512 MiB written), four level-0 fused sweeps in FP64 on the
+    workload, then one projection with a single BiCGStab step (every solver kernel once or
+    a few times)."""
     import numpy as np
     import torch
 
@@ -103,6 +104,10 @@ def probe(args):
     g.debug_sweep(p, f, lam=0.0, n=4, refresh=False)
     torch.cuda.synchronize()
     log("probe: 4 fused FP64 sweeps on %s done" % wl.name)
+    u, v, w = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in wl.velocity())
+    g.project(u, v, w, dt=1.0, fixed_cycles=1)
+    torch.cuda.synchronize()
+    log("probe: one projection with a single BiCGStab step done")
     print(json.dumps({"probe": wl.name, "cells": wl.ncells, "copy_bytes": int(src.numel() * 8)}), flush=True)
 
 
@@ -208,7 +213,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for hardware counters: a plain device copy of known size for "
-                         "calibration, then 4 fused FP64 sweeps of level 0 on the workload")
+                         "calibration, 4 fused FP64 sweeps of level 0, one single-step projection")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
