@@ -851,12 +851,13 @@ __global__ void k_fluid_volume(const uint8_t *__restrict__ type, int nx, int ny,
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_sum_partials(const double *partials, int n, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int q = 0; q < n; ++q) s += partials[q];
-        *out = s;
-    }
+// one workgroup of 256 threads; fixed combination order, so the sum is reproducible
+__global__ void __launch_bounds__(256) k_sum_partials(const double *partials, int n, double *out) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) s += partials[q];
+    s = block_sum<256>(s, sh, threadIdx.x);
+    if (threadIdx.x == 0) *out = s;
 }
 
 // open child-face area over the coarse centre distance, for each cell's low face along d
@@ -928,7 +929,7 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
     // level-0 fluid volume
     hipLaunchKernelGGL(k_fluid_volume, dim3(RED_BLOCKS), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, g->w0[0],
                        g->w0[1], g->w0[2], g->partials);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, g->partials, RED_BLOCKS, &g->sc->vol[0]);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, &g->sc->vol[0]);
     for (int l = 1; l < g->nlev; ++l) {
         LevelHost &Fh = g->lev[l - 1], &Ch = g->lev[l];
         LevelDims F, C;
@@ -946,7 +947,7 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
         double *parts = (double *)g->crossings;  // geometry scratch is free after classification
         hipLaunchKernelGGL(k_coarsen_active, dim3(nb), dim3(256), 0, s, F, C, fa, fine_type, Ch.active, Ch.w64[0],
                            Ch.w64[1], Ch.w64[2], parts);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, parts, (int)nb, &g->sc->vol[l]);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, parts, (int)nb, &g->sc->vol[l]);
         const double *fw0 = (l == 1) ? g->w0[0] : Fh.w64[0];
         const double *fw1 = (l == 1) ? g->w0[1] : Fh.w64[1];
         const double *fw2 = (l == 1) ? g->w0[2] : Fh.w64[2];

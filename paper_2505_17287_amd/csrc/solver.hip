@@ -283,68 +283,116 @@ __global__ void k_sweepC(Coarse<T> L, int colour) {
     }
 }
 
+
 // coarsest level in one workgroup: e = 0 (set by the restriction), n sweeps, then removal
 // of the volume-weighted mean over the active cells
+// nsweeps red-black sweeps of a level of at most SMALL_LEVEL cells in one workgroup of 1024
+// threads: each thread keeps the coefficients of up to SMALL_CPT cells in registers and the
+// iterate lives in LDS, so a colour costs one LDS pass and one barrier instead of a launch.
+// remove_mean != 0 (coarsest level): afterwards subtract the volume-weighted mean over the
+// active cells.  The arithmetic of every cell is that of k_sweepC.
+constexpr int SMALL_CPT = 4, SMALL_LEVEL = 1024 * SMALL_CPT;
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_smallC(Coarse<T> L, int nsweeps, const double *vol, int remove_mean) {
+    __shared__ double sh[NT / 64];
+    __shared__ T es[NT * SMALL_CPT];
+    __shared__ double mean_s;
+    const int NC = L.n[0] * L.n[1] * L.n[2];
+    const int sy = L.n[0], sz = L.n[0] * L.n[1];
+    const T mu = (T)(*L.mu);
+    // per cell: bit 0 live, 1 active, 2 colour, 3..8 neighbour present at -x,+x,-y,+y,-z,+z
+    unsigned fl[SMALL_CPT];
+    T txm[SMALL_CPT], txp[SMALL_CPT], tym[SMALL_CPT], typ[SMALL_CPT], tzm[SMALL_CPT], tzp[SMALL_CPT];
+    T rhs[SMALL_CPT], dg[SMALL_CPT];
+#pragma unroll
+    for (int c = 0; c < SMALL_CPT; ++c) {
+        const int id = (int)threadIdx.x + NT * c;
+        const bool live = id < NC;
+        const int idc = live ? id : 0;
+        const int I = idc % L.n[0], J = (idc / L.n[0]) % L.n[1], K = idc / sz;
+        const bool hx0 = I > 0, hx1 = I < L.n[0] - 1, hy0 = J > 0, hy1 = J < L.n[1] - 1, hz0 = K > 0,
+                   hz1 = K < L.n[2] - 1;
+        fl[c] = (live ? 1u : 0u) | ((live && L.active[idc] != 0) ? 2u : 0u) | ((unsigned)((I + J + K) & 1) << 2) |
+                (hx0 ? 8u : 0u) | (hx1 ? 16u : 0u) | (hy0 ? 32u : 0u) | (hy1 ? 64u : 0u) | (hz0 ? 128u : 0u) |
+                (hz1 ? 256u : 0u);
+        txm[c] = L.Tl[0][idc];
+        txp[c] = hx1 ? L.Tl[0][idc + 1] : T(0);
+        tym[c] = L.Tl[1][idc];
+        typ[c] = hy1 ? L.Tl[1][idc + sy] : T(0);
+        tzm[c] = L.Tl[2][idc];
+        tzp[c] = hz1 ? L.Tl[2][idc + sz] : T(0);
+        const T v = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+        rhs[c] = L.R[idc] - v * mu;
+        T d = txm[c] + txp[c];
+        d = d + tym[c];
+        d = d + typ[c];
+        d = d + tzm[c];
+        d = d + tzp[c];
+        dg[c] = d;
+        if (live) es[id] = L.e[id];
+    }
+    __syncthreads();
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        for (unsigned col = 0; col < 2; ++col) {
+#pragma unroll
+            for (int c = 0; c < SMALL_CPT; ++c) {
+                const int id = (int)threadIdx.x + NT * c;
+                const unsigned f = fl[c];
+                if ((f & 2u) && ((f >> 2) & 1u) == col && dg[c] > T(0)) {
+                    T num = 0;
+                    num = num + ((f & 8u) ? txm[c] * es[id - 1] : T(0));
+                    num = num + ((f & 16u) ? txp[c] * es[id + 1] : T(0));
+                    num = num + ((f & 32u) ? tym[c] * es[id - sy] : T(0));
+                    num = num + ((f & 64u) ? typ[c] * es[id + sy] : T(0));
+                    num = num + ((f & 128u) ? tzm[c] * es[id - sz] : T(0));
+                    num = num + ((f & 256u) ? tzp[c] * es[id + sz] : T(0));
+                    es[id] = (num - rhs[c]) / dg[c];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double mean = 0.0;
+    if (remove_mean) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < SMALL_CPT; ++c) {
+            const int id = (int)threadIdx.x + NT * c;
+            if (fl[c] & 2u) {
+                const int I = id % L.n[0], J = (id / L.n[0]) % L.n[1], K = id / sz;
+                acc += (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)es[id];
+            }
+        }
+        const double tot = block_sum<NT>(acc, sh, threadIdx.x);
+        if (threadIdx.x == 0) mean_s = (*vol > 0.0) ? tot / *vol : 0.0;
+        __syncthreads();
+        mean = mean_s;
+    }
+#pragma unroll
+    for (int c = 0; c < SMALL_CPT; ++c) {
+        const int id = (int)threadIdx.x + NT * c;
+        if (fl[c] & 1u) L.e[id] = (remove_mean && (fl[c] & 2u)) ? es[id] - (T)mean : es[id];
+    }
+}
+
+// the smallest workgroup that holds the level (one wave for the tiny levels, where barriers
+// are nearly free)
+template <typename T>
+static void launch_smallC(const Coarse<T> &L, int64_t ncell, int nsweeps, const double *vol, int remove_mean,
+                          hipStream_t s) {
+    if (ncell <= 64 * SMALL_CPT)
+        hipLaunchKernelGGL((k_smallC<T, 64>), dim3(1), dim3(64), 0, s, L, nsweeps, vol, remove_mean);
+    else if (ncell <= 256 * SMALL_CPT)
+        hipLaunchKernelGGL((k_smallC<T, 256>), dim3(1), dim3(256), 0, s, L, nsweeps, vol, remove_mean);
+    else
+        hipLaunchKernelGGL((k_smallC<T, 1024>), dim3(1), dim3(1024), 0, s, L, nsweeps, vol, remove_mean);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(1024) k_coarsest(Coarse<T> L, int nsweeps, const double *vol) {
     __shared__ double sh[16];
-    __shared__ T es[1024];
     const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
     const T mu = (T)(*L.mu);
-    if (NC <= 1024) {
-        // one cell per thread: coefficients in registers, the iterate in LDS
-        const int id = threadIdx.x;
-        const bool live = id < NC;
-        int I = 0, J = 0, K = 0;
-        T txm = 0, txp = 0, tym = 0, typ = 0, tzm = 0, tzp = 0, rhs = 0, d = 0;
-        bool act = false;
-        const int sy = L.n[0], sz = L.n[0] * L.n[1];
-        if (live) {
-            I = id % L.n[0];
-            J = (id / L.n[0]) % L.n[1];
-            K = id / sz;
-            act = L.active[id] != 0;
-            txm = L.Tl[0][id];
-            txp = (I < L.n[0] - 1) ? L.Tl[0][id + 1] : T(0);
-            tym = L.Tl[1][id];
-            typ = (J < L.n[1] - 1) ? L.Tl[1][id + sy] : T(0);
-            tzm = L.Tl[2][id];
-            tzp = (K < L.n[2] - 1) ? L.Tl[2][id + sz] : T(0);
-            const T v = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
-            rhs = L.R[id] - v * mu;
-            d = txm + txp;
-            d = d + tym;
-            d = d + typ;
-            d = d + tzm;
-            d = d + tzp;
-            es[id] = L.e[id];
-        }
-        __syncthreads();
-        const int colour = (I + J + K) & 1;
-        for (int s = 0; s < nsweeps; ++s) {
-            for (int c = 0; c < 2; ++c) {
-                if (live && act && colour == c && d > T(0)) {
-                    T num = 0;
-                    num = num + (I > 0 ? txm * es[id - 1] : T(0));
-                    num = num + (I < L.n[0] - 1 ? txp * es[id + 1] : T(0));
-                    num = num + (J > 0 ? tym * es[id - sy] : T(0));
-                    num = num + (J < L.n[1] - 1 ? typ * es[id + sy] : T(0));
-                    num = num + (K > 0 ? tzm * es[id - sz] : T(0));
-                    num = num + (K < L.n[2] - 1 ? tzp * es[id + sz] : T(0));
-                    es[id] = (num - rhs) / d;
-                }
-                __syncthreads();
-            }
-        }
-        double acc = 0.0;
-        if (live && act) acc = (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)es[id];
-        __shared__ double mean_s;
-        const double tot = block_sum<1024>(acc, sh, threadIdx.x);
-        if (threadIdx.x == 0) mean_s = (*vol > 0.0) ? tot / *vol : 0.0;
-        __syncthreads();
-        if (live) L.e[id] = act ? es[id] - (T)mean_s : es[id];
-        return;
-    }
     for (int s = 0; s < nsweeps; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             for (int64_t id = threadIdx.x; id < NC; id += 1024) {
@@ -640,9 +688,13 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
         for (int l = 1; l < Lc; ++l) {
             Coarse<T> L = coarse_view<T>(g, l);
             int nb = nblk(g->lev[l].ncell());
-            for (int q = 0; q < o->nu1; ++q) {
-                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
-                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+            if (g->lev[l].ncell() <= SMALL_LEVEL) {
+                if (o->nu1 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu1, &g->sc->vol[l], 0, s);
+            } else {
+                for (int q = 0; q < o->nu1; ++q) {
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+                }
             }
             Coarse<T> C = coarse_view<T>(g, l + 1);
             Halv H;
@@ -652,15 +704,22 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
                                &g->sc->mu[l + 1]);
         }
-        hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(1024), 0, s, coarse_view<T>(g, Lc), o->coarsest_sweeps,
-                           &g->sc->vol[Lc]);
+        if (g->lev[Lc].ncell() <= SMALL_LEVEL)
+            launch_smallC<T>(coarse_view<T>(g, Lc), g->lev[Lc].ncell(), o->coarsest_sweeps, &g->sc->vol[Lc], 1, s);
+        else
+            hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(1024), 0, s, coarse_view<T>(g, Lc), o->coarsest_sweeps,
+                               &g->sc->vol[Lc]);
         for (int l = Lc - 1; l >= 1; --l) {
             Coarse<T> L = coarse_view<T>(g, l);
             int nb = nblk(g->lev[l].ncell());
             hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), prolong_tab(g, l));
-            for (int q = 0; q < o->nu2; ++q) {
-                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
-                hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+            if (g->lev[l].ncell() <= SMALL_LEVEL) {
+                if (o->nu2 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu2, &g->sc->vol[l], 0, s);
+            } else {
+                for (int q = 0; q < o->nu2; ++q) {
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+                }
             }
         }
         {
@@ -844,17 +903,17 @@ __global__ void __launch_bounds__(NORM_NT) k_divmax(Fine<double> F, const double
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void k_max_finalize(const double *partials, int nb, Scalars *sc) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double m = 0.0;
-        for (int q = 0; q < nb; ++q) m = fmax(m, partials[q]);
-        sc->div_max = m;
-    }
+__global__ void __launch_bounds__(256) k_max_finalize(const double *partials, int nb, Scalars *sc) {
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) m = fmax(m, partials[q]);
+    m = block_max<256>(m, sh, threadIdx.x);
+    if (threadIdx.x == 0) sc->div_max = m;
 }
 
 hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s) {
     hipLaunchKernelGGL(k_divmax, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), u, v, w, g->partials);
-    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(64), 0, s, g->partials, RED_BLOCKS, g->sc);
+    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc);
     return hipGetLastError();
 }
 
