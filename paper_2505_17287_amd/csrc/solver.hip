@@ -267,20 +267,26 @@ __global__ void k_finalize_mu(const double *partials, int n, const double *vol, 
 // coarse levels: red-black GS on  sum_F T_F (e_NB - e_C) = R_C - V_C mu
 // =======================================================================================
 
+// one colour of a red-black sweep of a coarse level: a thread per cell of that colour (in
+// each x pair of a row exactly one cell has the colour), every load issued before the
+// activity test
 template <typename T>
 __global__ void k_sweepC(Coarse<T> L, int colour) {
-    const int64_t NC = (int64_t)L.n[0] * L.n[1] * L.n[2];
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= NC) return;
-    int I, J, K;
-    unflatten(id, L.n[0], L.n[1], I, J, K);
-    if (((I + J + K) & 1) != colour || !L.active[id]) return;
+    const int hx = (L.n[0] + 1) >> 1;
+    const int64_t npair = (int64_t)hx * L.n[1] * L.n[2];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npair) return;
+    int P, J, K;
+    unflatten(t, hx, L.n[1], P, J, K);
+    const int I = 2 * P + ((J + K + colour) & 1);
+    if (I >= L.n[0]) return;
+    const int64_t id = ((int64_t)K * L.n[1] + J) * L.n[0] + I;
+    const uint8_t act = L.active[id];
     T num, diag;
     coarse_stencil(L, L.e, I, J, K, id, num, diag);
-    if (diag > T(0)) {
-        const T vol = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
-        L.e[id] = (num - (L.R[id] - vol * (T)(*L.mu))) / diag;
-    }
+    const T vol = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+    const T r = L.R[id];
+    if (act && diag > T(0)) L.e[id] = (num - (r - vol * (T)(*L.mu))) / diag;
 }
 
 
@@ -372,6 +378,274 @@ __global__ void __launch_bounds__(NT) k_smallC(Coarse<T> L, int nsweeps, const d
     for (int c = 0; c < SMALL_CPT; ++c) {
         const int id = (int)threadIdx.x + NT * c;
         if (fl[c] & 1u) L.e[id] = (remove_mean && (fl[c] & 2u)) ? es[id] - (T)mean : es[id];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// The tail of the V-cycle in one workgroup: every level from the first one with at most
+// SMALL_LEVEL cells down to the coarsest.  Pre-smoothing, residual and restriction, the
+// coarsest sweeps with mean removal, prolongation and post-smoothing of these levels run
+// with the iterates in LDS, separated by workgroup barriers; right-hand sides and
+// coefficients stay in global memory (they are small and cache-resident).  Per cell the
+// arithmetic is that of k_sweepC / k_resrestrictC / k_prolongC / k_coarsest.
+// ---------------------------------------------------------------------------------------
+constexpr int TAIL_MAX = 8, TAIL_NT = 1024, TAIL_E = 2 * SMALL_LEVEL;
+
+template <typename T>
+struct TailArgs {
+    int nl;                   // tail levels; index 0 is the first, nl - 1 the coarsest
+    Coarse<T> L[TAIL_MAX];    // level views (e and R in global memory)
+    ProlongTab P[TAIL_MAX];   // P[q]: table of tail level q from level q + 1
+    int off[TAIL_MAX];        // offset of each level's iterate in LDS
+    const double *vol[TAIL_MAX];
+    double *mu[TAIL_MAX];
+    const double *partials;   // restriction partials of tail level 0
+    int nparts, nu1, nu2, ncoarse;
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_ijk(const Coarse<T> &L, int id, int &I, int &J, int &K) {
+    I = id % L.n[0];
+    J = (id / L.n[0]) % L.n[1];
+    K = id / (L.n[0] * L.n[1]);
+}
+
+// ns red-black sweeps of one level on its LDS iterate es (coefficients of a thread's cells in
+// registers, as in k_smallC); remove_mean: subtract the volume-weighted active mean
+template <typename T>
+__device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const double *vol, int remove_mean,
+                            double *sh, double *mean_s) {
+    const int NC = L.n[0] * L.n[1] * L.n[2];
+    const int sy = L.n[0], sz = L.n[0] * L.n[1];
+    unsigned fl[SMALL_CPT];
+    T txm[SMALL_CPT], txp[SMALL_CPT], tym[SMALL_CPT], typ[SMALL_CPT], tzm[SMALL_CPT], tzp[SMALL_CPT];
+    T rhs[SMALL_CPT], dg[SMALL_CPT];
+#pragma unroll
+    for (int c = 0; c < SMALL_CPT; ++c) {
+        const int id = (int)threadIdx.x + TAIL_NT * c;
+        const bool live = id < NC;
+        const int idc = live ? id : 0;
+        int I, J, K;
+        tail_ijk(L, idc, I, J, K);
+        const bool hx1 = I < L.n[0] - 1, hy1 = J < L.n[1] - 1, hz1 = K < L.n[2] - 1;
+        fl[c] = (live ? 1u : 0u) | ((live && L.active[idc] != 0) ? 2u : 0u) | ((unsigned)((I + J + K) & 1) << 2) |
+                (I > 0 ? 8u : 0u) | (hx1 ? 16u : 0u) | (J > 0 ? 32u : 0u) | (hy1 ? 64u : 0u) | (K > 0 ? 128u : 0u) |
+                (hz1 ? 256u : 0u);
+        txm[c] = L.Tl[0][idc];
+        txp[c] = hx1 ? L.Tl[0][idc + 1] : T(0);
+        tym[c] = L.Tl[1][idc];
+        typ[c] = hy1 ? L.Tl[1][idc + sy] : T(0);
+        tzm[c] = L.Tl[2][idc];
+        tzp[c] = hz1 ? L.Tl[2][idc + sz] : T(0);
+        const T v = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+        rhs[c] = L.R[idc] - v * mu;
+        T d = txm[c] + txp[c];
+        d = d + tym[c];
+        d = d + typ[c];
+        d = d + tzm[c];
+        d = d + tzp[c];
+        dg[c] = d;
+    }
+    // a level that the first wave holds alone (cells of a thread are tid + TAIL_NT c, so with
+    // NC <= 64 only lanes of wave 0 own cells) is swept by that wave with wave-level
+    // ordering of its LDS traffic, without workgroup barriers
+    const bool one_wave = NC <= 64;
+    if (one_wave) {
+        if (threadIdx.x < 64) {
+            for (int sw = 0; sw < ns; ++sw) {
+                for (unsigned col = 0; col < 2; ++col) {
+                    const int id = (int)threadIdx.x;
+                    const unsigned f = fl[0];
+                    if ((f & 2u) && ((f >> 2) & 1u) == col && dg[0] > T(0)) {
+                        T num = 0;
+                        num = num + ((f & 8u) ? txm[0] * es[id - 1] : T(0));
+                        num = num + ((f & 16u) ? txp[0] * es[id + 1] : T(0));
+                        num = num + ((f & 32u) ? tym[0] * es[id - sy] : T(0));
+                        num = num + ((f & 64u) ? typ[0] * es[id + sy] : T(0));
+                        num = num + ((f & 128u) ? tzm[0] * es[id - sz] : T(0));
+                        num = num + ((f & 256u) ? tzp[0] * es[id + sz] : T(0));
+                        es[id] = (num - rhs[0]) / dg[0];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        for (int sw = 0; sw < ns; ++sw) {
+            for (unsigned col = 0; col < 2; ++col) {
+#pragma unroll
+                for (int c = 0; c < SMALL_CPT; ++c) {
+                    const int id = (int)threadIdx.x + TAIL_NT * c;
+                    const unsigned f = fl[c];
+                    if ((f & 2u) && ((f >> 2) & 1u) == col && dg[c] > T(0)) {
+                        T num = 0;
+                        num = num + ((f & 8u) ? txm[c] * es[id - 1] : T(0));
+                        num = num + ((f & 16u) ? txp[c] * es[id + 1] : T(0));
+                        num = num + ((f & 32u) ? tym[c] * es[id - sy] : T(0));
+                        num = num + ((f & 64u) ? typ[c] * es[id + sy] : T(0));
+                        num = num + ((f & 128u) ? tzm[c] * es[id - sz] : T(0));
+                        num = num + ((f & 256u) ? tzp[c] * es[id + sz] : T(0));
+                        es[id] = (num - rhs[c]) / dg[c];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (remove_mean) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < SMALL_CPT; ++c) {
+            const int id = (int)threadIdx.x + TAIL_NT * c;
+            if (fl[c] & 2u) {
+                int I, J, K;
+                tail_ijk(L, id, I, J, K);
+                acc += (double)((L.w[0][I] * L.w[1][J]) * L.w[2][K]) * (double)es[id];
+            }
+        }
+        const double tot = block_sum<TAIL_NT>(acc, sh, threadIdx.x);
+        if (threadIdx.x == 0) *mean_s = (*vol > 0.0) ? tot / *vol : 0.0;
+        __syncthreads();
+        const T m = (T)*mean_s;
+#pragma unroll
+        for (int c = 0; c < SMALL_CPT; ++c) {
+            const int id = (int)threadIdx.x + TAIL_NT * c;
+            if (fl[c] & 2u) es[id] -= m;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
+    __shared__ T es[TAIL_E];           // iterates of all tail levels
+    __shared__ T rs[SMALL_LEVEL];      // residual of the level being restricted
+    __shared__ double sh[TAIL_NT / 64];
+    __shared__ double mean_s, mu_s[TAIL_MAX];
+    const int tid = threadIdx.x;
+    {   // mu of the first tail level from the restriction partials
+        double a = 0.0;
+        for (int q = tid; q < A.nparts; q += TAIL_NT) a += A.partials[q];
+        const double tot = block_sum<TAIL_NT>(a, sh, tid);
+        if (tid == 0) {
+            const double m = (*A.vol[0] > 0.0) ? tot / *A.vol[0] : 0.0;
+            mu_s[0] = m;
+            *A.mu[0] = m;
+        }
+        const int n0 = A.L[0].n[0] * A.L[0].n[1] * A.L[0].n[2];
+        for (int id = tid; id < n0; id += TAIL_NT) es[A.off[0] + id] = T(0);
+        __syncthreads();
+    }
+    // down: smooth, restrict
+    for (int q = 0; q + 1 < A.nl; ++q) {
+        const Coarse<T> &L = A.L[q];
+        T *e = es + A.off[q];
+        const T mu = (T)mu_s[q];
+        tail_smooth<T>(L, e, A.nu1, mu, A.vol[q], 0, sh, &mean_s);
+        const int NC = L.n[0] * L.n[1] * L.n[2];
+        const int sy = L.n[0], sz = L.n[0] * L.n[1];
+        for (int id = tid; id < NC; id += TAIL_NT) {
+            int I, J, K;
+            tail_ijk(L, id, I, J, K);
+            T r = T(0);
+            if (L.active[id]) {
+                const T txm = L.Tl[0][id], txp = (I < L.n[0] - 1) ? L.Tl[0][id + 1] : T(0);
+                const T tym = L.Tl[1][id], typ = (J < L.n[1] - 1) ? L.Tl[1][id + sy] : T(0);
+                const T tzm = L.Tl[2][id], tzp = (K < L.n[2] - 1) ? L.Tl[2][id + sz] : T(0);
+                T sm = 0;
+                sm = sm + (I > 0 ? txm * e[id - 1] : T(0));
+                sm = sm + (I < L.n[0] - 1 ? txp * e[id + 1] : T(0));
+                sm = sm + (J > 0 ? tym * e[id - sy] : T(0));
+                sm = sm + (J < L.n[1] - 1 ? typ * e[id + sy] : T(0));
+                sm = sm + (K > 0 ? tzm * e[id - sz] : T(0));
+                sm = sm + (K < L.n[2] - 1 ? tzp * e[id + sz] : T(0));
+                T d = txm + txp;
+                d = d + tym;
+                d = d + typ;
+                d = d + tzm;
+                d = d + tzp;
+                const T vol = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
+                r = (L.R[id] - vol * mu) - (sm - d * e[id]);
+            }
+            rs[id] = r;
+        }
+        __syncthreads();
+        const Coarse<T> &C = A.L[q + 1];
+        const int *h = A.P[q].halved;
+        const int NCC = C.n[0] * C.n[1] * C.n[2];
+        double psum = 0.0;
+        for (int cid = tid; cid < NCC; cid += TAIL_NT) {
+            int I, J, K;
+            tail_ijk(C, cid, I, J, K);
+            const int i0 = h[0] ? 2 * I : I, i1 = h[0] ? 2 * I + 1 : I;
+            const int j0 = h[1] ? 2 * J : J, j1 = h[1] ? 2 * J + 1 : J;
+            const int k0 = h[2] ? 2 * K : K, k1 = h[2] ? 2 * K + 1 : K;
+            T R = 0;
+            for (int k = k0; k <= k1; ++k)
+                for (int j = j0; j <= j1; ++j)
+                    for (int i = i0; i <= i1; ++i) {
+                        const int id = (k * L.n[1] + j) * L.n[0] + i;
+                        if (L.active[id]) R += rs[id];
+                    }
+            C.R[cid] = R;
+            es[A.off[q + 1] + cid] = T(0);
+            psum += (double)R;
+        }
+        const double tot = block_sum<TAIL_NT>(psum, sh, tid);
+        if (tid == 0) {
+            const double m = (*A.vol[q + 1] > 0.0) ? tot / *A.vol[q + 1] : 0.0;
+            mu_s[q + 1] = m;
+            *A.mu[q + 1] = m;
+        }
+        __syncthreads();
+    }
+    // coarsest
+    {
+        const int q = A.nl - 1;
+        tail_smooth<T>(A.L[q], es + A.off[q], A.ncoarse, (T)mu_s[q], A.vol[q], 1, sh, &mean_s);
+    }
+    // up: prolong, smooth
+    for (int q = A.nl - 2; q >= 0; --q) {
+        const Coarse<T> &L = A.L[q], &C = A.L[q + 1];
+        const ProlongTab &P = A.P[q];
+        T *e = es + A.off[q];
+        const T *ec = es + A.off[q + 1];
+        const int NC = L.n[0] * L.n[1] * L.n[2];
+        for (int id = tid; id < NC; id += TAIL_NT) {
+            if (!L.active[id]) continue;
+            int i, j, k;
+            tail_ijk(L, id, i, j, k);
+            const int ix[2] = {P.lo[0][i], P.hi[0][i]}, iy[2] = {P.lo[1][j], P.hi[1][j]},
+                      iz[2] = {P.lo[2][k], P.hi[2][k]};
+            const double tx = P.t[0][i], ty = P.t[1][j], tz = P.t[2][k];
+            const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+            const int nx_ = (ix[0] == ix[1]) ? 1 : 2, ny_ = (iy[0] == iy[1]) ? 1 : 2, nz_ = (iz[0] == iz[1]) ? 1 : 2;
+            bool all = true;
+            double sv = 0.0;
+            for (int c = 0; c < nz_; ++c)
+                for (int b = 0; b < ny_; ++b)
+                    for (int a = 0; a < nx_; ++a) {
+                        const int cid = (iz[c] * C.n[1] + iy[b]) * C.n[0] + ix[a];
+                        if (!C.active[cid]) all = false;
+                        sv += (wx[a] * wy[b]) * wz[c] * (double)ec[cid];
+                    }
+            if (!all) {
+                const int pi = P.halved[0] ? i / 2 : i, pj = P.halved[1] ? j / 2 : j, pk = P.halved[2] ? k / 2 : k;
+                sv = (double)ec[(pk * C.n[1] + pj) * C.n[0] + pi];
+            }
+            e[id] = (T)((double)e[id] + sv);
+        }
+        __syncthreads();
+        tail_smooth<T>(L, e, A.nu2, (T)mu_s[q], A.vol[q], 0, sh, &mean_s);
+    }
+    // the first tail level's correction goes back to global memory for the prolongation above
+    {
+        const Coarse<T> &L = A.L[0];
+        const int NC = L.n[0] * L.n[1] * L.n[2];
+        for (int id = tid; id < NC; id += TAIL_NT) L.e[id] = es[A.off[0] + id];
     }
 }
 
@@ -675,25 +949,36 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
         *cur = 1 - *cur;
     }
     if (g->nlev > 1) {
+        const int Lc = g->nlev - 1;
+        // the tail: every level from the first one with at most SMALL_LEVEL cells down to the
+        // coarsest, run by one workgroup (levels only shrink, so all of them are small)
+        int lt = Lc + 1;
+        for (int l = 1; l <= Lc; ++l)
+            if (g->lev[l].ncell() <= SMALL_LEVEL) {
+                lt = l;
+                break;
+            }
+        const bool tail = lt <= Lc && Lc - lt + 1 <= TAIL_MAX;
+        const int Lb = tail ? lt : Lc;  // levels 1 .. Lb-1 run level by level
+        int nparts = 0;                 // restriction partials into level Lb
         {
             Coarse<T> C1 = coarse_view<T>(g, 1);
-            int nb = 0;
-            if ((e = launch_restrict0<T>(F, bufs[*cur], rhs, lam, C1, g->lev[1].halved, g->partials, &nb, s)) !=
+            if ((e = launch_restrict0<T>(F, bufs[*cur], rhs, lam, C1, g->lev[1].halved, g->partials, &nparts, s)) !=
                 hipSuccess)
                 return e;
-            hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nb, &g->sc->vol[1],
-                               &g->sc->mu[1]);
+            if (!(tail && lt == 1))
+                hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nparts, &g->sc->vol[1],
+                                   &g->sc->mu[1]);
         }
-        const int Lc = g->nlev - 1;
-        for (int l = 1; l < Lc; ++l) {
+        for (int l = 1; l < Lb; ++l) {
             Coarse<T> L = coarse_view<T>(g, l);
-            int nb = nblk(g->lev[l].ncell());
+            const int nbh = nblk((int64_t)((g->lev[l].n[0] + 1) / 2) * g->lev[l].n[1] * g->lev[l].n[2]);
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
                 if (o->nu1 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu1, &g->sc->vol[l], 0, s);
             } else {
                 for (int q = 0; q < o->nu1; ++q) {
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 0);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 1);
                 }
             }
             Coarse<T> C = coarse_view<T>(g, l + 1);
@@ -701,24 +986,47 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             for (int d = 0; d < 3; ++d) H.h[d] = g->lev[l + 1].halved[d];
             int nbc = nblk(g->lev[l + 1].ncell());
             hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, H, g->partials);
-            hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
-                               &g->sc->mu[l + 1]);
+            nparts = nbc;
+            if (!(tail && l + 1 == lt))
+                hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
+                                   &g->sc->mu[l + 1]);
         }
-        if (g->lev[Lc].ncell() <= SMALL_LEVEL)
+        if (tail) {
+            TailArgs<T> A;
+            A.nl = Lc - lt + 1;
+            int off = 0;
+            for (int q = 0; q < A.nl; ++q) {
+                const int l = lt + q;
+                A.L[q] = coarse_view<T>(g, l);
+                if (q + 1 < A.nl) A.P[q] = prolong_tab(g, l);
+                A.off[q] = off;
+                off += (int)g->lev[l].ncell();
+                A.vol[q] = &g->sc->vol[l];
+                A.mu[q] = &g->sc->mu[l];
+            }
+            A.partials = g->partials;
+            A.nparts = nparts;
+            A.nu1 = o->nu1;
+            A.nu2 = o->nu2;
+            A.ncoarse = o->coarsest_sweeps;
+            hipLaunchKernelGGL(k_tailC<T>, dim3(1), dim3(TAIL_NT), 0, s, A);
+        } else if (g->lev[Lc].ncell() <= SMALL_LEVEL) {
             launch_smallC<T>(coarse_view<T>(g, Lc), g->lev[Lc].ncell(), o->coarsest_sweeps, &g->sc->vol[Lc], 1, s);
-        else
+        } else {
             hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(1024), 0, s, coarse_view<T>(g, Lc), o->coarsest_sweeps,
                                &g->sc->vol[Lc]);
-        for (int l = Lc - 1; l >= 1; --l) {
+        }
+        for (int l = Lb - 1; l >= 1; --l) {
             Coarse<T> L = coarse_view<T>(g, l);
             int nb = nblk(g->lev[l].ncell());
+            const int nbh = nblk((int64_t)((g->lev[l].n[0] + 1) / 2) * g->lev[l].n[1] * g->lev[l].n[2]);
             hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), prolong_tab(g, l));
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
                 if (o->nu2 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu2, &g->sc->vol[l], 0, s);
             } else {
                 for (int q = 0; q < o->nu2; ++q) {
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 0);
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nb), dim3(256), 0, s, L, 1);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 0);
+                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 1);
                 }
             }
         }
