@@ -337,11 +337,245 @@ __global__ void __launch_bounds__(ZM_NT)
     zm_block_sum_store<ZM_NT>(psum, partials);
 }
 
+// ---- paired-column variants (nx even) ----------------------------------------------------
+// A thread owns two adjacent columns (16-byte loads); a 256-thread workgroup covers 64 x 8
+// columns and a wave holds two rows (lanes l and l + 32).  For the restriction a thread's
+// pair is exactly one coarse cell's x children and a wave's row pair its y children, so the
+// in-plane part of the sum needs no LDS and no barrier.
+constexpr int ZP_TX = 64, ZP_TY = 8, ZP_NT = 256;
+
+ZTiles ztiles2(int nx, int ny, int nz) {
+    ZTiles t;
+    t.ntx = (nx + ZP_TX - 1) / ZP_TX;
+    t.nty = (ny + ZP_TY - 1) / ZP_TY;
+    const int64_t per_slab = (int64_t)t.ntx * t.nty;
+    int nchunk = (int)std::max<int64_t>(1, (int64_t)8 * device_cu_count() / per_slab);
+    nchunk = std::min(nchunk, std::max(1, nz / 2));
+    int kc = (nz + nchunk - 1) / nchunk;
+    kc += kc & 1;
+    nchunk = (nz + kc - 1) / kc;
+    t.kc = kc;
+    t.ntiles = (int)(per_slab * nchunk);
+    t.grid = ((t.ntiles + 7) / 8) * 8;
+    return t;
+}
+
+struct ZPos2 {
+    bool live;
+    int i0, j, k0, k1, half;  // first column of the pair, row, chunk, lane half (row within the wave)
+};
+
+__device__ __forceinline__ ZPos2 zpos2(const ZTiles &t, int nz) {
+    ZPos2 z;
+    const int per = gridDim.x >> 3;
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    z.live = logical < t.ntiles;
+    int tile = logical;
+    const int txi = tile % t.ntx;
+    tile /= t.ntx;
+    const int tyi = tile % t.nty;
+    const int chunk = tile / t.nty;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    z.half = lane >> 5;
+    z.i0 = txi * ZP_TX + 2 * (lane & 31);
+    z.j = tyi * ZP_TY + 2 * wave + z.half;
+    z.k0 = chunk * t.kc;
+    z.k1 = min(nz, z.k0 + t.kc);
+    return z;
+}
+
+template <typename T>
+struct Vec2T;
+template <>
+struct Vec2T<double> {
+    using type = double2;
+};
+template <>
+struct Vec2T<float> {
+    using type = float2;
+};
+
+template <typename T>
+struct RPlane2 {
+    typename Vec2T<T>::type pp, ym, yp, fv;  // pairs: p(k+1), p(j-1), p(j+1), f(k)
+    T xm, xp;                                // p(i0-1), p(i0+2) of plane k
+    T azm, azp, wz;
+    uint16_t tt;                             // the two cell types
+};
+
+template <typename T>
+__global__ void __launch_bounds__(ZP_NT)
+    k_restrict0_zm2(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
+                    Coarse<T> C, int hx, int hy, int hz, ZTiles t, double *partials) {
+    using V = typename Vec2T<T>::type;
+    const ZPos2 z = zpos2(t, F.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i0 < nx && z.j < ny;  // nx even: the pair is wholly inside or outside
+    const int ic = min(z.i0, nx - 2), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic + 2 < nx, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 2 : 1, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const T axm0 = F.axm[ic], axp0 = F.axp[ic], axm1 = F.axm[ic + 1], axp1 = F.axp[ic + 1];
+    const T aym = F.aym[jc], ayp = F.ayp[jc];
+    const T vxy0 = F.wx[ic] * F.wy[jc], vxy1 = F.wx[ic + 1] * F.wy[jc];
+    const T lam = *lamp;
+    const bool writer = in && (!hy || z.half == 0);
+    const int I = hx ? ic >> 1 : ic, J = hy ? jc >> 1 : jc;
+    auto ld = [=](int k) -> RPlane2<T> {
+        RPlane2<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = *reinterpret_cast<const V *>(p + base + (kk < nz - 1 ? plane : 0));
+        d.ym = *reinterpret_cast<const V *>(p + base + dym);
+        d.yp = *reinterpret_cast<const V *>(p + base + dyp);
+        d.fv = *reinterpret_cast<const V *>(f + base);
+        d.xm = p[base + dxm];
+        d.xp = p[base + dxp];
+        d.tt = *reinterpret_cast<const uint16_t *>(F.type + base);
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        d.wz = F.wz[kk];
+        return d;
+    };
+    V pm = (z.k0 > 0) ? *reinterpret_cast<const V *>(p + (int64_t)(z.k0 - 1) * plane + rowoff) : V{T(0), T(0)};
+    V pc = *reinterpret_cast<const V *>(p + (int64_t)z.k0 * plane + rowoff);
+    T acc0 = 0, acc1 = 0;
+    double psum = 0.0;
+#define IBM_RESTRICT_PLANE2(D, kk)                                                                                \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        const bool z0_ = k_ > 0, z1_ = k_ < nz - 1;                                                                \
+        T n0, d0, n1, d1;                                                                                          \
+        zm_stencil<T>(axm0, axp0, aym, ayp, (D).azm, (D).azp, hx0, true, hy0, hy1, z0_, z1_, (D).xm, pc.y,        \
+                      (D).ym.x, (D).yp.x, pm.x, (D).pp.x, n0, d0);                                                 \
+        zm_stencil<T>(axm1, axp1, aym, ayp, (D).azm, (D).azp, true, hx1, hy0, hy1, z0_, z1_, pc.x, (D).xp,        \
+                      (D).ym.y, (D).yp.y, pm.y, (D).pp.y, n1, d1);                                                 \
+        const T r0 = ((D).fv.x - lam) - (n0 - d0 * pc.x);                                                          \
+        const T r1 = ((D).fv.y - lam) - (n1 - d1 * pc.y);                                                          \
+        const bool ok_ = in && k_ < z.k1;                                                                          \
+        T v0 = (ok_ && ((D).tt & 0xff) == T_FLUID) ? (vxy0 * (D).wz) * r0 : T(0);                                  \
+        T v1 = (ok_ && ((D).tt >> 8) == T_FLUID) ? (vxy1 * (D).wz) * r1 : T(0);                                    \
+        if (hx) {                                                                                                  \
+            v0 = v0 + v1;                                                                                          \
+            v1 = T(0);                                                                                             \
+        }                                                                                                          \
+        if (hy) {                                                                                                  \
+            v0 = v0 + __shfl_xor(v0, 32, 64);                                                                      \
+            v1 = v1 + __shfl_xor(v1, 32, 64);                                                                      \
+        }                                                                                                          \
+        acc0 = (hz && (k_ & 1)) ? acc0 + v0 : v0;                                                                  \
+        acc1 = (hz && (k_ & 1)) ? acc1 + v1 : v1;                                                                  \
+        if ((!hz || (k_ & 1)) && writer && k_ < z.k1) {                                                            \
+            const int K_ = hz ? k_ >> 1 : k_;                                                                      \
+            const int64_t cid = ((int64_t)K_ * C.n[1] + J) * C.n[0] + I;                                           \
+            C.R[cid] = acc0;                                                                                       \
+            C.e[cid] = T(0);                                                                                       \
+            psum += (double)acc0;                                                                                  \
+            if (!hx) {                                                                                             \
+                C.R[cid + 1] = acc1;                                                                               \
+                C.e[cid + 1] = T(0);                                                                               \
+                psum += (double)acc1;                                                                              \
+            }                                                                                                      \
+        }                                                                                                          \
+        pm = pc;                                                                                                   \
+        pc = (D).pp;                                                                                               \
+    }
+    RPlane2<T> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_RESTRICT_PLANE2(qa, k);
+        qa = ld(k + 2);
+        IBM_RESTRICT_PLANE2(qb, k + 1);
+    }
+#undef IBM_RESTRICT_PLANE2
+    zm_block_sum_store<ZP_NT>(psum, partials);
+}
+
+__global__ void __launch_bounds__(ZP_NT)
+    k_apply_fluid_zm2(Fine<double> F, const double *__restrict__ y, double *__restrict__ w, ZTiles t,
+                      double *partials) {
+    using V = double2;
+    const ZPos2 z = zpos2(t, F.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i0 < nx && z.j < ny;
+    const int ic = min(z.i0, nx - 2), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic + 2 < nx, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 2 : 1, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const double axm0 = F.axm[ic], axp0 = F.axp[ic], axm1 = F.axm[ic + 1], axp1 = F.axp[ic + 1];
+    const double aym = F.aym[jc], ayp = F.ayp[jc];
+    const double vxy0 = F.wx[ic] * F.wy[jc], vxy1 = F.wx[ic + 1] * F.wy[jc];
+    auto ld = [=](int k) -> RPlane2<double> {
+        RPlane2<double> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = *reinterpret_cast<const V *>(y + base + (kk < nz - 1 ? plane : 0));
+        d.ym = *reinterpret_cast<const V *>(y + base + dym);
+        d.yp = *reinterpret_cast<const V *>(y + base + dyp);
+        d.xm = y[base + dxm];
+        d.xp = y[base + dxp];
+        d.tt = *reinterpret_cast<const uint16_t *>(F.type + base);
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        d.wz = F.wz[kk];
+        return d;
+    };
+    V ym1 = (z.k0 > 0) ? *reinterpret_cast<const V *>(y + (int64_t)(z.k0 - 1) * plane + rowoff) : V{0.0, 0.0};
+    V yc = *reinterpret_cast<const V *>(y + (int64_t)z.k0 * plane + rowoff);
+    double psum = 0.0;
+#define IBM_APPLY_PLANE2(D, kk)                                                                                   \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        const bool z0_ = k_ > 0, z1_ = k_ < nz - 1;                                                                \
+        double n0, d0, n1, d1;                                                                                     \
+        zm_stencil<double>(axm0, axp0, aym, ayp, (D).azm, (D).azp, hx0, true, hy0, hy1, z0_, z1_, (D).xm, yc.y,   \
+                           (D).ym.x, (D).yp.x, ym1.x, (D).pp.x, n0, d0);                                           \
+        zm_stencil<double>(axm1, axp1, aym, ayp, (D).azm, (D).azp, true, hx1, hy0, hy1, z0_, z1_, yc.x, (D).xp,   \
+                           (D).ym.y, (D).yp.y, ym1.y, (D).pp.y, n1, d1);                                           \
+        const double a0 = (in && ((D).tt & 0xff) == T_FLUID) ? n0 - d0 * yc.x : 0.0;                              \
+        const double a1 = (in && ((D).tt >> 8) == T_FLUID) ? n1 - d1 * yc.y : 0.0;                                \
+        if (in && k_ < z.k1) {                                                                                     \
+            V o_;                                                                                                  \
+            o_.x = a0;                                                                                             \
+            o_.y = a1;                                                                                             \
+            *reinterpret_cast<V *>(w + (int64_t)k_ * plane + rowoff) = o_;                                         \
+            psum += (vxy0 * (D).wz) * a0;                                                                          \
+            psum += (vxy1 * (D).wz) * a1;                                                                          \
+        }                                                                                                          \
+        ym1 = yc;                                                                                                  \
+        yc = (D).pp;                                                                                               \
+    }
+    RPlane2<double> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_APPLY_PLANE2(qa, k);
+        qa = ld(k + 2);
+        IBM_APPLY_PLANE2(qb, k + 1);
+    }
+#undef IBM_APPLY_PLANE2
+    zm_block_sum_store<ZP_NT>(psum, partials);
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
                             const int halved[3], double *partials, int *nparts, hipStream_t s) {
+    if ((F.nx & 1) == 0 && F.nx >= 2) {
+        const ZTiles t = ztiles2(F.nx, F.ny, F.nz);
+        hipLaunchKernelGGL(k_restrict0_zm2<T>, dim3(t.grid), dim3(ZP_NT), 0, s, F, p, f, lam, C, halved[0],
+                           halved[1], halved[2], t, partials);
+        *nparts = t.grid;
+        return hipGetLastError();
+    }
     const ZTiles t = ztiles(F.nx, F.ny, F.nz);
     hipLaunchKernelGGL(k_restrict0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, p, f, lam, C, halved[0], halved[1],
                        halved[2], t, partials);
@@ -359,6 +593,12 @@ hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coar
 
 hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
                               hipStream_t s) {
+    if ((F.nx & 1) == 0 && F.nx >= 2) {
+        const ZTiles t = ztiles2(F.nx, F.ny, F.nz);
+        hipLaunchKernelGGL(k_apply_fluid_zm2, dim3(t.grid), dim3(ZP_NT), 0, s, F, y, w, t, partials);
+        *nparts = t.grid;
+        return hipGetLastError();
+    }
     const ZTiles t = ztiles(F.nx, F.ny, F.nz);
     hipLaunchKernelGGL(k_apply_fluid_zm, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, w, t, partials);
     *nparts = t.grid;

@@ -551,13 +551,35 @@ __device__ __forceinline__ void consider_tri(const double *V, const int32_t *T, 
     }
 }
 
-__global__ void k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, int nz,
-                          const double *__restrict__ xc, const double *__restrict__ yc, const double *__restrict__ zc,
-                          const double *__restrict__ V, const int32_t *__restrict__ T, int64_t nt,
-                          const int32_t *__restrict__ boff, const int32_t *__restrict__ bent, BucketGrid G, double *gbi,
-                          int32_t *gtri) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
+// One wave per ghost: the lanes stride over the triangles of each bucket in the search box,
+// then the wave keeps the lexicographic minimum of (squared distance, triangle index).  The
+// candidate set and the tie rule are those of a sequential scan, so the result is the same.
+constexpr int CLOSEST_WAVES = 4;
+__device__ __forceinline__ void closest_wave_min(double &best, int32_t &bt, double bq[3]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int32_t ot = __shfl_xor(bt, off, 64);
+        const double o0 = __shfl_xor(bq[0], off, 64), o1 = __shfl_xor(bq[1], off, 64),
+                     o2 = __shfl_xor(bq[2], off, 64);
+        if (ob < best || (ob == best && ot < bt)) {
+            best = ob;
+            bt = ot;
+            bq[0] = o0;
+            bq[1] = o1;
+            bq[2] = o2;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64 * CLOSEST_WAVES)
+    k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, int nz, const double *__restrict__ xc,
+              const double *__restrict__ yc, const double *__restrict__ zc, const double *__restrict__ V,
+              const int32_t *__restrict__ T, int64_t nt, const int32_t *__restrict__ boff,
+              const int32_t *__restrict__ bent, BucketGrid G, double *gbi, int32_t *gtri) {
+    const int64_t g = (int64_t)blockIdx.x * CLOSEST_WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= ng) return;  // whole wave
     int64_t id = gcell[g];
     int i, j, k;
     unflatten(id, nx, ny, i, j, k);
@@ -581,7 +603,7 @@ __global__ void k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         for (int by = b0[1]; by <= b1[1]; ++by)
             for (int bx = b0[0]; bx <= b1[0]; ++bx) {
                 int b = (bz * G.nb[1] + by) * G.nb[0] + bx;
-                for (int q = boff[b]; q < boff[b + 1]; ++q) {
+                for (int q = boff[b] + lane; q < boff[b + 1]; q += 64) {
                     int32_t t = bent[q];
                     double lo[3], hi[3];
                     tri_bbox(V, T, t, lo, hi);
@@ -592,12 +614,15 @@ __global__ void k_closest(int64_t ng, const int32_t *__restrict__ gcell, int nx,
                     consider_tri(V, T, t, x, best, bt, bq);
                 }
             }
+    closest_wave_min(best, bt, bq);
     if (bt == 0x7fffffff || !(best <= r * r)) {
         // nothing within the radius: search every triangle
         best = INFINITY;
         bt = 0x7fffffff;
-        for (int64_t t = 0; t < nt; ++t) consider_tri(V, T, (int32_t)t, x, best, bt, bq);
+        for (int64_t t = lane; t < nt; t += 64) consider_tri(V, T, (int32_t)t, x, best, bt, bq);
+        closest_wave_min(best, bt, bq);
     }
+    if (lane != 0) return;
     if (two_d) bq[2] = x[2];  // prism bodies of a one-cell-thick grid: stay in the cell plane
     gbi[3 * g] = bq[0];
     gbi[3 * g + 1] = bq[1];
@@ -782,7 +807,8 @@ hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
         G.nb[d] = g->nb[d];
     }
     unsigned nb = (unsigned)((g->ng + 127) / 128);
-    hipLaunchKernelGGL(k_closest, dim3(nb), dim3(128), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
+    hipLaunchKernelGGL(k_closest, dim3((unsigned)((g->ng + CLOSEST_WAVES - 1) / CLOSEST_WAVES)),
+                       dim3(64 * CLOSEST_WAVES), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
                        g->c0[2], g->verts, g->tris, g->nt, g->bucket_off, g->bucket_ent, G, g->g_bi, g->g_tri);
     hipLaunchKernelGGL(k_weights, dim3(nb), dim3(128), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
                        g->c0[2], g->w0[0], g->w0[1], g->w0[2], g->type, g->verts, g->tris, g->g_bi, g->g_tri, g->g_n,
