@@ -23,44 +23,50 @@ namespace ibm {
 // Weights are FP64; the right-hand sides gh may be absent (homogeneous error equation).
 // =======================================================================================
 
+// Eight lanes per ghost: lane m of a group takes stencil member m (the index and weight
+// loads of a wave are contiguous and the eight gathers are in flight together), and the
+// group sums its terms with three shuffle steps.  Degenerate ghosts (mean of the fluid
+// 26-neighbours) are handled by the group's first lane.
+constexpr int REFRESH_NT = 256;
 template <typename T>
-__global__ void k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T *dst, int nx, int ny, int nz,
-                                const uint8_t *__restrict__ type, const double *__restrict__ gh) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G.ng) return;
-    const int64_t cell = G.cell[g];
+__global__ void __launch_bounds__(REFRESH_NT)
+    k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T *dst, int nx, int ny, int nz,
+                    const uint8_t *__restrict__ type, const double *__restrict__ gh) {
+    const int64_t g = ((int64_t)blockIdx.x * REFRESH_NT + threadIdx.x) >> 3;
+    const int m = threadIdx.x & 7;
+    const bool live = g < G.ng;
+    const int64_t gc = live ? g : 0;
+    const int32_t q = G.st[8 * gc + m];
+    const double beta = G.beta[8 * gc + m];
+    const unsigned gm = G.gmask[gc];
+    const int32_t flags = G.flags[gc];
+    double term = 0.0;
+    if (live && q >= 0) term = beta * (double)(((gm >> m) & 1u) ? src_ghost[q] : dst[q]);
+    term += __shfl_xor(term, 1, 64);
+    term += __shfl_xor(term, 2, 64);
+    term += __shfl_xor(term, 4, 64);
+    if (!live || m != 0) return;
+    const int64_t cell = G.cell[gc];
     double v;
-    if (G.flags[g] & GF_DEGENERATE) {
+    if (flags & GF_DEGENERATE) {
         int i, j, k;
         unflatten(cell, nx, ny, i, j, k);
-        double s = 0.0;
+        double sm = 0.0;
         int n = 0;
         for (int dk = -1; dk <= 1; ++dk)
             for (int dj = -1; dj <= 1; ++dj)
                 for (int di = -1; di <= 1; ++di) {
                     int ii = i + di, jj = j + dj, kk = k + dk;
                     if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
-                    int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
-                    if (type[q] == T_FLUID) {
-                        s += (double)dst[q];
+                    int64_t qq = ((int64_t)kk * ny + jj) * nx + ii;
+                    if (type[qq] == T_FLUID) {
+                        sm += (double)dst[qq];
                         ++n;
                     }
                 }
-        v = n ? s / n : 0.0;
+        v = n ? sm / n : 0.0;
     } else {
-        const int32_t *st = G.st + 8 * g;
-        const double *beta = G.beta + 8 * g;
-        const unsigned gm = G.gmask[g];
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int32_t q = st[m];
-            if (q >= 0) {
-                const T pv = ((gm >> m) & 1u) ? src_ghost[q] : dst[q];
-                s = s + beta[m] * (double)pv;
-            }
-        }
-        v = gh ? s + gh[g] : s;
+        v = gh ? term + gh[gc] : term;
     }
     dst[cell] = (T)v;
 }
@@ -80,7 +86,8 @@ static GhostView ghost_view(ibm_grid *g) {
 template <typename T>
 static hipError_t launch_refresh(ibm_grid *g, const T *src_ghost, T *dst, const double *gh, hipStream_t s) {
     if (g->ng == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ghost_refresh<T>, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, ghost_view(g),
+    hipLaunchKernelGGL(k_ghost_refresh<T>, dim3((unsigned)((8 * g->ng + REFRESH_NT - 1) / REFRESH_NT)),
+                       dim3(REFRESH_NT), 0, s, ghost_view(g),
                        src_ghost, dst, g->nx, g->ny, g->nz, g->type, gh);
     return hipGetLastError();
 }

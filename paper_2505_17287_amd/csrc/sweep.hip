@@ -139,6 +139,12 @@ __global__ void __launch_bounds__(BXT *BY)
     const int icv = min(max(ia, 0), nx - 2);  // pair start for the vector path (nx even)
     const int64_t rowoff0 = (int64_t)jc * nx + (VEC ? icv : ic0);
     const int64_t rowoff1 = (int64_t)jc * nx + ic1;
+    // The outermost halo rows only supply old values: their f and type loads are pointed at
+    // the adjacent row (lines the tile reads anyway), which keeps every lane's load sequence
+    // identical without streaming f and type of rows nobody updates.
+    const int jft = min(max((ty == 0) ? j + 1 : (ty == BY - 1) ? j - 1 : j, 0), ny - 1);
+    const int64_t ftoff0 = (int64_t)jft * nx + (VEC ? icv : ic0);
+    const int64_t ftoff1 = (int64_t)jft * nx + ic1;
     const T axm0 = in0 ? F.axm[ic0] : T(0), axp0 = in0 ? F.axp[ic0] : T(0);
     const T axm1 = in1 ? F.axm[ic1] : T(0), axp1 = in1 ? F.axp[ic1] : T(0);
     const T aym = rowin ? F.aym[jc] : T(0), ayp = rowin ? F.ayp[jc] : T(0);
@@ -159,20 +165,20 @@ __global__ void __launch_bounds__(BXT *BY)
         const int64_t base = (int64_t)min(max(k, 0), klast) * plane;
         if constexpr (VEC) {
             const V o = *reinterpret_cast<const V *>(pin + base + rowoff0);
-            const V fv = *reinterpret_cast<const V *>(f + base + rowoff0);
+            const V fv = *reinterpret_cast<const V *>(f + base + ftoff0);
             d.o0 = o.x;
             d.o1 = o.y;
             d.f0 = fv.x;
             d.f1 = fv.y;
-            if constexpr (VEC) d.tt = *reinterpret_cast<const uint16_t *>(F.type + base + rowoff0);
+            if constexpr (VEC) d.tt = *reinterpret_cast<const uint16_t *>(F.type + base + ftoff0);
         } else {
             d.o0 = pin[base + rowoff0];
             d.o1 = pin[base + rowoff1];
-            d.f0 = f[base + rowoff0];
-            d.f1 = f[base + rowoff1];
+            d.f0 = f[base + ftoff0];
+            d.f1 = f[base + ftoff1];
             if constexpr (!VEC) {
-                d.t0 = F.type[base + rowoff0];
-                d.t1 = F.type[base + rowoff1];
+                d.t0 = F.type[base + ftoff0];
+                d.t1 = F.type[base + ftoff1];
             }
         }
         return d;
