@@ -116,6 +116,7 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     ibm_grid tmp;
     ibm_grid *G = g ? g : &tmp;
     G->type = P.take<uint8_t>(N);
+    G->inject0 = P.take<uint8_t>(N);
     G->p2 = P.take<double>(N);
     G->frhs = P.take<double>(N);
     if (prec == IBM_MIXED) {

@@ -196,12 +196,13 @@ __global__ void __launch_bounds__(ZM_NT)
 // ---- prolongation ------------------------------------------------------------------------
 // pnext = pcur + P e_1 on fluid cells (ghost cells are refreshed afterwards).  The loads of
 // plane k+1 (its z table entry, fine values and the coarse contributors) are issued before
-// plane k is computed.
+// plane k is computed.  A cell with an inactive contributor takes its parent's value; the
+// parent is the first contributor on every axis (lo of the table), and the per-cell flag is
+// fixed by the geometry (computed with the hierarchy), so no activity is read here.
 template <typename T>
 struct PPlane {
     T pv, e[8];
-    uint8_t ty, act[8];
-    int pk;
+    uint8_t ty, inj;
     double tz;
     bool twoz;
 };
@@ -220,7 +221,6 @@ __global__ void __launch_bounds__(ZM_NT)
     const double tx = P.t[0][ic], ty = P.t[1][jc];
     const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty};
     const bool twox = ix[0] != ix[1], twoy = iy[0] != iy[1];
-    const int pi = P.halved[0] ? ic / 2 : ic, pj = P.halved[1] ? jc / 2 : jc;
     const int64_t cny = C.n[1], cnx = C.n[0];
     auto ld = [=](int k) -> PPlane<T> {
         PPlane<T> d;
@@ -229,38 +229,31 @@ __global__ void __launch_bounds__(ZM_NT)
         const int iz[2] = {P.lo[2][kk], P.hi[2][kk]};
         d.tz = P.t[2][kk];
         d.twoz = iz[0] != iz[1];
-        d.pk = P.halved[2] ? kk / 2 : kk;
         d.ty = F.type[base];
+        d.inj = F.inject[base];
         d.pv = pcur[base];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const int64_t cid = ((int64_t)iz[c] * cny + iy[b]) * cnx + ix[a];
-                    d.act[4 * c + 2 * b + a] = C.active[cid];
-                    d.e[4 * c + 2 * b + a] = C.e[cid];
-                }
+                for (int a = 0; a < 2; ++a)
+                    d.e[4 * c + 2 * b + a] = C.e[((int64_t)iz[c] * cny + iy[b]) * cnx + ix[a]];
         return d;
     };
 #define IBM_PROLONG_PLANE(D, kk)                                                                                  \
     {                                                                                                              \
         const int k_ = (kk);                                                                                       \
         const double wz[2] = {1.0 - (D).tz, (D).tz};                                                               \
-        bool all = true;                                                                                           \
         double s = 0.0;                                                                                            \
         _Pragma("unroll") for (int c = 0; c < 2; ++c) _Pragma("unroll") for (int b = 0; b < 2; ++b)                \
             _Pragma("unroll") for (int a = 0; a < 2; ++a) {                                                        \
             const bool ok = (a == 0 || twox) && (b == 0 || twoy) && (c == 0 || (D).twoz);                          \
             const double term = (wx[a] * wy[b]) * wz[c] * (double)(D).e[4 * c + 2 * b + a];                       \
-            if (ok) {                                                                                              \
-                if (!(D).act[4 * c + 2 * b + a]) all = false;                                                      \
-                s += term;                                                                                         \
-            }                                                                                                      \
+            if (ok) s += term;                                                                                     \
         }                                                                                                          \
+        if ((D).inj) s = (double)(D).e[0];                                                                         \
         if (in && k_ < z.k1 && (D).ty == T_FLUID) {                                                                \
-            if (!all) s = (double)C.e[((int64_t)(D).pk * cny + pj) * cnx + pi];                                    \
             pnext[(int64_t)k_ * plane + rowoff] = (T)((double)(D).pv + s);                                         \
         }                                                                                                          \
     }

@@ -887,6 +887,28 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *partials, in
 }
 
 // open child-face area over the coarse centre distance, for each cell's low face along d
+// Level-0 cells whose trilinear prolongation would read an inactive level-1 cell: those fluid
+// cells take the parent's value instead (the parent is always the first contributor).  The
+// flag is fixed by the geometry, so it is computed once with the hierarchy.
+__global__ void k_inject0(int nx, int ny, int nz, const uint8_t *__restrict__ type, LevelDims C,
+                          const uint8_t *__restrict__ cactive, const int *lo0, const int *hi0, const int *lo1,
+                          const int *hi1, const int *lo2, const int *hi2, uint8_t *inject) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    uint8_t v = 0;
+    if (type[id] == T_FLUID) {
+        int i, j, k;
+        unflatten(id, nx, ny, i, j, k);
+        const int ix[2] = {lo0[i], hi0[i]}, iy[2] = {lo1[j], hi1[j]}, iz[2] = {lo2[k], hi2[k]};
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    if (!cactive[((int64_t)iz[c] * C.n[1] + iy[b]) * C.n[0] + ix[a]]) v = 1;
+    }
+    inject[id] = v;
+}
+
 __global__ void k_face_T(LevelDims F, LevelDims C, int d, const uint8_t *__restrict__ fine_active, bool fine_is_type,
                          const double *__restrict__ fw0, const double *__restrict__ fw1, const double *__restrict__ fw2,
                          const double *__restrict__ cc, double *T64, float *T32) {
@@ -984,6 +1006,17 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
             hipLaunchKernelGGL(k_prolong_tab, dim3((Fh.n[d] + 127) / 128), dim3(128), 0, s, Fh.n[d], Ch.n[d],
                                Ch.halved[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
         }
+    }
+    if (g->nlev > 1) {
+        const LevelHost &F0 = g->lev[0], &C1 = g->lev[1];
+        LevelDims C;
+        for (int d = 0; d < 3; ++d) {
+            C.n[d] = C1.n[d];
+            C.h[d] = C1.halved[d];
+        }
+        hipLaunchKernelGGL(k_inject0, dim3((unsigned)((g->N + 255) / 256)), dim3(256), 0, s, g->nx, g->ny, g->nz,
+                           g->type, C, C1.active, F0.plo[0], F0.phi[0], F0.plo[1], F0.phi[1], F0.plo[2], F0.phi[2],
+                           g->inject0);
     }
     return hipGetLastError();
 }

@@ -44,6 +44,7 @@ struct Fine {  // level-0 operator view in precision T
     const T *axm, *axp, *aym, *ayp, *azm, *azp;
     const T *wx, *wy, *wz;
     const uint8_t *type;
+    const uint8_t *inject;  // 1: fluid cell whose prolongation has an inactive coarse contributor
 };
 
 template <typename T>
@@ -179,6 +180,7 @@ struct ibm_grid {
     int device = 0;
     // level-0 device arrays
     uint8_t *type = nullptr;
+    uint8_t *inject0 = nullptr;            // per cell: prolongation falls back to injection
     double *p2 = nullptr;                  // second FP64 pressure buffer
     double *frhs = nullptr;                // projection right-hand side
     float *e32a = nullptr, *e32b = nullptr, *r32 = nullptr;

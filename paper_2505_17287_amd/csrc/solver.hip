@@ -111,6 +111,7 @@ static Fine<double> fine64(ibm_grid *g) {
     F.wy = g->w0[1];
     F.wz = g->w0[2];
     F.type = g->type;
+    F.inject = g->inject0;
     return F;
 }
 static Fine<float> fine32(ibm_grid *g) {
@@ -128,6 +129,7 @@ static Fine<float> fine32(ibm_grid *g) {
     F.wy = g->w0f[1];
     F.wz = g->w0f[2];
     F.type = g->type;
+    F.inject = g->inject0;
     return F;
 }
 template <typename T>
@@ -417,16 +419,28 @@ __device__ __forceinline__ void tail_ijk(const Coarse<T> &L, int id, int &I, int
     K = id / (L.n[0] * L.n[1]);
 }
 
-// ns red-black sweeps of one level on its LDS iterate es (coefficients of a thread's cells in
-// registers, as in k_smallC); remove_mean: subtract the volume-weighted active mean
+// prolongation into a tail level from the next coarser one (both held in LDS)
 template <typename T>
-__device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const double *vol, int remove_mean,
-                            double *sh, double *mean_s) {
+struct TailUp {
+    const T *ec;           // coarser iterate
+    const uint8_t *cact;   // coarser active flags
+    int cn0, cn1;          // coarser x and y sizes
+    const ProlongTab *P;   // table of this level from the coarser one
+};
+
+// One tail level in one workgroup: optional prolongation from the coarser level (up leg),
+// ns red-black sweeps on the LDS iterate es, optional removal of the volume-weighted active
+// mean (coarsest level), optional residual into rs (down leg).  A thread owns cells
+// tid + TAIL_NT c and keeps their coefficients in registers through all three phases; the
+// sweep multiplies by the reciprocal of the diagonal.  act: the level's active flags (LDS).
+template <typename T>
+__device__ void tail_smooth(const Coarse<T> &L, T *es, const uint8_t *act, int ns, T mu, const double *vol,
+                            int remove_mean, const TailUp<T> *up, T *rs, double *sh, double *mean_s) {
     const int NC = L.n[0] * L.n[1] * L.n[2];
     const int sy = L.n[0], sz = L.n[0] * L.n[1];
     unsigned fl[SMALL_CPT];
     T txm[SMALL_CPT], txp[SMALL_CPT], tym[SMALL_CPT], typ[SMALL_CPT], tzm[SMALL_CPT], tzp[SMALL_CPT];
-    T rhs[SMALL_CPT], dg[SMALL_CPT];
+    T rhs[SMALL_CPT], inv[SMALL_CPT];
 #pragma unroll
     for (int c = 0; c < SMALL_CPT; ++c) {
         const int id = (int)threadIdx.x + TAIL_NT * c;
@@ -435,7 +449,7 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
         int I, J, K;
         tail_ijk(L, idc, I, J, K);
         const bool hx1 = I < L.n[0] - 1, hy1 = J < L.n[1] - 1, hz1 = K < L.n[2] - 1;
-        fl[c] = (live ? 1u : 0u) | ((live && L.active[idc] != 0) ? 2u : 0u) | ((unsigned)((I + J + K) & 1) << 2) |
+        fl[c] = (live ? 1u : 0u) | ((live && act[idc] != 0) ? 2u : 0u) | ((unsigned)((I + J + K) & 1) << 2) |
                 (I > 0 ? 8u : 0u) | (hx1 ? 16u : 0u) | (J > 0 ? 32u : 0u) | (hy1 ? 64u : 0u) | (K > 0 ? 128u : 0u) |
                 (hz1 ? 256u : 0u);
         txm[c] = L.Tl[0][idc];
@@ -451,8 +465,30 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
         d = d + typ[c];
         d = d + tzm[c];
         d = d + tzp[c];
-        dg[c] = d;
+        inv[c] = d > T(0) ? T(1) / d : T(0);
+        if (up && (fl[c] & 2u)) {
+            // trilinear from the 2 x 2 x 2 nearest coarser centres, or the parent's value when
+            // one of them is inactive (the parent is the first contributor on every axis)
+            const ProlongTab &P = *up->P;
+            const int ix[2] = {P.lo[0][I], P.hi[0][I]}, iy[2] = {P.lo[1][J], P.hi[1][J]},
+                      iz[2] = {P.lo[2][K], P.hi[2][K]};
+            const double tx = P.t[0][I], ty = P.t[1][J], tz = P.t[2][K];
+            const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
+            const int nx_ = (ix[0] == ix[1]) ? 1 : 2, ny_ = (iy[0] == iy[1]) ? 1 : 2, nz_ = (iz[0] == iz[1]) ? 1 : 2;
+            bool all = true;
+            double sv = 0.0;
+            for (int cz = 0; cz < nz_; ++cz)
+                for (int b = 0; b < ny_; ++b)
+                    for (int a = 0; a < nx_; ++a) {
+                        const int cid = (iz[cz] * up->cn1 + iy[b]) * up->cn0 + ix[a];
+                        if (!up->cact[cid]) all = false;
+                        sv += (wx[a] * wy[b]) * wz[cz] * (double)up->ec[cid];
+                    }
+            if (!all) sv = (double)up->ec[(iz[0] * up->cn1 + iy[0]) * up->cn0 + ix[0]];
+            es[id] = (T)((double)es[id] + sv);  // the thread's own cell: no other thread reads it yet
+        }
     }
+    if (up) __syncthreads();
     // a level that the first wave holds alone (cells of a thread are tid + TAIL_NT c, so with
     // NC <= 64 only lanes of wave 0 own cells) is swept by that wave with wave-level
     // ordering of its LDS traffic, without workgroup barriers
@@ -463,7 +499,7 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
                 for (unsigned col = 0; col < 2; ++col) {
                     const int id = (int)threadIdx.x;
                     const unsigned f = fl[0];
-                    if ((f & 2u) && ((f >> 2) & 1u) == col && dg[0] > T(0)) {
+                    if ((f & 2u) && ((f >> 2) & 1u) == col && inv[0] > T(0)) {
                         T num = 0;
                         num = num + ((f & 8u) ? txm[0] * es[id - 1] : T(0));
                         num = num + ((f & 16u) ? txp[0] * es[id + 1] : T(0));
@@ -471,7 +507,7 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
                         num = num + ((f & 64u) ? typ[0] * es[id + sy] : T(0));
                         num = num + ((f & 128u) ? tzm[0] * es[id - sz] : T(0));
                         num = num + ((f & 256u) ? tzp[0] * es[id + sz] : T(0));
-                        es[id] = (num - rhs[0]) / dg[0];
+                        es[id] = (num - rhs[0]) * inv[0];
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -487,7 +523,7 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
                 for (int c = 0; c < SMALL_CPT; ++c) {
                     const int id = (int)threadIdx.x + TAIL_NT * c;
                     const unsigned f = fl[c];
-                    if ((f & 2u) && ((f >> 2) & 1u) == col && dg[c] > T(0)) {
+                    if ((f & 2u) && ((f >> 2) & 1u) == col && inv[c] > T(0)) {
                         T num = 0;
                         num = num + ((f & 8u) ? txm[c] * es[id - 1] : T(0));
                         num = num + ((f & 16u) ? txp[c] * es[id + 1] : T(0));
@@ -495,7 +531,7 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
                         num = num + ((f & 64u) ? typ[c] * es[id + sy] : T(0));
                         num = num + ((f & 128u) ? tzm[c] * es[id - sz] : T(0));
                         num = num + ((f & 256u) ? tzp[c] * es[id + sz] : T(0));
-                        es[id] = (num - rhs[c]) / dg[c];
+                        es[id] = (num - rhs[c]) * inv[c];
                     }
                 }
                 __syncthreads();
@@ -524,18 +560,50 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, int ns, T mu, const doubl
         }
         __syncthreads();
     }
+    if (rs) {
+        // residual (R - V mu) - (A e) of the active cells, 0 elsewhere
+#pragma unroll
+        for (int c = 0; c < SMALL_CPT; ++c) {
+            const int id = (int)threadIdx.x + TAIL_NT * c;
+            const unsigned f = fl[c];
+            if (!(f & 1u)) continue;
+            T r = T(0);
+            if (f & 2u) {
+                T sm = 0;
+                sm = sm + ((f & 8u) ? txm[c] * es[id - 1] : T(0));
+                sm = sm + ((f & 16u) ? txp[c] * es[id + 1] : T(0));
+                sm = sm + ((f & 32u) ? tym[c] * es[id - sy] : T(0));
+                sm = sm + ((f & 64u) ? typ[c] * es[id + sy] : T(0));
+                sm = sm + ((f & 128u) ? tzm[c] * es[id - sz] : T(0));
+                sm = sm + ((f & 256u) ? tzp[c] * es[id + sz] : T(0));
+                T d = txm[c] + txp[c];
+                d = d + tym[c];
+                d = d + typ[c];
+                d = d + tzm[c];
+                d = d + tzp[c];
+                r = rhs[c] - (sm - d * es[id]);
+            }
+            rs[id] = r;
+        }
+        __syncthreads();
+    }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
     __shared__ T es[TAIL_E];           // iterates of all tail levels
     __shared__ T rs[SMALL_LEVEL];      // residual of the level being restricted
+    __shared__ uint8_t acts[TAIL_E];   // active flags of all tail levels
     __shared__ double sh[TAIL_NT / 64];
     __shared__ double mean_s, mu_s[TAIL_MAX];
     const int tid = threadIdx.x;
-    {   // mu of the first tail level from the restriction partials
+    {   // mu of the first tail level from the restriction partials; activity of every level
         double a = 0.0;
         for (int q = tid; q < A.nparts; q += TAIL_NT) a += A.partials[q];
+        for (int q = 0; q < A.nl; ++q) {
+            const int n = A.L[q].n[0] * A.L[q].n[1] * A.L[q].n[2];
+            for (int id = tid; id < n; id += TAIL_NT) acts[A.off[q] + id] = A.L[q].active[id];
+        }
         const double tot = block_sum<TAIL_NT>(a, sh, tid);
         if (tid == 0) {
             const double m = (*A.vol[0] > 0.0) ? tot / *A.vol[0] : 0.0;
@@ -546,40 +614,10 @@ __global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
         for (int id = tid; id < n0; id += TAIL_NT) es[A.off[0] + id] = T(0);
         __syncthreads();
     }
-    // down: smooth, restrict
+    // down: smooth and form the residual, restrict it (inactive cells hold a zero residual)
     for (int q = 0; q + 1 < A.nl; ++q) {
         const Coarse<T> &L = A.L[q];
-        T *e = es + A.off[q];
-        const T mu = (T)mu_s[q];
-        tail_smooth<T>(L, e, A.nu1, mu, A.vol[q], 0, sh, &mean_s);
-        const int NC = L.n[0] * L.n[1] * L.n[2];
-        const int sy = L.n[0], sz = L.n[0] * L.n[1];
-        for (int id = tid; id < NC; id += TAIL_NT) {
-            int I, J, K;
-            tail_ijk(L, id, I, J, K);
-            T r = T(0);
-            if (L.active[id]) {
-                const T txm = L.Tl[0][id], txp = (I < L.n[0] - 1) ? L.Tl[0][id + 1] : T(0);
-                const T tym = L.Tl[1][id], typ = (J < L.n[1] - 1) ? L.Tl[1][id + sy] : T(0);
-                const T tzm = L.Tl[2][id], tzp = (K < L.n[2] - 1) ? L.Tl[2][id + sz] : T(0);
-                T sm = 0;
-                sm = sm + (I > 0 ? txm * e[id - 1] : T(0));
-                sm = sm + (I < L.n[0] - 1 ? txp * e[id + 1] : T(0));
-                sm = sm + (J > 0 ? tym * e[id - sy] : T(0));
-                sm = sm + (J < L.n[1] - 1 ? typ * e[id + sy] : T(0));
-                sm = sm + (K > 0 ? tzm * e[id - sz] : T(0));
-                sm = sm + (K < L.n[2] - 1 ? tzp * e[id + sz] : T(0));
-                T d = txm + txp;
-                d = d + tym;
-                d = d + typ;
-                d = d + tzm;
-                d = d + tzp;
-                const T vol = (L.w[0][I] * L.w[1][J]) * L.w[2][K];
-                r = (L.R[id] - vol * mu) - (sm - d * e[id]);
-            }
-            rs[id] = r;
-        }
-        __syncthreads();
+        tail_smooth<T>(L, es + A.off[q], acts + A.off[q], A.nu1, (T)mu_s[q], A.vol[q], 0, nullptr, rs, sh, &mean_s);
         const Coarse<T> &C = A.L[q + 1];
         const int *h = A.P[q].halved;
         const int NCC = C.n[0] * C.n[1] * C.n[2];
@@ -593,10 +631,7 @@ __global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
             T R = 0;
             for (int k = k0; k <= k1; ++k)
                 for (int j = j0; j <= j1; ++j)
-                    for (int i = i0; i <= i1; ++i) {
-                        const int id = (k * L.n[1] + j) * L.n[0] + i;
-                        if (L.active[id]) R += rs[id];
-                    }
+                    for (int i = i0; i <= i1; ++i) R += rs[(k * L.n[1] + j) * L.n[0] + i];
             C.R[cid] = R;
             es[A.off[q + 1] + cid] = T(0);
             psum += (double)R;
@@ -612,41 +647,19 @@ __global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
     // coarsest
     {
         const int q = A.nl - 1;
-        tail_smooth<T>(A.L[q], es + A.off[q], A.ncoarse, (T)mu_s[q], A.vol[q], 1, sh, &mean_s);
+        tail_smooth<T>(A.L[q], es + A.off[q], acts + A.off[q], A.ncoarse, (T)mu_s[q], A.vol[q], 1, nullptr, nullptr,
+                       sh, &mean_s);
     }
-    // up: prolong, smooth
+    // up: prolong and smooth
     for (int q = A.nl - 2; q >= 0; --q) {
-        const Coarse<T> &L = A.L[q], &C = A.L[q + 1];
-        const ProlongTab &P = A.P[q];
-        T *e = es + A.off[q];
-        const T *ec = es + A.off[q + 1];
-        const int NC = L.n[0] * L.n[1] * L.n[2];
-        for (int id = tid; id < NC; id += TAIL_NT) {
-            if (!L.active[id]) continue;
-            int i, j, k;
-            tail_ijk(L, id, i, j, k);
-            const int ix[2] = {P.lo[0][i], P.hi[0][i]}, iy[2] = {P.lo[1][j], P.hi[1][j]},
-                      iz[2] = {P.lo[2][k], P.hi[2][k]};
-            const double tx = P.t[0][i], ty = P.t[1][j], tz = P.t[2][k];
-            const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty}, wz[2] = {1.0 - tz, tz};
-            const int nx_ = (ix[0] == ix[1]) ? 1 : 2, ny_ = (iy[0] == iy[1]) ? 1 : 2, nz_ = (iz[0] == iz[1]) ? 1 : 2;
-            bool all = true;
-            double sv = 0.0;
-            for (int c = 0; c < nz_; ++c)
-                for (int b = 0; b < ny_; ++b)
-                    for (int a = 0; a < nx_; ++a) {
-                        const int cid = (iz[c] * C.n[1] + iy[b]) * C.n[0] + ix[a];
-                        if (!C.active[cid]) all = false;
-                        sv += (wx[a] * wy[b]) * wz[c] * (double)ec[cid];
-                    }
-            if (!all) {
-                const int pi = P.halved[0] ? i / 2 : i, pj = P.halved[1] ? j / 2 : j, pk = P.halved[2] ? k / 2 : k;
-                sv = (double)ec[(pk * C.n[1] + pj) * C.n[0] + pi];
-            }
-            e[id] = (T)((double)e[id] + sv);
-        }
-        __syncthreads();
-        tail_smooth<T>(L, e, A.nu2, (T)mu_s[q], A.vol[q], 0, sh, &mean_s);
+        TailUp<T> up;
+        up.ec = es + A.off[q + 1];
+        up.cact = acts + A.off[q + 1];
+        up.cn0 = A.L[q + 1].n[0];
+        up.cn1 = A.L[q + 1].n[1];
+        up.P = &A.P[q];
+        tail_smooth<T>(A.L[q], es + A.off[q], acts + A.off[q], A.nu2, (T)mu_s[q], A.vol[q], 0, &up, nullptr, sh,
+                       &mean_s);
     }
     // the first tail level's correction goes back to global memory for the prolongation above
     {
