@@ -254,6 +254,30 @@ def face_velocity(seed: int, nx: int, ny: int, nz: int):
     return u, v, w
 
 
+def cell_velocity(seed: int, nx: int, ny: int, nz: int, n_modes: int = 6, amplitude: float = 1.0):
+    """Cell-centred velocity components, shape (3, nz, ny, nx): per component a sum of
+    ``n_modes`` seeded low-wavenumber (0..3 per axis) products of cosines in index space,
+    scaled so the largest magnitude is ``amplitude``; w == 0 in 2D."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((3, nz, ny, nx))
+    idx = [(np.arange(n) + 0.5) / n for n in (nx, ny, nz)]
+    for c in range(3):
+        for _ in range(n_modes):
+            kx, ky, kz = rng.integers(0, 4, size=3)
+            ph = rng.uniform(0.0, 2.0 * np.pi, size=3)
+            a = rng.standard_normal()
+            fx = np.cos(2.0 * np.pi * kx * idx[0] + ph[0])
+            fy = np.cos(2.0 * np.pi * ky * idx[1] + ph[1])
+            fz = np.cos(2.0 * np.pi * kz * idx[2] + ph[2]) if nz > 1 else np.ones(1)
+            out[c] += a * (fz[:, None, None] * fy[None, :, None]) * fx[None, None, :]
+        mx = np.max(np.abs(out[c]))
+        if mx > 0.0:
+            out[c] *= amplitude / mx
+    if nz == 1:
+        out[2] = 0.0
+    return out
+
+
 # ----------------------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------------------
@@ -283,6 +307,13 @@ class Workload:
     def velocity(self):
         nx, ny, nz = self.shape
         return face_velocity(self.seed, nx, ny, nz)
+
+    def cell_fields(self):
+        """(u^n, H^{n-1}) of an advection-diffusion step: two seeded smooth cell-centred
+        fields of order 1 (seeds 1000 + seed and 2000 + seed)."""
+        nx, ny, nz = self.shape
+        return (cell_velocity(1000 + self.seed, nx, ny, nz),
+                cell_velocity(2000 + self.seed, nx, ny, nz))
 
 
 def cylinder2d(n: int = 128) -> Workload:
