@@ -172,6 +172,66 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *s);
 /* Level count and dims of the multigrid hierarchy (after build_ghost_stencils). */
 ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims /* 3*n_levels, may be NULL */);
 
+/* ---- advection-diffusion half-step (Section 2.1) with Dirichlet ghost rows (2.2) ---- */
+
+#define IBM_SRJ_MAX 256 /* most relaxation factors in one scheduled-Jacobi cycle */
+
+/* Options of ibm_momentum_step.  Defaults (ibm_default_momentum_opts): nu = dt = 0 (must be
+   set), later steps (first_step 0), 8 relaxation factors of the Chebyshev schedule,
+   rel_tol 1e-10, at most 200 cycles, convergence-tested. */
+typedef struct {
+    double nu;            /* kinematic viscosity (1/Re) */
+    double dt;            /* time step */
+    int first_step;       /* 1: no previous convective term (H^{n-1} := H^n, forward Euler) */
+    int srj_factors;      /* m: sweeps per scheduled-Jacobi cycle, 1..IBM_SRJ_MAX */
+    const double *omega;  /* host, m relaxation factors, NULL: ibm_srj_schedule(rho, m) */
+    double rel_tol;       /* stop when ||b - A u||_2 <= rel_tol ||b||_2 over fluid rows */
+    int max_cycles;       /* cycles of m sweeps */
+    int fixed_cycles;     /* > 0: run exactly this many cycles, no convergence test */
+} ibm_momentum_opts;
+
+typedef struct {
+    int cycles, sweeps;   /* scheduled-Jacobi cycles and sweeps run */
+    double rel_residual;  /* fluid-row residual of the input of the last sweep / ||b|| */
+    double rho;           /* half-width of the Jacobi-scaled spectrum interval [1-rho, 1+rho] */
+    double t_step;        /* seconds (host wall clock around enqueue + sync) */
+} ibm_momentum_stats;
+
+void ibm_default_momentum_opts(ibm_momentum_opts *o);
+
+/* Host only.  The m relaxation factors 1/kappa_k, kappa_k = 1 + rho cos((2k-1) pi / (2m)) the
+   Chebyshev nodes of [1 - rho, 1 + rho] (the min-max optimal factors for that interval),
+   ordered largest, smallest, second largest, ...  omega (host) receives m values.
+   IBM_E_ARG unless 0 <= rho < 1 and 1 <= m <= IBM_SRJ_MAX. */
+ibm_status ibm_srj_schedule(double rho, int m, double *omega);
+
+/* Velocity at each body intercept for the Dirichlet ghost rows (host, 3*n_G values, x y z
+   per ghost; NULL = 0, a stationary no-slip body).  Default after build_ghost_stencils: 0. */
+ibm_status ibm_set_dirichlet_data(ibm_grid *g, const double *ubi, void *stream);
+
+/* Dirichlet weights (host out, either may be NULL): beta[8*n_G] on the members listed by
+   ibm_get_ghosts' stencil, beta_g[n_G] on the intercept value; ghost row
+   u_g + sum_m beta_m u_m = (2 - beta_g) u_BI (BI is the midpoint of the ghost centre and its
+   image point).  Zero for degenerate ghosts.  Synchronises `stream`. */
+ibm_status ibm_get_dirichlet_weights(const ibm_grid *g, void *stream, double *beta, double *beta_g);
+
+/* One advection-diffusion half-step of the cell-centred velocity (Section 2.1: central
+   differences, Adams-Bashforth convection, Crank-Nicolson viscous term solved by scheduled
+   relaxed Jacobi; Section 2.2: ghost cells, here with the Dirichlet condition at BI):
+     1. dead cells of u^n are cleared and the ghost rows applied once;
+     2. H^n = -div(u u) in conservative form (face values by linear interpolation between
+        centres; no flux through the box walls), b = u^n + dt (3/2 H^n - 1/2 H^{n-1})
+        + (nu dt / 2) L u^n on fluid rows, L the pressure operator's flux Laplacian;
+     3. (I - (nu dt / 2) L) u* = b on fluid rows with the ghost rows, by cycles of m relaxed
+        Jacobi sweeps (each followed by one pass of the ghost rows), from u^n.
+   u, v, w: device [nz][ny][nx] FP64, in u^n, out u* (dead cells 0).  hu, hv, hw: device,
+   in H^{n-1} (not read when o->first_step), out H^n (0 off the fluid cells).  Uses six
+   N-arrays of the workspace (those of the pressure solver's Krylov vectors): do not overlap
+   it with a pressure solve on the same handle.  Synchronises `stream` once per cycle.
+   IBM_NOT_CONVERGED when max_cycles is reached (u* is the last iterate). */
+ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, double *hu, double *hv, double *hw,
+                             const ibm_momentum_opts *o, ibm_momentum_stats *s, void *stream);
+
 /* ---- single-step hooks for kernel-level parity tests -------------------------------- */
 
 /* n red-black sweeps of level 0 on p (device, in/out) with right-hand side rhs and shift

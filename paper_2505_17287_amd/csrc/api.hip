@@ -1,7 +1,7 @@
 // C ABI of the ghost-cell IBM projection library (declarations and contracts: include/ibm.h).
 // Host-side logic only: argument checks, workspace layout, call-order state, mesh
 // validation, multigrid level planning and the solve drivers.  Every step of the method
-// runs in the kernels of geometry.hip and solver.hip.
+// runs in the kernels of geometry.hip, sweep.hip, finepass.hip, solver.hip and momentum.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -165,6 +165,9 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     G->g_data = P.take<double>(gm);
     G->g_scale = P.take<double>(gm);
     G->g_rhs = P.take<double>(gm);
+    G->g_betaD = P.take<double>(8 * gm);
+    G->g_betaDg = P.take<double>(gm);
+    G->g_ubi = P.take<double>(3 * gm);
     for (int q = 0; q < 10; ++q) G->kv[q] = P.take<double>(N);
     for (int l = 0; l < nlev; ++l) {
         LevelHost &L = lev[l];
@@ -422,6 +425,7 @@ ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_
     HIP_TRY(hipMemsetAsync(g->counters + 5, 0, sizeof(int64_t), s), "memset");
     HIP_TRY(launch_stencils(g, s), "ghost stencils");
     if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_data, 0, sizeof(double) * g->ng, s), "memset neumann");
+    if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_ubi, 0, sizeof(double) * 3 * g->ng, s), "memset dirichlet");
     HIP_TRY(launch_ghost_h(g, s), "ghost rhs");
     HIP_TRY(launch_hierarchy(g, s), "hierarchy");
     HIP_TRY(krylov_setup(g, s), "krylov setup");
@@ -932,6 +936,157 @@ ibm_status ibm_get_profile(const ibm_grid *g, double *ms_fp64, int64_t *n_fp64, 
     if (ms_fp32) *ms_fp32 = g->prof.ms[1];
     if (n_fp32) *n_fp32 = g->prof.count[1];
     return IBM_OK;
+}
+
+// ---- advection-diffusion half-step -------------------------------------------------------
+
+void ibm_default_momentum_opts(ibm_momentum_opts *o) {
+    if (!o) return;
+    o->nu = 0.0;
+    o->dt = 0.0;
+    o->first_step = 0;
+    o->srj_factors = 8;
+    o->omega = nullptr;
+    o->rel_tol = 1e-10;
+    o->max_cycles = 200;
+    o->fixed_cycles = 0;
+}
+
+ibm_status ibm_srj_schedule(double rho, int m, double *omega) {
+    if (!omega || m < 1 || m > IBM_SRJ_MAX || !(rho >= 0.0 && rho < 1.0))
+        return fail(nullptr, IBM_E_ARG, "ibm_srj_schedule: need 0 <= rho < 1, 1 <= m <= IBM_SRJ_MAX");
+    // Chebyshev nodes of [1 - rho, 1 + rho]; the factors are their reciprocals
+    std::vector<double> w(m);
+    for (int k = 1; k <= m; ++k) w[k - 1] = 1.0 / (1.0 + rho * std::cos((2 * k - 1) * M_PI / (2.0 * m)));
+    std::sort(w.begin(), w.end(), [](double a, double b) { return a > b; });
+    // largest, smallest, second largest, second smallest, ...
+    int lo = 0, hi = m - 1, q = 0;
+    while (lo <= hi) {
+        omega[q++] = w[lo];
+        if (lo != hi) omega[q++] = w[hi];
+        ++lo;
+        --hi;
+    }
+    return IBM_OK;
+}
+
+ibm_status ibm_set_dirichlet_data(ibm_grid *g, const double *ubi, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_dirichlet_data: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_set_dirichlet_data before ibm_build_ghost_stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    if (g->ng > 0) {
+        if (ubi) {
+            for (int64_t q = 0; q < 3 * g->ng; ++q)
+                if (!std::isfinite(ubi[q])) return fail(g, IBM_E_ARG, "non-finite Dirichlet data");
+            HIP_TRY(hipMemcpyAsync(g->g_ubi, ubi, sizeof(double) * 3 * g->ng, hipMemcpyHostToDevice, s), "upload");
+        } else {
+            HIP_TRY(hipMemsetAsync(g->g_ubi, 0, sizeof(double) * 3 * g->ng, s), "memset");
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s), "dirichlet sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_get_dirichlet_weights(const ibm_grid *gc, void *stream, double *beta, double *beta_g) {
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_get_dirichlet_weights: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_get_dirichlet_weights before stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    if (g->ng > 0) {
+        if (beta) HIP_TRY(hipMemcpyAsync(beta, g->g_betaD, sizeof(double) * 8 * g->ng, hipMemcpyDeviceToHost, s), "copy");
+        if (beta_g) HIP_TRY(hipMemcpyAsync(beta_g, g->g_betaDg, sizeof(double) * g->ng, hipMemcpyDeviceToHost, s), "copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "get_dirichlet sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, double *hu, double *hv, double *hw,
+                             const ibm_momentum_opts *o, ibm_momentum_stats *st, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_momentum_step: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_momentum_step before ibm_build_ghost_stencils");
+    if (!o) return fail(g, IBM_E_ARG, "NULL options");
+    if (!u || !v || !w || !hu || !hv || !hw) return fail(g, IBM_E_ARG, "NULL velocity or convective-term array");
+    if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(g, IBM_E_ARG, "dt must be positive and finite");
+    if (!(o->nu >= 0.0) || !std::isfinite(o->nu)) return fail(g, IBM_E_ARG, "nu must be non-negative and finite");
+    const int m = o->srj_factors;
+    if (m < 1 || m > IBM_SRJ_MAX) return fail(g, IBM_E_ARG, "srj_factors out of range");
+    if (o->fixed_cycles <= 0 && (o->max_cycles < 1 || !(o->rel_tol > 0.0)))
+        return fail(g, IBM_E_ARG, "need max_cycles >= 1 and rel_tol > 0, or fixed_cycles > 0");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    const double t0 = now_s();
+    const double a = 0.5 * o->nu * o->dt;
+    // the largest diagonal flux sum (separable: the per-axis maxima add up), read once
+    if (g->diag_max < 0.0) {
+        double dmax = 0.0;
+        const int n[3] = {g->nx, g->ny, g->nz};
+        for (int d = 0; d < 3; ++d) {
+            std::vector<double> am(n[d]), ap(n[d]);
+            HIP_TRY(hipMemcpy(am.data(), g->am0[d], sizeof(double) * n[d], hipMemcpyDeviceToHost), "read metrics");
+            HIP_TRY(hipMemcpy(ap.data(), g->ap0[d], sizeof(double) * n[d], hipMemcpyDeviceToHost), "read metrics");
+            double mx = 0.0;
+            for (int i = 0; i < n[d]; ++i) mx = std::max(mx, am[i] + ap[i]);
+            dmax += mx;
+        }
+        g->diag_max = dmax;
+    }
+    const double rho = (a * g->diag_max) / (1.0 + a * g->diag_max);
+    std::vector<double> om(m);
+    if (o->omega) {
+        for (int k = 0; k < m; ++k) {
+            if (!std::isfinite(o->omega[k]) || !(o->omega[k] > 0.0)) return fail(g, IBM_E_ARG, "invalid omega");
+            om[k] = o->omega[k];
+        }
+    } else {
+        ibm_status e = ibm_srj_schedule(rho, m, om.data());
+        if (e != IBM_OK) return fail(g, e, "schedule");
+    }
+    double *uvw[3] = {u, v, w}, *hc[3] = {hu, hv, hw};
+    double *work[6] = {g->kv[0], g->kv[1], g->kv[2], g->kv[3], g->kv[4], g->kv[5]};
+    double *wk[3] = {work[3], work[4], work[5]};
+    HIP_TRY(momentum_enqueue_prep(g, uvw, hc, work, o->dt, a, o->first_step ? 1 : 0, s), "momentum rhs");
+    double *const *X = wk;
+    double *const *Y = uvw;
+    const int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
+    Scalars *hs = g->sc_host;
+    ibm_status status = IBM_OK;
+    int cyc = 0;
+    double rel = 0.0;
+    for (cyc = 1; cyc <= ncyc; ++cyc) {
+        for (int k = 0; k < m; ++k) {
+            HIP_TRY(momentum_enqueue_sweep(g, X, Y, work, a, om[k], k == m - 1, s), "srj sweep");
+            std::swap(X, Y);
+        }
+        HIP_TRY(hipMemcpyAsync(&hs->mom_b2, &g->sc->mom_b2, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "read");
+        HIP_TRY(hipStreamSynchronize(s), "cycle sync");
+        const double bn = std::sqrt(hs->mom_b2);
+        rel = bn > 0.0 ? std::sqrt(hs->mom_r2) / bn : 0.0;
+        if (!std::isfinite(rel) || !std::isfinite(hs->mom_b2)) {
+            status = IBM_E_NUMERIC;
+            break;
+        }
+        if (o->fixed_cycles <= 0 && rel <= o->rel_tol) break;
+    }
+    if (cyc > ncyc) {
+        cyc = ncyc;
+        if (o->fixed_cycles <= 0 && status == IBM_OK) status = IBM_NOT_CONVERGED;
+    }
+    if (X != uvw) {  // the last iterate is in the workspace
+        for (int q = 0; q < 3; ++q)
+            HIP_TRY(hipMemcpyAsync(uvw[q], X[q], sizeof(double) * g->N, hipMemcpyDeviceToDevice, s), "copy back");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "momentum sync");
+    if (st) {
+        st->cycles = cyc;
+        st->sweeps = cyc * m;
+        st->rel_residual = rel;
+        st->rho = rho;
+        st->t_step = now_s() - t0;
+    }
+    if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite residual in the advection-diffusion solve");
+    return status;
 }
 
 void ibm_destroy_grid(ibm_grid *g) {

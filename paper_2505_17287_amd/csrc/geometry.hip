@@ -649,7 +649,7 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
                           const uint8_t *__restrict__ type, const double *__restrict__ V, const int32_t *__restrict__ T,
                           const double *__restrict__ gbi, const int32_t *__restrict__ gtri, double *gn, double *gip,
                           double *gdl, int32_t *gst, uint8_t *gmask, double *gbeta, double *gbetag, int32_t *gflags,
-                          int64_t *ndegen) {
+                          int64_t *ndegen, double *gbetaD, double *gbetaDg) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     int64_t id = gcell[g];
@@ -730,10 +730,16 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         st[m] = -1;
     }
     double bg = 0.0;
+    // Dirichlet weights (velocity ghost rows): the interpolant's own row is its value at the
+    // intercept, so with the Lagrange basis L_m of the box
+    //   betaD_m = L_m(IP) - L_m(BI) L_g(IP) / L_g(BI),  betaD_g = L_g(IP) / L_g(BI);
+    // for a mirrored image point BI lies between the ghost centre and IP, so L_g(BI) >= 1/8.
+    double betaD[8], bDg = 0.0;
+    for (int m = 0; m < 8; ++m) betaD[m] = 0.0;
     bool degenerate = (ndead > 0 || nfl == 0);
     if (!degenerate) {
-        // Lagrange basis at the image point and its normal derivative at the intercept
-        double L[8], dLn[8];
+        // Lagrange basis at the image point, at the intercept, and its normal derivative there
+        double L[8], dLn[8], LB[8];
         for (int m = 0; m < nm; ++m) {
             int bits[3] = {m & 1, (m >> 1) & 1, (m >> 2) & 1};
             double fi[3], fb[3];
@@ -741,6 +747,7 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
                 fi[d] = bits[d] ? s[d] : 1.0 - s[d];
                 fb[d] = bits[d] ? bl[d] : 1.0 - bl[d];
             }
+            LB[m] = two_d ? fb[0] * fb[1] : fb[0] * fb[1] * fb[2];
             if (two_d) {
                 L[m] = fi[0] * fi[1];
                 dLn[m] = n[0] * ((bits[0] ? 1.0 : -1.0) / hs[0]) * fb[1] + n[1] * ((bits[1] ? 1.0 : -1.0) / hs[1]) * fb[0];
@@ -754,9 +761,13 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         if (self < 0) {
             for (int m = 0; m < nm; ++m) {
                 beta[m] = L[m];
+                betaD[m] = L[m];
                 st[m] = mem[m];
             }
         } else if (dLn[self] < 0.0) {
+            bDg = L[self] / LB[self];
+            for (int m = 0; m < nm; ++m)
+                if (m != self) betaD[m] = L[m] - LB[m] * bDg;
             bg = L[self] / dLn[self];
             for (int m = 0; m < nm; ++m) {
                 if (m == self) {
@@ -776,8 +787,10 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         flags |= GF_DEGENERATE;
         gm = 0;
         bg = 0.0;
+        bDg = 0.0;
         for (int m = 0; m < 8; ++m) {
             beta[m] = 0.0;
+            betaD[m] = 0.0;
             st[m] = -1;
         }
         atomicAdd((unsigned long long *)ndegen, 1ull);
@@ -785,9 +798,11 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
     for (int m = 0; m < 8; ++m) {
         gst[8 * g + m] = st[m];
         gbeta[8 * g + m] = beta[m];
+        gbetaD[8 * g + m] = betaD[m];
     }
     gmask[g] = gm;
     gbetag[g] = bg;
+    gbetaDg[g] = bDg;
     gflags[g] = flags;
 }
 
@@ -812,7 +827,8 @@ hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
                        g->c0[2], g->verts, g->tris, g->nt, g->bucket_off, g->bucket_ent, G, g->g_bi, g->g_tri);
     hipLaunchKernelGGL(k_weights, dim3(nb), dim3(128), 0, s, g->ng, g->g_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1],
                        g->c0[2], g->w0[0], g->w0[1], g->w0[2], g->type, g->verts, g->tris, g->g_bi, g->g_tri, g->g_n,
-                       g->g_ip, g->g_dl, g->g_st, g->g_mask, g->g_beta, g->g_betag, g->g_flags, g->counters + 5);
+                       g->g_ip, g->g_dl, g->g_st, g->g_mask, g->g_beta, g->g_betag, g->g_flags, g->counters + 5,
+                       g->g_betaD, g->g_betaDg);
     return hipGetLastError();
 }
 

@@ -109,6 +109,8 @@ struct Scalars {
     float zero32, pad2;
     double mu[MAX_LEVELS];
     double vol[MAX_LEVELS];   // summed volume of the active cells of each level
+    double mom_b2;            // advection-diffusion step: sum of b^2 over fluid rows
+    double mom_r2;            // sum of r^2 at the input of the last sweep
 };
 
 // ---------------------------------------------------------------------------------------
@@ -211,6 +213,10 @@ struct ibm_grid {
     double *g_dl = nullptr, *g_h = nullptr, *g_data = nullptr;
     double *g_scale = nullptr;             // diagonal of the flux stencil at each ghost cell
     double *g_rhs = nullptr;               // ghost right-hand sides of a preconditioner call
+    double *g_betaD = nullptr;             // 8 per ghost: Dirichlet (velocity) weights
+    double *g_betaDg = nullptr;            // per ghost: weight of the intercept value
+    double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
+    double diag_max = -1.0;                // max over cells of the flux-coefficient sum (< 0: not read yet)
     // Krylov vectors (FP64, full grid)
     double *kv[10] = {nullptr};
     // multigrid
@@ -275,5 +281,11 @@ hipError_t krylov_setup(ibm_grid *g, hipStream_t s);
 hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s);
 hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s);
 hipError_t krylov_restart(ibm_grid *g, hipStream_t s);
+
+// advection-diffusion half-step launchers (momentum.hip)
+hipError_t momentum_enqueue_prep(ibm_grid *g, double *const uvw[3], double *const hc[3], double *const work[6],
+                                 double dt, double a, int first, hipStream_t s);
+hipError_t momentum_enqueue_sweep(ibm_grid *g, double *const X[3], double *const Y[3], double *const work[6],
+                                  double a, double omega, bool sum, hipStream_t s);
 
 }  // namespace ibm

@@ -35,6 +35,18 @@ class SolveStats(C.Structure):
 
 
 IBM_VCYCLE, IBM_BICGSTAB = 0, 1
+IBM_SRJ_MAX = 256
+
+
+class MomentumOpts(C.Structure):
+    _fields_ = [("nu", C.c_double), ("dt", C.c_double), ("first_step", C.c_int), ("srj_factors", C.c_int),
+                ("omega", C.POINTER(C.c_double)), ("rel_tol", C.c_double), ("max_cycles", C.c_int),
+                ("fixed_cycles", C.c_int)]
+
+
+class MomentumStats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("sweeps", C.c_int), ("rel_residual", C.c_double), ("rho", C.c_double),
+                ("t_step", C.c_double)]
 
 
 @dataclass
@@ -94,13 +106,19 @@ def lib():
         L.ibm_get_profile.argtypes = [vp, vp, vp, vp, vp]
         L.ibm_set_profiling.restype = C.c_int
         L.ibm_get_profile.restype = C.c_int
+        L.ibm_default_momentum_opts.argtypes = [C.POINTER(MomentumOpts)]
+        L.ibm_srj_schedule.argtypes = [C.c_double, C.c_int, vp]
+        L.ibm_set_dirichlet_data.argtypes = [vp, vp, vp]
+        L.ibm_get_dirichlet_weights.argtypes = [vp, vp, vp, vp]
+        L.ibm_momentum_step.argtypes = [vp] + [vp] * 6 + [C.POINTER(MomentumOpts), C.POINTER(MomentumStats), vp]
         L.ibm_destroy_grid.argtypes = [vp]
         L.ibm_last_error.restype = C.c_char_p
         L.ibm_last_error.argtypes = [vp]
         for name in ("ibm_create_grid", "ibm_bind_workspace", "ibm_set_geometry", "ibm_classify",
                      "ibm_build_ghost_stencils", "ibm_get_ghosts", "ibm_set_neumann_data", "ibm_get_cell_types",
                      "ibm_poisson_solve", "ibm_project", "ibm_solve_begin", "ibm_solve_step", "ibm_solve_poll",
-                     "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply"):
+                     "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply", "ibm_srj_schedule",
+                     "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -130,6 +148,15 @@ def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, p
 
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def srj_schedule(rho, m):
+    """The library's relaxation factors for [1 - rho, 1 + rho] (host call, no device)."""
+    out = np.zeros(m, dtype=np.float64)
+    code = lib().ibm_srj_schedule(float(rho), int(m), C.c_void_p(out.ctypes.data))
+    if code < 0:
+        raise IBMError(code, lib().ibm_last_error(None).decode())
+    return out
 
 
 def _stream_ptr(stream):
@@ -343,6 +370,47 @@ class Grid:
         st = SolveStats()
         code = self._check(lib().ibm_solve_poll(self._h, C.byref(done), C.byref(st)))
         return done.value, _stats(code, st)
+
+    # advection-diffusion half-step
+    def set_dirichlet_data(self, ubi=None):
+        arr = None if ubi is None else np.ascontiguousarray(ubi, dtype=np.float64).reshape(-1)
+        if arr is not None and arr.size != 3 * self.ng:
+            raise ValueError("need 3 values per ghost")
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_set_dirichlet_data(self._h, None if arr is None else C.c_void_p(arr.ctypes.data),
+                                                     self._s()))
+
+    def dirichlet_weights(self):
+        beta = np.empty((self.ng, 8))
+        beta_g = np.empty(self.ng)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_get_dirichlet_weights(self._h, self._s(), C.c_void_p(beta.ctypes.data),
+                                                        C.c_void_p(beta_g.ctypes.data)))
+        return beta, beta_g
+
+    def momentum_step(self, U, H, nu, dt, first_step=False, m=8, omega=None, rel_tol=1e-10, max_cycles=200,
+                      fixed_cycles=0):
+        """U: (3, nz, ny, nx) float64 device tensor, in u^n, out u*; H: same shape, in H^{n-1},
+        out H^n.  Returns (status, MomentumStats)."""
+        for a, nm in ((U, "U"), (H, "H")):
+            self._field(a, nm)
+            if tuple(a.shape) != (3,) + self.shape:
+                raise ValueError("%s shape %s != %s" % (nm, tuple(a.shape), (3,) + self.shape))
+        o = MomentumOpts()
+        lib().ibm_default_momentum_opts(C.byref(o))
+        o.nu, o.dt, o.first_step, o.srj_factors = float(nu), float(dt), int(bool(first_step)), int(m)
+        om = None
+        if omega is not None:
+            om = np.ascontiguousarray(omega, dtype=np.float64)
+            if om.size != m:
+                raise ValueError("omega must hold m factors")
+            o.omega = _dp(om)
+        o.rel_tol, o.max_cycles, o.fixed_cycles = float(rel_tol), int(max_cycles), int(fixed_cycles)
+        st = MomentumStats()
+        with self.torch.cuda.device(self.device):
+            code = self._check(lib().ibm_momentum_step(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]), _tptr(H[0]),
+                                                       _tptr(H[1]), _tptr(H[2]), C.byref(o), C.byref(st), self._s()))
+        return code, st
 
     # smoother timing
     def set_profiling(self, on=True):

@@ -79,3 +79,15 @@ def test_levels_follow_semicoarsening_rule():
 def test_options_defaults():
     o = ibm.make_opts()
     assert o.rel_tol == 1e-10 and o.max_cycles == 200 and (o.nu1, o.nu2, o.coarsest_sweeps) == (2, 2, 64)
+
+
+def test_srj_schedule_host_call():
+    """The library's schedule (host code, no device) equals the oracle's Chebyshev factors and
+    rejects out-of-range arguments."""
+    from oracle.momentum import srj_schedule as ref
+    for rho, m in ((0.0, 1), (0.3, 2), (0.9, 8), (0.999, 64)):
+        a = ibm.srj_schedule(rho, m)
+        assert np.max(np.abs(a - ref(rho, m)) / ref(rho, m)) <= 1e-15
+    for rho, m in ((1.0, 4), (-0.1, 4), (0.5, 0), (0.5, ibm.IBM_SRJ_MAX + 1)):
+        with pytest.raises(ibm.IBMError):
+            ibm.srj_schedule(rho, m)
