@@ -154,6 +154,53 @@ def mixed_form(wl, u0, v0, w0, args):
                            "frac": round(ach / HBM_PEAK_GBS, 4), "launches_timed": prof["n_fp32"]}}
 
 
+MOM_SWEEP_BYTES = 73.0  # algorithmic bytes per cell of one SRJ sweep: read 3 x 8 + 3 x 8 (b) + 1, write 3 x 8
+
+
+def momentum_form(wl, args, steps=None):
+    """The advection-diffusion half-step on the same grid and bodies (Re = 1000, dt = half the
+    smallest width, 8 Chebyshev factors per cycle, rel-res 1e-10): steps/s, and the scheduled
+    Jacobi sweep's algorithmic bandwidth, from the time difference between runs of 3 and 1
+    fixed cycles (each sweep with its ghost-row pass)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+
+    dev = torch.device("cuda:0")
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf)
+    g.setup(wl.verts, wl.tris)
+    U0n, H0n = wl.cell_fields()
+    U0 = torch.from_numpy(np.ascontiguousarray(U0n)).to(dev)
+    H0 = torch.from_numpy(np.ascontiguousarray(H0n)).to(dev)
+    del U0n, H0n
+    U, H = U0.clone(), H0.clone()
+    nu, dt, m = 1e-3, 0.5 * float(np.min(np.diff(wl.xf))), 8
+
+    def step(**kw):
+        U.copy_(U0)
+        H.copy_(H0)
+        torch.cuda.synchronize()
+        code, st = g.momentum_step(U, H, nu, dt, m=m, **kw)
+        return st
+
+    steps = steps or max(1, min(args.steps, 5))
+    step()
+    sts = [step(rel_tol=1e-10) for _ in range(steps)]
+    t_step = float(np.median([s.t_step for s in sts]))
+    t1 = float(np.median([step(fixed_cycles=1).t_step for _ in range(3)]))
+    t3 = float(np.median([step(fixed_cycles=3).t_step for _ in range(3)]))
+    per_sweep = (t3 - t1) / (2 * m)
+    ach = MOM_SWEEP_BYTES * wl.ncells / per_sweep / 1e9
+    g.close()
+    return {"value": round(1.0 / t_step, 3), "unit": "steps/s", "ms_per_step": round(1000.0 * t_step, 3),
+            "steps": steps, "dtype": "f64", "nu": nu, "dt": dt, "srj_factors": m,
+            "cycles": int(np.median([s.cycles for s in sts])), "sweeps": int(np.median([s.sweeps for s in sts])),
+            "rho": round(sts[0].rho, 6), "max_rel_residual": max(s.rel_residual for s in sts),
+            "srj_sweep": {"achieved_GBs": round(ach, 1), "ms_per_sweep": round(1000.0 * per_sweep, 4),
+                          "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell": MOM_SWEEP_BYTES}}
+
+
 def serving_form(args):
     """Continuous batching of whole projections (grids 64^3..256^3, 1-4 bodies) against the
     same requests served one at a time in plain FP64: saturation throughput, then p50/p99
@@ -211,6 +258,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests per serving run (sizes 64^3..256^3, 1-4 bodies each)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--momentum", action="store_true",
+                    help="only the advection-diffusion half-step form (3 steps), one JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for hardware counters: a plain device copy of known size for "
                          "calibration, 4 fused FP64 sweeps of level 0, one single-step projection")
@@ -220,6 +269,11 @@ def main():
         sys.exit(2)
     if args.probe:
         probe(args)
+        return
+    if args.momentum:
+        from paper_2505_17287_amd import inputs as I
+        wl = I.multibody(args.n)
+        print(json.dumps({"workload": wl.name, "momentum": momentum_form(wl, args, steps=3)}), flush=True)
         return
 
     import numpy as np
@@ -300,6 +354,7 @@ def main():
     }
     if not args.no_forms:
         out["forms"] = {"mixed": mixed_form(wl, u0, v0, w0, args),
+                        "momentum": momentum_form(wl, args),
                         "serving": serving_form(args)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

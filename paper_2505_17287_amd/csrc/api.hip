@@ -168,6 +168,7 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     G->g_betaD = P.take<double>(8 * gm);
     G->g_betaDg = P.take<double>(gm);
     G->g_ubi = P.take<double>(3 * gm);
+    G->g_uscr = P.take<double>(3 * gm);
     for (int q = 0; q < 10; ++q) G->kv[q] = P.take<double>(N);
     for (int l = 0; l < nlev; ++l) {
         LevelHost &L = lev[l];
@@ -1047,8 +1048,8 @@ ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, doubl
     double *work[6] = {g->kv[0], g->kv[1], g->kv[2], g->kv[3], g->kv[4], g->kv[5]};
     double *wk[3] = {work[3], work[4], work[5]};
     HIP_TRY(momentum_enqueue_prep(g, uvw, hc, work, o->dt, a, o->first_step ? 1 : 0, s), "momentum rhs");
-    double *const *X = wk;
-    double *const *Y = uvw;
+    double *const *X = uvw;
+    double *const *Y = wk;
     const int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
     Scalars *hs = g->sc_host;
     ibm_status status = IBM_OK;

@@ -216,6 +216,7 @@ struct ibm_grid {
     double *g_betaD = nullptr;             // 8 per ghost: Dirichlet (velocity) weights
     double *g_betaDg = nullptr;            // per ghost: weight of the intercept value
     double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
+    double *g_uscr = nullptr;              // 3 per ghost: held-back ghost values of an in-place pass
     double diag_max = -1.0;                // max over cells of the flux-coefficient sum (< 0: not read yet)
     // Krylov vectors (FP64, full grid)
     double *kv[10] = {nullptr};

@@ -3,16 +3,18 @@
 // scheduled relaxed Jacobi, with the no-slip (Dirichlet) ghost rows of Section 2.2.
 //
 // Cell-centred velocity components live in three arrays of the level-0 layout [nz][ny][nx].
-// Every kernel here is a single pass over the grid; neighbour values come through the
-// caches (the six neighbours of a cell are re-read by its neighbours' threads).
+// The two cell passes (right-hand side, relaxed Jacobi sweep) are z-marches over 64 x 4
+// column tiles: a thread owns a column, keeps the centre values of the planes below and
+// above in registers, and issues every load of the next plane before computing the current
+// one; x and y neighbours come from the lanes' common cache lines.
 #include "device_util.hpp"
 #include "ibm_impl.hpp"
+#include "zmarch.hpp"
 
 namespace ibm {
 
 namespace {
 
-constexpr int MOM_NT = 256;      // threads per block of the cell passes
 constexpr int DREF_NT = 256;     // ghost refresh: eight lanes per ghost
 
 struct CV3 {
@@ -55,15 +57,6 @@ MomView mom_view(ibm_grid *g) {
     return M;
 }
 
-// dst = src with dead cells cleared (three components)
-__global__ void k_mom_prep(int64_t N, const uint8_t *__restrict__ type, CV3 src, V3 dst) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    const bool dead = type[id] == T_DEAD;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) dst.c[q][id] = dead ? 0.0 : src.c[q][id];
-}
-
 // Dirichlet ghost rows, one pass: u_g = (2 - betaD_g) u_BI - sum_{m != g} betaD_m u_m with
 // fluid members read from dst (already updated) and ghost members from src (the values
 // before the pass).  Lane m of a group of eight takes member m; three shuffle steps sum the
@@ -71,7 +64,7 @@ __global__ void k_mom_prep(int64_t N, const uint8_t *__restrict__ type, CV3 src,
 __global__ void __launch_bounds__(DREF_NT)
     k_dirichlet_refresh(GhostView G, const double *__restrict__ betaD, const double *__restrict__ betaDg,
                         const double *__restrict__ ubi, CV3 src, V3 dst, int nx, int ny, int nz,
-                        const uint8_t *__restrict__ type) {
+                        const uint8_t *__restrict__ type, double *scr) {
     const int64_t g = ((int64_t)blockIdx.x * DREF_NT + threadIdx.x) >> 3;
     const int m = threadIdx.x & 7;
     const bool live = g < G.ng;
@@ -112,156 +105,284 @@ __global__ void __launch_bounds__(DREF_NT)
                     }
                 }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dst.c[c][cell] = 2.0 * ub[c] - (n ? sm[c] / n : 0.0);
+        for (int c = 0; c < 3; ++c) t[c] = 2.0 * ub[c] - (n ? sm[c] / n : 0.0);
     } else {
         const double w = 2.0 - betaDg[gc];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dst.c[c][cell] = w * ub[c] - t[c];
+        for (int c = 0; c < 3; ++c) t[c] = w * ub[c] - t[c];
+    }
+    if (scr) {  // values held back, scattered by k_ghost_scatter (an in-place pass)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) scr[3 * gc + c] = t[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst.c[c][cell] = t[c];
     }
 }
+
+__global__ void k_ghost_scatter(int64_t ng, const int32_t *__restrict__ gcell, const double *__restrict__ scr, V3 dst) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int64_t cell = gcell[g];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst.c[c][cell] = scr[3 * g + c];
+}
+
+// one plane of a column for the right-hand side pass: the four lateral neighbours and the
+// centre of the plane above, per component, the previous convective term and the type
+struct RhsPlane {
+    double xm[3], xp[3], ym[3], yp[3], up[3], hold[3];
+    double azm, azp, zpl, zph, zml, zmh, wz;
+    uint8_t ty;
+};
 
 // Right-hand side of the Crank-Nicolson system on fluid rows and the convective term:
 //   H = -(1/V) sum_faces (+/-) A_f Un_f (u_i)_f      (face values: linear interpolation)
 //   b = u + dt (3/2 H - 1/2 H_old) + a L u,   a = nu dt / 2   (first step: H_old = H)
-// H overwrites H_old in place (each thread reads and writes only its own cell).  Non-fluid
+// H overwrites H_old in place (each thread reads and writes only its own cells).  Non-fluid
 // cells get H = b = 0.  partials[block] = sum of b^2 over the block's fluid cells.
-__global__ void __launch_bounds__(MOM_NT)
-    k_mom_rhs(MomView M, CV3 U, V3 H, V3 B, double dt, double a, int first, double *partials) {
-    __shared__ double sh[MOM_NT / 64];
+__global__ void __launch_bounds__(ZM_NT)
+    k_mom_rhs(MomView M, CV3 U, V3 H, V3 B, double dt, double a, int first, ZTiles t, double *partials) {
+    __shared__ double sh[ZM_NT / 64];
+    const ZPos z = zpos(t, M.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
     const int nx = M.nx, ny = M.ny, nz = M.nz;
-    const int64_t N = (int64_t)nx * ny * nz, sy = nx, sz = (int64_t)nx * ny;
-    double acc = 0.0;
-    for (int64_t id = (int64_t)blockIdx.x * MOM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * MOM_NT) {
-        if (M.type[id] != T_FLUID) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                H.c[q][id] = 0.0;
-                B.c[q][id] = 0.0;
-            }
-            continue;
-        }
-        int i, j, k;
-        unflatten(id, nx, ny, i, j, k);
-        const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1, hz0 = k > 0, hz1 = k < nz - 1;
-        // interpolation weights (low cell, high cell) of the six faces
-        double xpl = 0, xph = 0, xml = 0, xmh = 0, ypl = 0, yph = 0, yml = 0, ymh = 0, zpl = 0, zph = 0, zml = 0,
-               zmh = 0;
-        if (hx1) {
-            const double h = M.xc[i + 1] - M.xc[i];
-            xpl = (M.xc[i + 1] - M.xf[i + 1]) / h;
-            xph = (M.xf[i + 1] - M.xc[i]) / h;
-        }
-        if (hx0) {
-            const double h = M.xc[i] - M.xc[i - 1];
-            xml = (M.xc[i] - M.xf[i]) / h;
-            xmh = (M.xf[i] - M.xc[i - 1]) / h;
-        }
-        if (hy1) {
-            const double h = M.yc[j + 1] - M.yc[j];
-            ypl = (M.yc[j + 1] - M.yf[j + 1]) / h;
-            yph = (M.yf[j + 1] - M.yc[j]) / h;
-        }
-        if (hy0) {
-            const double h = M.yc[j] - M.yc[j - 1];
-            yml = (M.yc[j] - M.yf[j]) / h;
-            ymh = (M.yf[j] - M.yc[j - 1]) / h;
-        }
-        if (hz1) {
-            const double h = M.zc[k + 1] - M.zc[k];
-            zpl = (M.zc[k + 1] - M.zf[k + 1]) / h;
-            zph = (M.zf[k + 1] - M.zc[k]) / h;
-        }
-        if (hz0) {
-            const double h = M.zc[k] - M.zc[k - 1];
-            zml = (M.zc[k] - M.zf[k]) / h;
-            zmh = (M.zf[k] - M.zc[k - 1]) / h;
-        }
-        const double ax = M.wz[k] * M.wy[j], ay = M.wz[k] * M.wx[i], az = M.wy[j] * M.wx[i];
-        const double vol = (M.wz[k] * M.wy[j]) * M.wx[i];
-        // normal velocities at the faces
-        const double *u = U.c[0], *v = U.c[1], *w = U.c[2];
-        const double uxp = hx1 ? xpl * u[id] + xph * u[id + 1] : 0.0;
-        const double uxm = hx0 ? xml * u[id - 1] + xmh * u[id] : 0.0;
-        const double vyp = hy1 ? ypl * v[id] + yph * v[id + sy] : 0.0;
-        const double vym = hy0 ? yml * v[id - sy] + ymh * v[id] : 0.0;
-        const double wzp = hz1 ? zpl * w[id] + zph * w[id + sz] : 0.0;
-        const double wzm = hz0 ? zml * w[id - sz] + zmh * w[id] : 0.0;
+    const bool in = z.i < nx && z.j < ny;
+    const int i = min(z.i, nx - 1), j = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, row = (int64_t)j * nx + i;
+    const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    // interpolation weights (low cell, high cell) of the four lateral faces
+    double xpl = 0, xph = 0, xml = 0, xmh = 0, ypl = 0, yph = 0, yml = 0, ymh = 0;
+    if (hx1) {
+        const double h = M.xc[i + 1] - M.xc[i];
+        xpl = (M.xc[i + 1] - M.xf[i + 1]) / h;
+        xph = (M.xf[i + 1] - M.xc[i]) / h;
+    }
+    if (hx0) {
+        const double h = M.xc[i] - M.xc[i - 1];
+        xml = (M.xc[i] - M.xf[i]) / h;
+        xmh = (M.xf[i] - M.xc[i - 1]) / h;
+    }
+    if (hy1) {
+        const double h = M.yc[j + 1] - M.yc[j];
+        ypl = (M.yc[j + 1] - M.yf[j + 1]) / h;
+        yph = (M.yf[j + 1] - M.yc[j]) / h;
+    }
+    if (hy0) {
+        const double h = M.yc[j] - M.yc[j - 1];
+        yml = (M.yc[j] - M.yf[j]) / h;
+        ymh = (M.yf[j] - M.yc[j - 1]) / h;
+    }
+    const double wx = M.wx[i], wy = M.wy[j];
+    const double cxm = M.axm[i], cxp = M.axp[i], cym = M.aym[j], cyp = M.ayp[j];
+    auto ld = [&](int k) -> RhsPlane {
+        RhsPlane d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + row;
+        const int64_t up = (kk < nz - 1) ? base + plane : base;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const double *f = U.c[q];
-            const double fc = f[id];
-            const double fxp = hx1 ? f[id + 1] : 0.0, fxm = hx0 ? f[id - 1] : 0.0;
-            const double fyp = hy1 ? f[id + sy] : 0.0, fym = hy0 ? f[id - sy] : 0.0;
-            const double fzp = hz1 ? f[id + sz] : 0.0, fzm = hz0 ? f[id - sz] : 0.0;
-            double h = 0.0;
-            if (hx1) h -= (uxp * (xpl * fc + xph * fxp)) * ax;
-            if (hx0) h += (uxm * (xml * fxm + xmh * fc)) * ax;
-            if (hy1) h -= (vyp * (ypl * fc + yph * fyp)) * ay;
-            if (hy0) h += (vym * (yml * fym + ymh * fc)) * ay;
-            if (hz1) h -= (wzp * (zpl * fc + zph * fzp)) * az;
-            if (hz0) h += (wzm * (zml * fzm + zmh * fc)) * az;
-            h /= vol;
-            double lap = 0.0;
-            if (hx1) lap += M.axp[i] * (fxp - fc);
-            if (hx0) lap -= M.axm[i] * (fc - fxm);
-            if (hy1) lap += M.ayp[j] * (fyp - fc);
-            if (hy0) lap -= M.aym[j] * (fc - fym);
-            if (hz1) lap += M.azp[k] * (fzp - fc);
-            if (hz0) lap -= M.azm[k] * (fc - fzm);
-            const double hp = first ? h : H.c[q][id];
-            const double b = fc + dt * (1.5 * h - 0.5 * hp) + a * lap;
-            H.c[q][id] = h;
-            B.c[q][id] = b;
-            acc += b * b;
+            d.xm[q] = U.c[q][base + dxm];
+            d.xp[q] = U.c[q][base + dxp];
+            d.ym[q] = U.c[q][base + dym];
+            d.yp[q] = U.c[q][base + dyp];
+            d.up[q] = U.c[q][up];
+            d.hold[q] = H.c[q][base];
+        }
+        d.ty = M.type[base];
+        d.azm = M.azm[kk];
+        d.azp = M.azp[kk];
+        d.wz = M.wz[kk];
+        d.zpl = d.zph = d.zml = d.zmh = 0.0;
+        if (kk < nz - 1) {
+            const double h = M.zc[kk + 1] - M.zc[kk];
+            d.zpl = (M.zc[kk + 1] - M.zf[kk + 1]) / h;
+            d.zph = (M.zf[kk + 1] - M.zc[kk]) / h;
+        }
+        if (kk > 0) {
+            const double h = M.zc[kk] - M.zc[kk - 1];
+            d.zml = (M.zc[kk] - M.zf[kk]) / h;
+            d.zmh = (M.zf[kk] - M.zc[kk - 1]) / h;
+        }
+        return d;
+    };
+    double cm[3], cc[3];  // centres of the planes k - 1 and k
+    {
+        const int64_t b0 = (int64_t)z.k0 * plane + row;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cc[q] = U.c[q][b0];
+            cm[q] = z.k0 > 0 ? U.c[q][b0 - plane] : 0.0;
         }
     }
-    const double t = block_sum<MOM_NT>(acc, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    double acc = 0.0;
+    auto compute = [&](const RhsPlane &D, int k) {
+        const int64_t id = (int64_t)k * plane + row;
+        if (in && k < z.k1) {
+            if (D.ty != T_FLUID) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    H.c[q][id] = 0.0;
+                    B.c[q][id] = 0.0;
+                }
+            } else {
+                const bool hz0 = k > 0, hz1 = k < nz - 1;
+                const double ax = D.wz * wy, ay = D.wz * wx, az = wy * wx;
+                const double vol = (D.wz * wy) * wx;
+                const double uxp = hx1 ? xpl * cc[0] + xph * D.xp[0] : 0.0;
+                const double uxm = hx0 ? xml * D.xm[0] + xmh * cc[0] : 0.0;
+                const double vyp = hy1 ? ypl * cc[1] + yph * D.yp[1] : 0.0;
+                const double vym = hy0 ? yml * D.ym[1] + ymh * cc[1] : 0.0;
+                const double wzp = hz1 ? D.zpl * cc[2] + D.zph * D.up[2] : 0.0;
+                const double wzm = hz0 ? D.zml * cm[2] + D.zmh * cc[2] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const double fc = cc[q];
+                    const double fxp = D.xp[q], fxm = D.xm[q], fyp = D.yp[q], fym = D.ym[q];
+                    const double fzp = D.up[q], fzm = cm[q];
+                    double h = 0.0;
+                    if (hx1) h -= (uxp * (xpl * fc + xph * fxp)) * ax;
+                    if (hx0) h += (uxm * (xml * fxm + xmh * fc)) * ax;
+                    if (hy1) h -= (vyp * (ypl * fc + yph * fyp)) * ay;
+                    if (hy0) h += (vym * (yml * fym + ymh * fc)) * ay;
+                    if (hz1) h -= (wzp * (D.zpl * fc + D.zph * fzp)) * az;
+                    if (hz0) h += (wzm * (D.zml * fzm + D.zmh * fc)) * az;
+                    h /= vol;
+                    double lap = 0.0;
+                    if (hx1) lap += cxp * (fxp - fc);
+                    if (hx0) lap -= cxm * (fc - fxm);
+                    if (hy1) lap += cyp * (fyp - fc);
+                    if (hy0) lap -= cym * (fc - fym);
+                    if (hz1) lap += D.azp * (fzp - fc);
+                    if (hz0) lap -= D.azm * (fc - fzm);
+                    const double hp = first ? h : D.hold[q];
+                    const double b = fc + dt * (1.5 * h - 0.5 * hp) + a * lap;
+                    H.c[q][id] = h;
+                    B.c[q][id] = b;
+                    acc += b * b;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cm[q] = cc[q];
+            cc[q] = D.up[q];
+        }
+    };
+    RhsPlane qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        compute(qa, k);
+        qa = ld(k + 2);
+        compute(qb, k + 1);
+    }
+    const double tot = block_sum<ZM_NT>(acc, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
+
+struct SrjPlane {
+    double xm[3], xp[3], ym[3], yp[3], up[3], b[3];
+    double azm, azp;
+    uint8_t ty;
+};
 
 // One relaxed Jacobi sweep of the fluid rows of (I - a L) u = b:
 //   y = (1 - omega) x + omega (b + a sum_f a_f x_nb) / (1 + a sum_f a_f)
-// other cells are copied (ghost rows follow in their own pass).  partials[block] = sum of
-// the squared fluid-row residuals b - (I - a L) x at the input iterate.
-__global__ void __launch_bounds__(MOM_NT)
-    k_srj_sweep(MomView M, CV3 X, V3 Y, CV3 B, double a, double omega, double *partials) {
-    __shared__ double sh[MOM_NT / 64];
+// ghost cells are copied (their rows follow in their own pass), dead cells cleared.
+// partials[block] = sum of the squared fluid-row residuals b - (I - a L) x at the input.
+__global__ void __launch_bounds__(ZM_NT)
+    k_srj_sweep(MomView M, CV3 X, V3 Y, CV3 B, double a, double omega, ZTiles t, double *partials) {
+    __shared__ double sh[ZM_NT / 64];
+    const ZPos z = zpos(t, M.nz);
+    if (!z.live) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
     const int nx = M.nx, ny = M.ny, nz = M.nz;
-    const int64_t N = (int64_t)nx * ny * nz, sy = nx, sz = (int64_t)nx * ny;
-    double acc = 0.0;
-    for (int64_t id = (int64_t)blockIdx.x * MOM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * MOM_NT) {
-        if (M.type[id] != T_FLUID) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) Y.c[q][id] = X.c[q][id];
-            continue;
-        }
-        int i, j, k;
-        unflatten(id, nx, ny, i, j, k);
-        const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1, hz0 = k > 0, hz1 = k < nz - 1;
-        const double cxp = hx1 ? M.axp[i] : 0.0, cxm = hx0 ? M.axm[i] : 0.0;
-        const double cyp = hy1 ? M.ayp[j] : 0.0, cym = hy0 ? M.aym[j] : 0.0;
-        const double czp = hz1 ? M.azp[k] : 0.0, czm = hz0 ? M.azm[k] : 0.0;
-        const double d = ((czm + czp) + (cym + cyp)) + (cxm + cxp);
-        const double den = 1.0 + a * d;
+    const bool in = z.i < nx && z.j < ny;
+    const int i = min(z.i, nx - 1), j = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, row = (int64_t)j * nx + i;
+    const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const double cxp = hx1 ? M.axp[i] : 0.0, cxm = hx0 ? M.axm[i] : 0.0;
+    const double cyp = hy1 ? M.ayp[j] : 0.0, cym = hy0 ? M.aym[j] : 0.0;
+    auto ld = [&](int k) -> SrjPlane {
+        SrjPlane d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + row;
+        const int64_t up = (kk < nz - 1) ? base + plane : base;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const double *x = X.c[q];
-            double s = 0.0;
-            if (hx1) s += cxp * x[id + 1];
-            if (hx0) s += cxm * x[id - 1];
-            if (hy1) s += cyp * x[id + sy];
-            if (hy0) s += cym * x[id - sy];
-            if (hz1) s += czp * x[id + sz];
-            if (hz0) s += czm * x[id - sz];
-            const double xc = x[id];
-            const double num = B.c[q][id] + a * s;
-            const double r = num - den * xc;
-            Y.c[q][id] = (1.0 - omega) * xc + omega * (num / den);
-            acc += r * r;
+            d.xm[q] = X.c[q][base + dxm];
+            d.xp[q] = X.c[q][base + dxp];
+            d.ym[q] = X.c[q][base + dym];
+            d.yp[q] = X.c[q][base + dyp];
+            d.up[q] = X.c[q][up];
+            d.b[q] = B.c[q][base];
+        }
+        d.ty = M.type[base];
+        d.azm = M.azm[kk];
+        d.azp = M.azp[kk];
+        return d;
+    };
+    double cm[3], cc[3];
+    {
+        const int64_t b0 = (int64_t)z.k0 * plane + row;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cc[q] = X.c[q][b0];
+            cm[q] = z.k0 > 0 ? X.c[q][b0 - plane] : 0.0;
         }
     }
-    const double t = block_sum<MOM_NT>(acc, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    double acc = 0.0;
+    auto compute = [&](const SrjPlane &D, int k) {
+        const int64_t id = (int64_t)k * plane + row;
+        if (in && k < z.k1) {
+            if (D.ty != T_FLUID) {
+                const bool dead = D.ty == T_DEAD;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) Y.c[q][id] = dead ? 0.0 : cc[q];
+            } else {
+                const bool hz0 = k > 0, hz1 = k < nz - 1;
+                const double czp = hz1 ? D.azp : 0.0, czm = hz0 ? D.azm : 0.0;
+                const double d = ((czm + czp) + (cym + cyp)) + (cxm + cxp);
+                const double den = 1.0 + a * d;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    double s = 0.0;
+                    if (hx1) s += cxp * D.xp[q];
+                    if (hx0) s += cxm * D.xm[q];
+                    if (hy1) s += cyp * D.yp[q];
+                    if (hy0) s += cym * D.ym[q];
+                    if (hz1) s += czp * D.up[q];
+                    if (hz0) s += czm * cm[q];
+                    const double xc = cc[q];
+                    const double num = D.b[q] + a * s;
+                    const double r = num - den * xc;
+                    Y.c[q][id] = (1.0 - omega) * xc + omega * (num / den);
+                    acc += r * r;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cm[q] = cc[q];
+            cc[q] = D.up[q];
+        }
+    };
+    SrjPlane qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        compute(qa, k);
+        qa = ld(k + 2);
+        compute(qb, k + 1);
+    }
+    const double tot = block_sum<ZM_NT>(acc, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 __global__ void k_mom_sum(const double *partials, int n, double *out) {
@@ -299,30 +420,33 @@ GhostView ghosts(ibm_grid *g) {
     return G;
 }
 
-hipError_t refresh(ibm_grid *g, CV3 src, V3 dst, hipStream_t s) {
+hipError_t refresh(ibm_grid *g, CV3 src, V3 dst, hipStream_t s, double *scr = nullptr) {
     if (g->ng == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dirichlet_refresh, dim3((unsigned)((8 * g->ng + DREF_NT - 1) / DREF_NT)), dim3(DREF_NT), 0,
-                       s, ghosts(g), g->g_betaD, g->g_betaDg, g->g_ubi, src, dst, g->nx, g->ny, g->nz, g->type);
+                       s, ghosts(g), g->g_betaD, g->g_betaDg, g->g_ubi, src, dst, g->nx, g->ny, g->nz, g->type,
+                       scr);
+    if (scr)
+        hipLaunchKernelGGL(k_ghost_scatter, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, g->ng, g->g_cell,
+                           scr, dst);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // ---- host driver ------------------------------------------------------------------------
-// uvw: three device arrays (u, v, w) of N doubles, in: u^n, out: u*.  hc: three arrays, in
-// H^{n-1} (ignored on the first step), out H^n.  work: six N-arrays of workspace.
-// omega: the schedule (m factors), one cycle = m sweeps.  Reads one pinned scalar per cycle.
+// uvw: three device arrays (u, v, w) of N doubles, in: u^n (its ghost rows are applied in
+// place, from a snapshot held in a per-ghost scratch), out: u*.  hc: three arrays, in
+// H^{n-1} (ignored on the first step), out H^n.  work: the right-hand side b (0..2) and the
+// second iterate buffer (3..5).
 hipError_t momentum_enqueue_prep(ibm_grid *g, double *const uvw[3], double *const hc[3], double *const work[6],
                                  double dt, double a, int first, hipStream_t s) {
-    const int64_t N = g->N;
     const CV3 U = cv3(uvw[0], uvw[1], uvw[2]);
-    const V3 W = v3(work[3], work[4], work[5]);
-    hipLaunchKernelGGL(k_mom_prep, dim3((unsigned)((N + MOM_NT - 1) / MOM_NT)), dim3(MOM_NT), 0, s, N, g->type, U, W);
-    hipError_t e = refresh(g, U, W, s);
+    hipError_t e = refresh(g, U, v3(uvw[0], uvw[1], uvw[2]), s, g->g_uscr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mom_rhs, dim3(RED_BLOCKS), dim3(MOM_NT), 0, s, mom_view(g), cv3(work[3], work[4], work[5]),
-                       v3(hc[0], hc[1], hc[2]), v3(work[0], work[1], work[2]), dt, a, first, g->partials);
-    hipLaunchKernelGGL(k_mom_sum, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, &g->sc->mom_b2);
+    const ZTiles t = ztiles(g->nx, g->ny, g->nz);
+    hipLaunchKernelGGL(k_mom_rhs, dim3(t.grid), dim3(ZM_NT), 0, s, mom_view(g), U, v3(hc[0], hc[1], hc[2]),
+                       v3(work[0], work[1], work[2]), dt, a, first, t, g->partials);
+    hipLaunchKernelGGL(k_mom_sum, dim3(1), dim3(256), 0, s, g->partials, t.grid, &g->sc->mom_b2);
     return hipGetLastError();
 }
 
@@ -332,9 +456,10 @@ hipError_t momentum_enqueue_sweep(ibm_grid *g, double *const X[3], double *const
                                   double a, double omega, bool sum, hipStream_t s) {
     const CV3 x = cv3(X[0], X[1], X[2]);
     const V3 y = v3(Y[0], Y[1], Y[2]);
-    hipLaunchKernelGGL(k_srj_sweep, dim3(RED_BLOCKS), dim3(MOM_NT), 0, s, mom_view(g), x, y,
-                       cv3(work[0], work[1], work[2]), a, omega, g->partials);
-    if (sum) hipLaunchKernelGGL(k_mom_sum, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, &g->sc->mom_r2);
+    const ZTiles t = ztiles(g->nx, g->ny, g->nz);
+    hipLaunchKernelGGL(k_srj_sweep, dim3(t.grid), dim3(ZM_NT), 0, s, mom_view(g), x, y, cv3(work[0], work[1], work[2]),
+                       a, omega, t, g->partials);
+    if (sum) hipLaunchKernelGGL(k_mom_sum, dim3(1), dim3(256), 0, s, g->partials, t.grid, &g->sc->mom_r2);
     return refresh(g, x, y, s);
 }
 
