@@ -60,7 +60,11 @@ typedef enum { IBM_FP64 = 0, IBM_MIXED = 1 } ibm_precision;
                  enter the Krylov operator scaled by the local stencil diagonal, and the
                  fluid part of every residual is projected to zero volume-weighted mean (the
                  uniform source shift lambda).  Both methods converge to the same solution. */
-typedef enum { IBM_VCYCLE = 0, IBM_BICGSTAB = 1 } ibm_method;
+typedef enum { IBM_VCYCLE = 0, IBM_BICGSTAB = 1, IBM_BICGSTAB_SRJ = 2 } ibm_method;
+/* IBM_BICGSTAB_SRJ: the paper's own configuration (Section 2.1: BiCGStab with a scheduled
+   relaxed Jacobi preconditioner): each preconditioner application is srj_sweeps relaxed
+   Jacobi sweeps from zero, with the factors ibm_srj_schedule(max(0, cos(pi / srj_sweeps)),
+   srj_sweeps), each sweep followed by the ghost refresh.  FP64 only. */
 
 /* Solver options.  Defaults (ibm_default_opts): rel_tol 1e-10, max_cycles 200, V(2,2),
    64 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested,
@@ -73,7 +77,8 @@ typedef struct {
     ibm_precision precision; /* IBM_MIXED: FP32 V-cycle inside FP64 iterative refinement */
     int use_initial_guess;   /* 1: start from the p passed in */
     int fixed_cycles;        /* > 0: run exactly this many cycles, no convergence test */
-    int method;              /* IBM_VCYCLE or IBM_BICGSTAB (default) */
+    int method;              /* IBM_VCYCLE, IBM_BICGSTAB (default) or IBM_BICGSTAB_SRJ */
+    int srj_sweeps;          /* IBM_BICGSTAB_SRJ: sweeps per preconditioner application (16) */
 } ibm_solve_opts;
 
 typedef struct {

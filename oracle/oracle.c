@@ -62,7 +62,10 @@ typedef struct {
 typedef struct {
     double rel_tol;
     int max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles;
-    int method; /* 0: V-cycle iteration, 1: BiCGStab preconditioned by one V-cycle */
+    int method; /* 0: V-cycle iteration, 1: BiCGStab preconditioned by one V-cycle,
+                   2: BiCGStab preconditioned by srj_m scheduled relaxed Jacobi sweeps */
+    int srj_m;                /* method 2: sweeps per preconditioner application */
+    const double *srj_omega;  /* method 2: their relaxation factors, in order */
 } orc_opts;
 
 typedef struct {
@@ -1275,7 +1278,31 @@ static double norm_fluid(const orc_problem *P, const double *a) {
     return sqrt(s);
 }
 
-/* e = M r: one V-cycle for A e = r from e = 0 (lambda 0, ghost right-hand sides r_g/s_g) */
+/* m relaxed Jacobi sweeps of the fluid rows of A e = r (Section 2.1: the paper preconditions
+   BiCGStab with scheduled relaxed Jacobi), sweep k with factor omega[k]:
+     e_c <- (1 - w) e_c + w (sum_f a_f e_nb - r_c) / sum_f a_f,
+   each followed by one pass of the ghost rows (right-hand sides gh) */
+static void srj_sweeps(orc_problem *P, double *e, const double *r, const double *gh, int m, const double *omega) {
+    const int64_t n = P->ncell;
+    double *tmp = dalloc(n);
+    for (int q = 0; q < m; ++q) {
+        const double w = omega[q];
+#pragma omp parallel for
+        for (int64_t id = 0; id < n; ++id) {
+            if (P->type[id] != T_FLUID) { tmp[id] = e[id]; continue; }
+            int i = (int)(id % P->nx), j = (int)((id / P->nx) % P->ny), k = (int)(id / ((int64_t)P->nx * P->ny));
+            double num, diag;
+            stencil0(P, e, i, j, k, &num, &diag);
+            tmp[id] = (1.0 - w) * e[id] + w * ((num - r[id]) / diag);
+        }
+        memcpy(e, tmp, sizeof(double) * (size_t)n);
+        ghost_refresh_h(P, e, gh);
+    }
+    free(tmp);
+}
+
+/* e = M r from e = 0 (lambda 0, ghost right-hand sides r_g/s_g): one V-cycle (method 1) or
+   the scheduled relaxed Jacobi sweeps (method 2) */
 static void precondition(orc_problem *P, const double *r, double *e, double *gh, const orc_opts *o) {
     for (int64_t g = 0; g < P->nghost; ++g) {
         int64_t id = P->gcell[g];
@@ -1283,7 +1310,8 @@ static void precondition(orc_problem *P, const double *r, double *e, double *gh,
     }
     memset(e, 0, sizeof(double) * (size_t)P->ncell);
     ghost_refresh_h(P, e, gh);
-    vcycle_h(P, e, r, 0.0, gh, o);
+    if (o->method == 2) srj_sweeps(P, e, r, gh, o->srj_m, o->srj_omega);
+    else vcycle_h(P, e, r, 0.0, gh, o);
 }
 
 /* b - A x, projected */
@@ -1387,7 +1415,8 @@ int orc_solve(orc_problem *P, const double *f, double *p, const orc_opts *o, orc
     int status = ORC_OK, cyc = 0;
     double rel = ref > 0.0 ? r0 / ref : 0.0;
     st->first_norm = r0;
-    if (ref > 0.0 && o->method == 1) {
+    if (o->method == 2 && (o->srj_m < 1 || !o->srj_omega)) { free(rbuf); return ORC_E_ARG; }
+    if (ref > 0.0 && (o->method == 1 || o->method == 2)) {
         cyc = bicgstab(P, f, p, o, ref, hist, hist_len, &rel, &status);
         residual_norm(P, p, f, &lambda, rbuf);
     } else if (ref > 0.0) {

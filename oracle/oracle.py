@@ -29,13 +29,20 @@ def build_oracle(force: bool = False) -> str:
 class OracleOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_sweeps", C.c_int), ("use_initial_guess", C.c_int), ("fixed_cycles", C.c_int),
-                ("method", C.c_int)]
+                ("method", C.c_int), ("srj_m", C.c_int), ("srj_omega", C.POINTER(C.c_double))]
 
     @staticmethod
     def make(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, use_initial_guess=0,
-             fixed_cycles=0, method="mg"):
-        m = {"mg": 0, "vcycle": 0, "bicgstab": 1}[method] if isinstance(method, str) else int(method)
-        return OracleOpts(rel_tol, max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles, m)
+             fixed_cycles=0, method="mg", srj_omega=None):
+        """method "bicgstab_srj" needs srj_omega (the relaxation factors of one preconditioner
+        application, kept alive by the caller for the duration of the call)."""
+        m = ({"mg": 0, "vcycle": 0, "bicgstab": 1, "bicgstab_srj": 2}[method] if isinstance(method, str)
+             else int(method))
+        o = OracleOpts(rel_tol, max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles, m)
+        if srj_omega is not None:
+            o.srj_m = len(srj_omega)
+            o.srj_omega = srj_omega.ctypes.data_as(C.POINTER(C.c_double))
+        return o
 
 
 class _Stats(C.Structure):
@@ -244,6 +251,9 @@ class OracleProblem:
         return act, T
 
     def solve(self, f, p0=None, hist_len=256, **kw):
+        om = kw.get("srj_omega")
+        if om is not None:
+            kw["srj_omega"] = om = np.ascontiguousarray(om, dtype=np.float64)
         o = OracleOpts.make(**kw)
         f = np.ascontiguousarray(f, dtype=np.float64)
         p = np.zeros(self.shape) if p0 is None else np.array(p0, dtype=np.float64, order="C", copy=True)

@@ -217,6 +217,7 @@ void ibm_default_opts(ibm_solve_opts *o) {
     o->use_initial_guess = 0;
     o->fixed_cycles = 0;
     o->method = IBM_BICGSTAB;
+    o->srj_sweeps = 16;
 }
 
 ibm_status ibm_create_grid(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
@@ -515,9 +516,22 @@ static ibm_status check_opts(ibm_grid *g, const ibm_solve_opts *o) {
     if (o->precision == IBM_MIXED && g->prec != IBM_MIXED)
         return fail(g, IBM_E_STATE, "mixed precision needs a workspace bound with IBM_MIXED");
     if (o->precision != IBM_FP64 && o->precision != IBM_MIXED) return fail(g, IBM_E_ARG, "unknown precision");
-    if (o->method != IBM_VCYCLE && o->method != IBM_BICGSTAB) return fail(g, IBM_E_ARG, "unknown method");
+    if (o->method != IBM_VCYCLE && o->method != IBM_BICGSTAB && o->method != IBM_BICGSTAB_SRJ)
+        return fail(g, IBM_E_ARG, "unknown method");
+    if (o->method == IBM_BICGSTAB_SRJ) {
+        if (o->precision != IBM_FP64) return fail(g, IBM_E_ARG, "the scheduled-Jacobi preconditioner is FP64 only");
+        if (o->srj_sweeps < 1 || o->srj_sweeps > IBM_SRJ_MAX) return fail(g, IBM_E_ARG, "srj_sweeps out of range");
+        // the schedule of this solve: Chebyshev factors on [1 - cos(pi/m), 1 + cos(pi/m)]
+        const int m = o->srj_sweeps;
+        g->srj_omega.assign(m, 0.0);
+        if (ibm_srj_schedule(std::max(0.0, std::cos(M_PI / m)), m, g->srj_omega.data()) != IBM_OK)
+            return fail(g, IBM_E_ARG, "schedule");
+    }
     return IBM_OK;
 }
+
+// BiCGStab outer iteration (with either preconditioner)
+static bool krylov_method(int method) { return method == IBM_BICGSTAB || method == IBM_BICGSTAB_SRJ; }
 
 // enqueue: lambda reset, reference norm, initial iterate + ghost refresh, first residual norm
 static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, hipStream_t s) {
@@ -525,7 +539,7 @@ static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const
     if ((e = hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s)) != hipSuccess) return e;
     if ((e = ref_norm_pass(g, rhs, s)) != hipSuccess) return e;
     if ((e = init_solution(g, p, g->p2, o->use_initial_guess, s)) != hipSuccess) return e;
-    if (o->method == IBM_BICGSTAB) {
+    if (krylov_method(o->method)) {
         if ((e = hipMemsetAsync(g->kv[2], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(g->kv[3], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
         if ((e = krylov_residual(g, rhs, g->p2, s)) != hipSuccess) return e;
@@ -537,7 +551,7 @@ static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const
 
 static hipError_t enqueue_cycle(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, int *cur,
                                 hipStream_t s) {
-    if (o->method == IBM_BICGSTAB) {
+    if (krylov_method(o->method)) {
         *cur = 1;  // the Krylov iterate lives in the second buffer
         return krylov_step(g, g->p2, o, s);
     }
@@ -646,7 +660,7 @@ static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ib
     ibm_status cs = check_opts(g, o);
     if (cs != IBM_OK) return cs;
     if (!rhs || !p) return fail(g, IBM_E_ARG, "NULL rhs or p");
-    if (o->method == IBM_BICGSTAB) {
+    if (krylov_method(o->method)) {
         HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
         return solve_krylov(g, rhs, p, o, st, s);
     }
@@ -814,7 +828,7 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
             *done = 1;
             if (st) {
                 st->cycles = S.cycles;
-                st->vcycles = (S.o.method == IBM_BICGSTAB) ? 2 * S.cycles : S.cycles;
+                st->vcycles = (krylov_method(S.o.method)) ? 2 * S.cycles : S.cycles;
                 st->rel_residual = hs->rel;
                 st->ghost_residual_max = 0.0;
                 st->lambda = hs->lambda;
@@ -844,7 +858,7 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
                 S.status = IBM_E_NUMERIC;
                 finish = true;
             } else if (S.o.fixed_cycles <= 0 && hs->rel <= S.o.rel_tol) {
-                if (S.o.method == IBM_BICGSTAB && S.phase == 0) {
+                if (krylov_method(S.o.method) && S.phase == 0) {
                     // confirm with the true residual before finishing (restarts the recurrences)
                     HIP_TRY(krylov_residual(g, S.rhs, g->p2, S.stream), "true residual");
                     HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream),
@@ -859,7 +873,7 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
             } else if (S.cycles >= ncyc) {
                 if (S.o.fixed_cycles <= 0) S.status = IBM_NOT_CONVERGED;
                 finish = true;
-            } else if (S.o.method == IBM_BICGSTAB) {
+            } else if (krylov_method(S.o.method)) {
                 S.phase = 0;
                 if (hs->rho == 0.0) HIP_TRY(krylov_restart(g, S.stream), "restart");
             }

@@ -282,6 +282,59 @@ __global__ void __launch_bounds__(ZM_NT)
     zm_block_sum_store<ZM_NT>(psum, partials);
 }
 
+// ---- relaxed Jacobi sweep (the scheduled-Jacobi preconditioner) -------------------------
+// out = (1 - omega) y + omega (sum_f a_f y_nb - f) / sum_f a_f on fluid cells, y elsewhere
+// (ghost cells are refreshed afterwards).  Same z-march as the operator above.
+__global__ void __launch_bounds__(ZM_NT)
+    k_jacobi0_zm(Fine<double> F, const double *__restrict__ y, const double *__restrict__ f, double *__restrict__ out,
+                 double omega, ZTiles t) {
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) return;
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const double axm = F.axm[ic], axp = F.axp[ic], aym = F.aym[jc], ayp = F.ayp[jc];
+    auto ld = [=](int k) -> RPlane<double> {
+        RPlane<double> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = y[base + (kk < nz - 1 ? plane : 0)];
+        d.xm = y[base + dxm];
+        d.xp = y[base + dxp];
+        d.ym = y[base + dym];
+        d.yp = y[base + dyp];
+        d.fv = f[base];
+        d.ty = F.type[base];
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        return d;
+    };
+    double ym1 = (z.k0 > 0) ? y[(int64_t)(z.k0 - 1) * plane + rowoff] : 0.0;
+    double yc = y[(int64_t)z.k0 * plane + rowoff];
+#define IBM_JACOBI_PLANE(D, kk)                                                                                   \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        double num, diag;                                                                                          \
+        zm_stencil<double>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,  \
+                           (D).xp, (D).ym, (D).yp, ym1, (D).pp, num, diag);                                        \
+        const double v = ((D).ty == T_FLUID) ? (1.0 - omega) * yc + omega * ((num - (D).fv) / diag) : yc;         \
+        if (in && k_ < z.k1) out[(int64_t)k_ * plane + rowoff] = v;                                                \
+        ym1 = yc;                                                                                                  \
+        yc = (D).pp;                                                                                               \
+    }
+    RPlane<double> qa = ld(z.k0), qb;
+    for (int k = z.k0; k < z.k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_JACOBI_PLANE(qa, k);
+        qa = ld(k + 2);
+        IBM_JACOBI_PLANE(qb, k + 1);
+    }
+#undef IBM_JACOBI_PLANE
+}
+
 // ---- paired-column variants (nx even) ----------------------------------------------------
 // A thread owns two adjacent columns (16-byte loads); a 256-thread workgroup covers 64 x 8
 // columns and a wave holds two rows (lanes l and l + 32).  For the restriction a thread's
@@ -551,6 +604,13 @@ hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w,
 }
 
 // upper bound of the workgroup count of any z-march launch, whatever the CU count
+hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *f, double *out, double omega,
+                          hipStream_t s) {
+    const ZTiles t = ztiles(F.nx, F.ny, F.nz);
+    hipLaunchKernelGGL(k_jacobi0_zm, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, f, out, omega, t);
+    return hipGetLastError();
+}
+
 int64_t zmarch_partials_max(int nx, int ny, int nz) {
     const int64_t per_slab = (int64_t)((nx + ZM_TX - 1) / ZM_TX) * ((ny + ZM_TY - 1) / ZM_TY);
     return per_slab * std::max(1, nz / 2 + 1) + 8;

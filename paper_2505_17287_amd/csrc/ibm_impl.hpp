@@ -77,6 +77,8 @@ hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coar
                            hipStream_t s);
 hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
                               hipStream_t s);
+hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *f, double *out, double omega,
+                          hipStream_t s);
 int64_t zmarch_partials_max(int nx, int ny, int nz);
 
 struct GhostView {
@@ -218,6 +220,7 @@ struct ibm_grid {
     double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
     double *g_uscr = nullptr;              // 3 per ghost: held-back ghost values of an in-place pass
     double diag_max = -1.0;                // max over cells of the flux-coefficient sum (< 0: not read yet)
+    std::vector<double> srj_omega;         // relaxation factors of the scheduled-Jacobi preconditioner
     // Krylov vectors (FP64, full grid)
     double *kv[10] = {nullptr};
     // multigrid

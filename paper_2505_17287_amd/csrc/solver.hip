@@ -1480,6 +1480,8 @@ __global__ void k_widen(const uint8_t *__restrict__ type, int64_t N, const float
 // y = M r: one V-cycle from zero on the error equation with right-hand side r (fluid) and
 // ghost right-hand sides r_g / s_g.  FP64: the result lands in one of (ya, yb), returned.
 // Mixed: the cycle runs in FP32 on the workspace's FP32 buffers and is widened into ya.
+// IBM_BICGSTAB_SRJ: instead of the V-cycle, the scheduled relaxed Jacobi sweeps of the
+// grid's schedule, each followed by the ghost refresh (FP64).
 static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double *yb, double **out,
                                const ibm_solve_opts *o, hipStream_t s) {
     hipError_t e;
@@ -1496,6 +1498,21 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
         if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
         *out = ya;
+    } else if (o->method == IBM_BICGSTAB_SRJ) {
+        // scheduled relaxed Jacobi: every sweep writes all cells of the other buffer
+        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, (double *)nullptr);
+        if (g->ng > 0)
+            hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
+                               g->g_scale, r, g->g_rhs, ya);
+        double *bufs[2] = {ya, yb};
+        int cur = 0;
+        const Fine<double> F = fine64(g);
+        for (double w : g->srj_omega) {
+            if ((e = launch_jacobi0(F, bufs[cur], r, bufs[1 - cur], w, s)) != hipSuccess) return e;
+            if ((e = launch_refresh<double>(g, bufs[cur], bufs[1 - cur], g->g_rhs, s)) != hipSuccess) return e;
+            cur = 1 - cur;
+        }
+        *out = bufs[cur];
     } else {
         hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya,
                            o->nu1 > 0 ? (double *)nullptr : yb);

@@ -25,7 +25,7 @@ _STATUS = {0: "IBM_OK", 1: "IBM_NOT_CONVERGED", -1: "IBM_E_ARG", -2: "IBM_E_STAT
 class SolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_sweeps", C.c_int), ("precision", C.c_int), ("use_initial_guess", C.c_int),
-                ("fixed_cycles", C.c_int), ("method", C.c_int)]
+                ("fixed_cycles", C.c_int), ("method", C.c_int), ("srj_sweeps", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -34,7 +34,8 @@ class SolveStats(C.Structure):
                 ("t_solve", C.c_double), ("t_correct", C.c_double), ("vcycles", C.c_int)]
 
 
-IBM_VCYCLE, IBM_BICGSTAB = 0, 1
+IBM_VCYCLE, IBM_BICGSTAB, IBM_BICGSTAB_SRJ = 0, 1, 2
+_METHODS = {"vcycle": IBM_VCYCLE, "bicgstab": IBM_BICGSTAB, "bicgstab_srj": IBM_BICGSTAB_SRJ}
 IBM_SRJ_MAX = 256
 
 
@@ -133,7 +134,7 @@ def declared_symbols(header=None):
 
 
 def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, precision="fp64",
-              use_initial_guess=False, fixed_cycles=0, method="bicgstab"):
+              use_initial_guess=False, fixed_cycles=0, method="bicgstab", srj_sweeps=16):
     o = SolveOpts()
     lib().ibm_default_opts(C.byref(o))
     o.rel_tol = rel_tol
@@ -142,7 +143,8 @@ def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, p
     o.precision = IBM_MIXED if precision in ("mixed", IBM_MIXED) else IBM_FP64
     o.use_initial_guess = int(bool(use_initial_guess))
     o.fixed_cycles = fixed_cycles
-    o.method = {"vcycle": IBM_VCYCLE, "bicgstab": IBM_BICGSTAB}[method] if isinstance(method, str) else int(method)
+    o.method = _METHODS[method] if isinstance(method, str) else int(method)
+    o.srj_sweeps = int(srj_sweeps)
     return o
 
 

@@ -141,6 +141,47 @@ def test_solve_converged(name, method):
     assert abs(sg2.cycles - sr2.cycles) <= 1
 
 
+def _srj_omega(m=16):
+    from oracle.momentum import srj_schedule
+    return srj_schedule(max(0.0, np.cos(np.pi / m)), m)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_srj_preconditioned_fixed_cycles(name):
+    """The paper's configuration (BiCGStab + scheduled relaxed Jacobi): same schedule, same
+    number of steps, iterates agree to rounding."""
+    torch = _torch()
+    wl, P, g, counts = _pair(name)
+    u, v, w = wl.velocity()
+    f = P.rhs(u, v, w)
+    fd = torch.from_numpy(f).cuda()
+    act = P.types() != 2
+    for ncyc in (1, 4):
+        pr, sr = P.solve(f, fixed_cycles=ncyc, method="bicgstab_srj", srj_omega=_srj_omega(16))
+        pg, sg = g.poisson_solve(fd, fixed_cycles=ncyc, method="bicgstab_srj", srj_sweeps=16)
+        assert sg.cycles == ncyc
+        assert _rel(pg.cpu().numpy(), pr, act) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["cylinder2d", "spheres48"])
+def test_srj_preconditioned_converged(name):
+    """Converged to 1e-12: the same discrete solution as the multigrid-preconditioned solve."""
+    torch = _torch()
+    wl, P, g, counts = _pair(name)
+    u, v, w = wl.velocity()
+    f = P.rhs(u, v, w)
+    fd = torch.from_numpy(f).cuda()
+    act = P.types() != 2
+    pr, sr = P.solve(f, rel_tol=1e-12, method="vcycle", max_cycles=400)
+    pg, sg = g.poisson_solve(fd, rel_tol=1e-12, method="bicgstab_srj", srj_sweeps=16, max_cycles=3000)
+    assert sg.status == 0 and sg.rel_residual <= 1e-12
+    assert _rel(pg.cpu().numpy(), pr, act) <= 1e-9
+    assert abs(sg.lam - sr.lam) <= 1e-9 * max(abs(sr.lam), np.abs(f).max() * 1e-6)
+    print(name, "SRJ-BiCGStab steps", sg.cycles, flush=True)
+    with pytest.raises(Exception):
+        g.poisson_solve(fd, method="bicgstab_srj", srj_sweeps=0)
+
+
 @pytest.mark.parametrize("name", ["wing_small", "spheres48", "cylinder2d"])
 def test_projection_matches(name):
     torch = _torch()

@@ -154,7 +154,14 @@ def dense_bordered_solution(P, f):
     return x[:n].reshape(P.shape), x[n]
 
 
-@pytest.mark.parametrize("method", ["vcycle", "bicgstab"])
+def srj_pressure_schedule(m):
+    """Relaxation factors of the SRJ preconditioner: the Chebyshev schedule on
+    [1 - cos(pi/m), 1 + cos(pi/m)] (oracle.momentum.srj_schedule)."""
+    from oracle.momentum import srj_schedule
+    return srj_schedule(np.cos(np.pi / m), m)
+
+
+@pytest.mark.parametrize("method", ["vcycle", "bicgstab", "bicgstab_srj"])
 @pytest.mark.parametrize("case", ["sphere3d", "plate3d", "cylinder2d"])
 def test_multigrid_equals_dense_bordered_solve(case, method):
     if case == "sphere3d":
@@ -173,7 +180,8 @@ def test_multigrid_equals_dense_bordered_solve(case, method):
     f = rng.standard_normal(P.shape) * (P.types() == 0)
     # nonzero Neumann data so the ghost right-hand sides are exercised
     P.set_neumann(rng.standard_normal(len(P.ghost_cells())))
-    p, st = P.solve(f, rel_tol=1e-13, max_cycles=200, method=method)
+    kw = dict(srj_omega=srj_pressure_schedule(8)) if method == "bicgstab_srj" else {}
+    p, st = P.solve(f, rel_tol=1e-13, max_cycles=200, method=method, **kw)
     assert st.status == 0
     pd, lam = dense_bordered_solution(P, f)
     act = P.types() != 2
