@@ -219,6 +219,101 @@ __global__ void __launch_bounds__(ZM_NT)
 #undef IBM_PROLONG_PLANE
 }
 
+// Prolongation when z is halved (the usual case).  Fine planes 2K and 2K+1 have the coarse
+// plane K as their first contributor and K-1 or K+1 as their second, so a column needs one
+// new coarse plane per pair of fine planes: a window of three coarse planes (four
+// contributor values each) stays in registers, and the next coarse plane and the next two
+// fine planes are loaded before the current pair is computed.  Same arithmetic, order of
+// summation and injection rule as k_prolong0_zm.
+template <typename T>
+struct CPlane4 {
+    T v[4];  // [b][a]: y contributor b, x contributor a
+};
+template <typename T>
+struct FPlaneZ {
+    T pv;
+    uint8_t ty, inj;
+    int dz;     // second z contributor minus the first: -1, 0 or +1
+    double tz;  // its weight
+};
+
+template <typename T>
+__global__ void __launch_bounds__(ZM_NT)
+    k_prolong0_zh(Fine<T> F, const T *__restrict__ pcur, T *__restrict__ pnext, Coarse<T> C, ProlongTab P,
+                  ZTiles t) {
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) return;
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    const int ix[2] = {P.lo[0][ic], P.hi[0][ic]}, iy[2] = {P.lo[1][jc], P.hi[1][jc]};
+    const double tx = P.t[0][ic], ty = P.t[1][jc];
+    const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty};
+    const bool twox = ix[0] != ix[1], twoy = iy[0] != iy[1];
+    const int64_t cny = C.n[1], cnx = C.n[0];
+    const int cnz = C.n[2];
+    auto ldc = [&](int K) -> CPlane4<T> {
+        CPlane4<T> c;
+        const int64_t Kc = min(max(K, 0), cnz - 1);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) c.v[2 * b + a] = C.e[(Kc * cny + iy[b]) * cnx + ix[a]];
+        return c;
+    };
+    auto ldf = [&](int k) -> FPlaneZ<T> {
+        FPlaneZ<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pv = pcur[base];
+        d.ty = F.type[base];
+        d.inj = F.inject[base];
+        d.dz = P.hi[2][kk] - P.lo[2][kk];
+        d.tz = P.t[2][kk];
+        return d;
+    };
+    auto fine = [&](const FPlaneZ<T> &D, int k, const CPlane4<T> &lo, const CPlane4<T> &hi) {
+        const double wz[2] = {1.0 - D.tz, D.tz};
+        const bool twoz = D.dz != 0;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const bool ok = (a == 0 || twox) && (b == 0 || twoy) && (c == 0 || twoz);
+                    const double e = (double)(c == 0 ? lo.v[2 * b + a] : hi.v[2 * b + a]);
+                    const double term = (wx[a] * wy[b]) * wz[c] * e;
+                    if (ok) s += term;
+                }
+        if (D.inj) s = (double)lo.v[0];
+        if (in && k < z.k1 && D.ty == T_FLUID) pnext[(int64_t)k * plane + rowoff] = (T)((double)D.pv + s);
+    };
+    // four coarse-plane slots and two fine-pair slots rotate by name (unrolled by four
+    // pairs), so no register copy of a value still in flight stalls the queue
+    const int K0 = z.k0 >> 1;
+    CPlane4<T> q0 = ldc(K0 - 1), q1 = ldc(K0), q2 = ldc(K0 + 1), q3;
+    FPlaneZ<T> fa = ldf(z.k0), fb = ldf(z.k0 + 1), ga, gb;
+#define IBM_PROLONG_PAIR(CM, C0, CP, CN, FA, FB, NA, NB, kk)                                                      \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        CN = ldc((k_ >> 1) + 2);                                                                                   \
+        NA = ldf(k_ + 2);                                                                                          \
+        NB = ldf(k_ + 3);                                                                                          \
+        fine(FA, k_, C0, FA.dz < 0 ? CM : (FA.dz > 0 ? CP : C0));                                                  \
+        fine(FB, k_ + 1, C0, FB.dz < 0 ? CM : (FB.dz > 0 ? CP : C0));                                              \
+    }
+    for (int k = z.k0; k < z.k1; k += 8) {
+        IBM_PROLONG_PAIR(q0, q1, q2, q3, fa, fb, ga, gb, k);
+        IBM_PROLONG_PAIR(q1, q2, q3, q0, ga, gb, fa, fb, k + 2);
+        IBM_PROLONG_PAIR(q2, q3, q0, q1, fa, fb, ga, gb, k + 4);
+        IBM_PROLONG_PAIR(q3, q0, q1, q2, ga, gb, fa, fb, k + 6);
+    }
+#undef IBM_PROLONG_PAIR
+}
+
 // ---- Krylov operator ---------------------------------------------------------------------
 // w = S y on fluid rows, 0 elsewhere; partials[block] = sum over the block of V w.  The loads
 // of plane k+1 are issued before plane k is computed.
@@ -584,8 +679,11 @@ hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *l
 template <typename T>
 hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coarse<T> &C, const ProlongTab &P,
                            hipStream_t s) {
-    const ZTiles t = ztiles(F.nx, F.ny, F.nz);
-    hipLaunchKernelGGL(k_prolong0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
+    const ZTiles t = ztiles(F.nx, F.ny, F.nz);  // chunks start at even planes and have even length
+    if (P.halved[2] && (F.nz & 1) == 0)
+        hipLaunchKernelGGL(k_prolong0_zh<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
+    else
+        hipLaunchKernelGGL(k_prolong0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
     return hipGetLastError();
 }
 
