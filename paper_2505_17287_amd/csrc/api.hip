@@ -195,8 +195,11 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
             }
         }
     }
-    G->partials = P.take<double>(std::max<int64_t>(std::max<int64_t>(4 * RED_BLOCKS, N / 256 + 1024),
-                                                   zmarch_partials_max(nx, ny, nz)));
+    // the largest of: reductions over RED_BLOCKS workgroups (up to 4 sums), the coarsening
+    // sums, and one Krylov operator pass (2 sums per z-march workgroup, then 2 per ghost block)
+    G->partials = P.take<double>(std::max<int64_t>(
+        std::max<int64_t>(4 * RED_BLOCKS, N / 256 + 1024),
+        2 * zmarch_partials_max(nx, ny, nz) + 2 * (std::max<int64_t>(gmax, 1) / 256 + 2)));
     G->sc = P.take<Scalars>(1);
     return P.off + 256;
 }

@@ -54,6 +54,25 @@ __device__ __forceinline__ void zm_block_sum_store(double v, double *partials) {
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// NS sums per workgroup, stored at partials[NS * block + q]
+template <int NT, int NS>
+__device__ __forceinline__ void zm_block_sums_store(const double (&v)[NS], double *partials) {
+    __shared__ double sh[NT / 64];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const double s = block_sum<NT>(v[q], sh, threadIdx.x);
+        if (threadIdx.x == 0) partials[NS * blockIdx.x + q] = s;
+    }
+}
+
+// Sums of the Krylov operator passes.  DOTS 0: w = S y, sum V w.  DOTS 1 and 2: w = S y - mu
+// (the image with its volume-weighted fluid mean, known beforehand, removed), sum o w, and
+// for DOTS 2 also sum w w (o is the vector the image is dotted with: the shadow residual or s)
+template <int DOTS>
+struct ApplySums {
+    static constexpr int NS = DOTS == 2 ? 2 : 1;
+};
+
 // ---- residual + restriction --------------------------------------------------------------
 // R_1(C) = sum over fluid children c of V_c r_c with r = (f - lambda) - S p; e_1 = 0;
 // partials[block] = sum of the R_1 written by the block.  The loads of plane k+1 are issued
@@ -315,14 +334,19 @@ __global__ void __launch_bounds__(ZM_NT)
 }
 
 // ---- Krylov operator ---------------------------------------------------------------------
-// w = S y on fluid rows, 0 elsewhere; partials[block] = sum over the block of V w.  The loads
-// of plane k+1 are issued before plane k is computed.
+// w = S y on fluid rows, 0 elsewhere, with the sums of ApplySums<DOTS> over the block (the
+// fluid rows' contributions; w is 0 elsewhere).  The loads of plane k+1 are issued before
+// plane k is computed.
+template <int DOTS>
 __global__ void __launch_bounds__(ZM_NT)
-    k_apply_fluid_zm(Fine<double> F, const double *__restrict__ y, double *__restrict__ w, ZTiles t,
-                     double *partials) {
+    k_apply_fluid_zm(Fine<double> F, const double *__restrict__ y, double *__restrict__ w,
+                     const double *__restrict__ o, const double *__restrict__ mup, ZTiles t, double *partials) {
+    constexpr int NS = ApplySums<DOTS>::NS;
+    const double mu = DOTS ? *mup : 0.0;
     const ZPos z = zpos(t, F.nz);
     if (!z.live) {
-        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        if (threadIdx.x == 0)
+            for (int q = 0; q < NS; ++q) partials[NS * blockIdx.x + q] = 0.0;
         return;
     }
     const int nx = F.nx, ny = F.ny, nz = F.nz;
@@ -346,11 +370,14 @@ __global__ void __launch_bounds__(ZM_NT)
         d.azm = F.azm[kk];
         d.azp = F.azp[kk];
         d.wz = F.wz[kk];
+        d.fv = DOTS ? o[base] : 0.0;
         return d;
     };
     double ym1 = (z.k0 > 0) ? y[(int64_t)(z.k0 - 1) * plane + rowoff] : 0.0;
     double yc = y[(int64_t)z.k0 * plane + rowoff];
-    double psum = 0.0;
+    double acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
 #define IBM_APPLY_PLANE(D, kk)                                                                                    \
     {                                                                                                              \
         const int k_ = (kk);                                                                                       \
@@ -358,10 +385,12 @@ __global__ void __launch_bounds__(ZM_NT)
         zm_stencil<double>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,  \
                            (D).xp, (D).ym, (D).yp, ym1, (D).pp, num, diag);                                        \
         const bool fl = in && (D).ty == T_FLUID;                                                                   \
-        const double a = fl ? num - diag * yc : 0.0;                                                               \
+        const double a = fl ? (DOTS ? (num - diag * yc) - mu : num - diag * yc) : 0.0;                             \
         if (in && k_ < z.k1) {                                                                                     \
             w[(int64_t)k_ * plane + rowoff] = a;                                                                   \
-            psum += (vxy * (D).wz) * a;                                                                            \
+            if (DOTS == 0) acc[0] += (vxy * (D).wz) * a;                                                           \
+            if (DOTS >= 1) acc[0] += (D).fv * a;                                                                   \
+            if (DOTS == 2) acc[1 % NS] += a * a;                                                                   \
         }                                                                                                          \
         ym1 = yc;                                                                                                  \
         yc = (D).pp;                                                                                               \
@@ -374,7 +403,7 @@ __global__ void __launch_bounds__(ZM_NT)
         IBM_APPLY_PLANE(qb, k + 1);
     }
 #undef IBM_APPLY_PLANE
-    zm_block_sum_store<ZM_NT>(psum, partials);
+    zm_block_sums_store<ZM_NT, NS>(acc, partials);
 }
 
 // ---- relaxed Jacobi sweep (the scheduled-Jacobi preconditioner) -------------------------
@@ -588,13 +617,17 @@ __global__ void __launch_bounds__(ZP_NT)
     zm_block_sum_store<ZP_NT>(psum, partials);
 }
 
+template <int DOTS>
 __global__ void __launch_bounds__(ZP_NT)
-    k_apply_fluid_zm2(Fine<double> F, const double *__restrict__ y, double *__restrict__ w, ZTiles t,
-                      double *partials) {
+    k_apply_fluid_zm2(Fine<double> F, const double *__restrict__ y, double *__restrict__ w,
+                      const double *__restrict__ o, const double *__restrict__ mup, ZTiles t, double *partials) {
     using V = double2;
+    constexpr int NS = ApplySums<DOTS>::NS;
+    const double mu = DOTS ? *mup : 0.0;
     const ZPos2 z = zpos2(t, F.nz);
     if (!z.live) {
-        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        if (threadIdx.x == 0)
+            for (int q = 0; q < NS; ++q) partials[NS * blockIdx.x + q] = 0.0;
         return;
     }
     const int nx = F.nx, ny = F.ny, nz = F.nz;
@@ -619,11 +652,14 @@ __global__ void __launch_bounds__(ZP_NT)
         d.azm = F.azm[kk];
         d.azp = F.azp[kk];
         d.wz = F.wz[kk];
+        d.fv = DOTS ? *reinterpret_cast<const V *>(o + base) : V{0.0, 0.0};
         return d;
     };
     V ym1 = (z.k0 > 0) ? *reinterpret_cast<const V *>(y + (int64_t)(z.k0 - 1) * plane + rowoff) : V{0.0, 0.0};
     V yc = *reinterpret_cast<const V *>(y + (int64_t)z.k0 * plane + rowoff);
-    double psum = 0.0;
+    double acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
 #define IBM_APPLY_PLANE2(D, kk)                                                                                   \
     {                                                                                                              \
         const int k_ = (kk);                                                                                       \
@@ -633,15 +669,27 @@ __global__ void __launch_bounds__(ZP_NT)
                            (D).ym.x, (D).yp.x, ym1.x, (D).pp.x, n0, d0);                                           \
         zm_stencil<double>(axm1, axp1, aym, ayp, (D).azm, (D).azp, true, hx1, hy0, hy1, z0_, z1_, yc.x, (D).xp,   \
                            (D).ym.y, (D).yp.y, ym1.y, (D).pp.y, n1, d1);                                           \
-        const double a0 = (in && ((D).tt & 0xff) == T_FLUID) ? n0 - d0 * yc.x : 0.0;                              \
-        const double a1 = (in && ((D).tt >> 8) == T_FLUID) ? n1 - d1 * yc.y : 0.0;                                \
+        const double a0 = (in && ((D).tt & 0xff) == T_FLUID) ? (DOTS ? (n0 - d0 * yc.x) - mu : n0 - d0 * yc.x)    \
+                                                             : 0.0;                                                \
+        const double a1 = (in && ((D).tt >> 8) == T_FLUID) ? (DOTS ? (n1 - d1 * yc.y) - mu : n1 - d1 * yc.y)      \
+                                                           : 0.0;                                                  \
         if (in && k_ < z.k1) {                                                                                     \
             V o_;                                                                                                  \
             o_.x = a0;                                                                                             \
             o_.y = a1;                                                                                             \
             *reinterpret_cast<V *>(w + (int64_t)k_ * plane + rowoff) = o_;                                         \
-            psum += (vxy0 * (D).wz) * a0;                                                                          \
-            psum += (vxy1 * (D).wz) * a1;                                                                          \
+            if (DOTS == 0) {                                                                                       \
+                acc[0] += (vxy0 * (D).wz) * a0;                                                                    \
+                acc[0] += (vxy1 * (D).wz) * a1;                                                                    \
+            }                                                                                                      \
+            if (DOTS >= 1) {                                                                                       \
+                acc[0] += (D).fv.x * a0;                                                                           \
+                acc[0] += (D).fv.y * a1;                                                                           \
+            }                                                                                                      \
+            if (DOTS == 2) {                                                                                       \
+                acc[1 % NS] += a0 * a0;                                                                            \
+                acc[1 % NS] += a1 * a1;                                                                            \
+            }                                                                                                      \
         }                                                                                                          \
         ym1 = yc;                                                                                                  \
         yc = (D).pp;                                                                                               \
@@ -654,7 +702,7 @@ __global__ void __launch_bounds__(ZP_NT)
         IBM_APPLY_PLANE2(qb, k + 1);
     }
 #undef IBM_APPLY_PLANE2
-    zm_block_sum_store<ZP_NT>(psum, partials);
+    zm_block_sums_store<ZP_NT, NS>(acc, partials);
 }
 
 }  // namespace
@@ -687,21 +735,28 @@ hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coar
     return hipGetLastError();
 }
 
-hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
-                              hipStream_t s) {
+template <int DOTS>
+static hipError_t apply_fluid_dots(const Fine<double> &F, const double *y, double *w, const double *o,
+                                   const double *mu, double *partials, int *nparts, hipStream_t s) {
     if ((F.nx & 1) == 0 && F.nx >= 2) {
         const ZTiles t = ztiles2(F.nx, F.ny, F.nz);
-        hipLaunchKernelGGL(k_apply_fluid_zm2, dim3(t.grid), dim3(ZP_NT), 0, s, F, y, w, t, partials);
+        hipLaunchKernelGGL(k_apply_fluid_zm2<DOTS>, dim3(t.grid), dim3(ZP_NT), 0, s, F, y, w, o, mu, t, partials);
         *nparts = t.grid;
         return hipGetLastError();
     }
     const ZTiles t = ztiles(F.nx, F.ny, F.nz);
-    hipLaunchKernelGGL(k_apply_fluid_zm, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, w, t, partials);
+    hipLaunchKernelGGL(k_apply_fluid_zm<DOTS>, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, w, o, mu, t, partials);
     *nparts = t.grid;
     return hipGetLastError();
 }
 
-// upper bound of the workgroup count of any z-march launch, whatever the CU count
+hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, const double *o, const double *mu,
+                              int dots, double *partials, int *nparts, hipStream_t s) {
+    if (dots == 1) return apply_fluid_dots<1>(F, y, w, o, mu, partials, nparts, s);
+    if (dots == 2) return apply_fluid_dots<2>(F, y, w, o, mu, partials, nparts, s);
+    return apply_fluid_dots<0>(F, y, w, o, mu, partials, nparts, s);
+}
+
 hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *f, double *out, double omega,
                           hipStream_t s) {
     const ZTiles t = ztiles(F.nx, F.ny, F.nz);
@@ -709,6 +764,7 @@ hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *
     return hipGetLastError();
 }
 
+// upper bound of the workgroup count of any z-march launch, whatever the CU count
 int64_t zmarch_partials_max(int nx, int ny, int nz) {
     const int64_t per_slab = (int64_t)((nx + ZM_TX - 1) / ZM_TX) * ((ny + ZM_TY - 1) / ZM_TY);
     return per_slab * std::max(1, nz / 2 + 1) + 8;

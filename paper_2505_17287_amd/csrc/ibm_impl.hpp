@@ -75,8 +75,11 @@ hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *l
 template <typename T>
 hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coarse<T> &C, const ProlongTab &P,
                            hipStream_t s);
-hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, double *partials, int *nparts,
-                              hipStream_t s);
+// Krylov operator on fluid rows.  dots 0: w = S y, one sum per workgroup (sum V w).  dots 1
+// and 2: w = S y - *mu (device scalar: the image's volume-weighted fluid mean), sums of o w and
+// (dots 2) of w w per workgroup, stored with a stride of 1 or 2.
+hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, const double *o, const double *mu,
+                              int dots, double *partials, int *nparts, hipStream_t s);
 hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *f, double *out, double omega,
                           hipStream_t s);
 int64_t zmarch_partials_max(int nx, int ny, int nz);

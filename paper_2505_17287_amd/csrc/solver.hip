@@ -1275,41 +1275,91 @@ __global__ void k_ghost_scale(int64_t ng, const int32_t *__restrict__ gcell, int
     scale[g] = d;
 }
 
-// ghost rows of A y (mode 0) or of b - A y (mode 1: out = s_g h_g - A y)
+// ghost rows of A y (mode 0) or of b - A y (mode 1: out = s_g h_g - A y).  With gpart, the
+// block sums of o_g out_g and out_g^2 over the ghost rows go to gpart[2 block + (0, 1)].
 __global__ void k_apply_ghost(GhostView G, const double *__restrict__ y, double *out, const double *__restrict__ scale,
-                              int nx, int ny, int nz, const uint8_t *__restrict__ type, int mode) {
+                              int nx, int ny, int nz, const uint8_t *__restrict__ type, int mode,
+                              const double *__restrict__ o, double *gpart) {
+    __shared__ double sh[4];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G.ng) return;
-    const int64_t cell = G.cell[g];
-    double target;
-    if (G.flags[g] & GF_DEGENERATE) {
-        int i, j, k;
-        unflatten(cell, nx, ny, i, j, k);
-        double s = 0.0;
-        int n = 0;
-        for (int dk = -1; dk <= 1; ++dk)
-            for (int dj = -1; dj <= 1; ++dj)
-                for (int di = -1; di <= 1; ++di) {
-                    const int ii = i + di, jj = j + dj, kk = k + dk;
-                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
-                    const int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
-                    if (type[q] == T_FLUID) {
-                        s += y[q];
-                        ++n;
+    double d0 = 0.0, d1 = 0.0;
+    if (g < G.ng) {
+        const int64_t cell = G.cell[g];
+        double target;
+        if (G.flags[g] & GF_DEGENERATE) {
+            int i, j, k;
+            unflatten(cell, nx, ny, i, j, k);
+            double s = 0.0;
+            int n = 0;
+            for (int dk = -1; dk <= 1; ++dk)
+                for (int dj = -1; dj <= 1; ++dj)
+                    for (int di = -1; di <= 1; ++di) {
+                        const int ii = i + di, jj = j + dj, kk = k + dk;
+                        if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                        const int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
+                        if (type[q] == T_FLUID) {
+                            s += y[q];
+                            ++n;
+                        }
                     }
-                }
-        target = n ? s / n : 0.0;
-    } else {
-        const int32_t *st = G.st + 8 * g;
-        const double *beta = G.beta + 8 * g;
-        double s = 0.0;
+            target = n ? s / n : 0.0;
+        } else {
+            const int32_t *st = G.st + 8 * g;
+            const double *beta = G.beta + 8 * g;
+            double s = 0.0;
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (st[m] >= 0) s = s + beta[m] * y[st[m]];
-        target = s;
+            for (int m = 0; m < 8; ++m)
+                if (st[m] >= 0) s = s + beta[m] * y[st[m]];
+            target = s;
+        }
+        const double a = scale[g] * (y[cell] - target);
+        const double v = mode ? scale[g] * G.h[g] - a : a;
+        out[cell] = v;
+        if (gpart) {
+            d0 = o[cell] * v;
+            d1 = v * v;
+        }
     }
-    const double a = scale[g] * (y[cell] - target);
-    out[cell] = mode ? scale[g] * G.h[g] - a : a;
+    if (gpart) {  // uniform: every thread of the block takes part in the sums
+        const double s0 = block_sum<256>(d0, sh, threadIdx.x);
+        const double s1 = block_sum<256>(d1, sh, threadIdx.x);
+        if (threadIdx.x == 0) {
+            gpart[2 * blockIdx.x] = s0;
+            gpart[2 * blockIdx.x + 1] = s1;
+        }
+    }
+}
+
+// The volume-weighted fluid sum of an operator image, before the image is formed.  Summed
+// over the fluid rows, V_c (S y)_c = sum_f T_f (y_nb - y_c) cancels on every face between two
+// fluid cells (T_f = V a_f is the same from both sides) and no flux crosses the box walls, so
+// only the faces between a fluid cell and a ghost cell remain: per block, the sum over ghosts
+// g and their fluid face neighbours c of V_c a_(c->g) (y_g - y_c).
+__global__ void k_ghost_flux(GhostView G, Fine<double> F, const double *__restrict__ y, double *partials) {
+    __shared__ double sh[4];
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (g < G.ng) {
+        const int64_t cell = G.cell[g];
+        int i, j, k;
+        unflatten(cell, F.nx, F.ny, i, j, k);
+        const int64_t sy = F.nx, sz = (int64_t)F.nx * F.ny;
+        const double yg = y[cell];
+        if (i > 0 && F.type[cell - 1] == T_FLUID)
+            acc += ((F.wx[i - 1] * F.wy[j]) * F.wz[k]) * F.axp[i - 1] * (yg - y[cell - 1]);
+        if (i < F.nx - 1 && F.type[cell + 1] == T_FLUID)
+            acc += ((F.wx[i + 1] * F.wy[j]) * F.wz[k]) * F.axm[i + 1] * (yg - y[cell + 1]);
+        if (j > 0 && F.type[cell - sy] == T_FLUID)
+            acc += ((F.wx[i] * F.wy[j - 1]) * F.wz[k]) * F.ayp[j - 1] * (yg - y[cell - sy]);
+        if (j < F.ny - 1 && F.type[cell + sy] == T_FLUID)
+            acc += ((F.wx[i] * F.wy[j + 1]) * F.wz[k]) * F.aym[j + 1] * (yg - y[cell + sy]);
+        if (k > 0 && F.type[cell - sz] == T_FLUID)
+            acc += ((F.wx[i] * F.wy[j]) * F.wz[k - 1]) * F.azp[k - 1] * (yg - y[cell - sz]);
+        if (k < F.nz - 1 && F.type[cell + sz] == T_FLUID)
+            acc += ((F.wx[i] * F.wy[j]) * F.wz[k + 1]) * F.azm[k + 1] * (yg - y[cell + sz]);
+    }
+    const double t = block_sum<256>(acc, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // r = f - (A x) on fluid rows (ghost rows written by k_apply_ghost mode 1), partial V-sums
@@ -1335,11 +1385,10 @@ __global__ void __launch_bounds__(NORM_NT) k_resid_fluid(Fine<double> F, const d
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// projection of the fluid part (v -= mu_v) fused with the inner products that follow it:
-//   mode 0 (alpha): sum rh.v ;  mode 1 (omega): sum t.s, sum t.t ;
-//   mode 2 (init) : rh = v, sum v.v (all), sum v.v (fluid)
-__global__ void __launch_bounds__(NORM_NT) k_project(const uint8_t *__restrict__ type, int64_t N, double *v,
-                                                     const double *__restrict__ other, double *rh,
+// start of the Krylov recurrences on the residual v: projection of its fluid part
+// (v -= mu_v; mode 2) or none (restart, mode 3), then rh = v and the sums v.v (all) and v.v
+// (fluid).  (The operator images of a step are projected where they are formed.)
+__global__ void __launch_bounds__(NORM_NT) k_project(const uint8_t *__restrict__ type, int64_t N, double *v, double *rh,
                                                      const Scalars *sc, int mode, double *partials) {
     __shared__ double sh[NORM_NT / 64];
     const double mu = sc->mu_v;
@@ -1352,16 +1401,9 @@ __global__ void __launch_bounds__(NORM_NT) k_project(const uint8_t *__restrict__
             x -= mu;
             v[id] = x;
         }
-        if (mode == 0) {
-            a += other[id] * x;
-        } else if (mode == 1) {
-            a += x * other[id];
-            b += x * x;
-        } else {
-            rh[id] = x;
-            a += x * x;
-            if (t == T_FLUID) b += x * x;
-        }
+        rh[id] = x;
+        a += x * x;
+        if (t == T_FLUID) b += x * x;
     }
     double s = block_sum<NORM_NT>(a, sh, threadIdx.x);
     if (threadIdx.x == 0) partials[2 * blockIdx.x] = s;
@@ -1381,8 +1423,8 @@ __global__ void k_krylov_finalize(const double *partials, int nb, int stride, Sc
     if (threadIdx.x != 0) return;
     switch (op) {
         case K_MU: sc->mu_v = a / sc->vol[0]; break;
-        case K_ALPHA: sc->alpha = (a != 0.0) ? sc->rho / a : 0.0; break;
-        case K_OMEGA: sc->omega = (b > 0.0) ? a / b : 0.0; break;
+        case K_ALPHA:
+        case K_OMEGA: break;  // formed by k_krylov_finalize_dots
         case K_RHO:
         case K_INIT:
         case K_RESTART: {
@@ -1397,6 +1439,27 @@ __global__ void k_krylov_finalize(const double *partials, int nb, int stride, Sc
             break;
         }
     }
+}
+
+// alpha = rho / rh.v or omega = t.s / t.t from the operator pass's sums (stride ns over nb
+// workgroups: o w, then w w) and the ghost rows' (stride 2 over ngb blocks)
+__global__ void k_krylov_finalize_dots(const double *part, int nb, int ns, const double *gpart, int ngb, Scalars *sc,
+                                       int op) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) {
+        a += part[ns * q];
+        if (ns > 1) b += part[ns * q + 1];
+    }
+    for (int q = threadIdx.x; q < ngb; q += 256) {
+        a += gpart[2 * q];
+        b += gpart[2 * q + 1];
+    }
+    a = block_sum<256>(a, sh, threadIdx.x);
+    b = block_sum<256>(b, sh, threadIdx.x);
+    if (threadIdx.x != 0) return;
+    if (op == K_ALPHA) sc->alpha = (a != 0.0) ? sc->rho / a : 0.0;
+    else sc->omega = (b > 0.0) ? a / b : 0.0;
 }
 
 // pd = r + beta (pd - omega v) on fluid + ghost cells
@@ -1527,19 +1590,25 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
     return hipGetLastError();
 }
 
-// w = P A y (fluid mean removed) fused with the inner products of `mode` (see k_project)
-static hipError_t apply_projected(ibm_grid *g, const double *y, double *w, const double *other, double *rh, int mode,
-                                  int op, hipStream_t s) {
+// w = P A y (the fluid part with its volume-weighted mean removed) and the inner products of
+// `mode` (0: rh.w for alpha; 1: t.s and t.t for omega), then alpha or omega.  The mean comes
+// first, from the fluid-ghost faces alone (k_ghost_flux), so the operator pass writes the
+// projected image and forms its inner products in the same sweep.
+static hipError_t apply_projected(ibm_grid *g, const double *y, double *w, const double *other, int mode, int op,
+                                  hipStream_t s) {
+    const int ngb = g->ng > 0 ? nblk(g->ng) : 0;
+    double *gpart = g->partials + 2 * zmarch_partials_max(g->nx, g->ny, g->nz);
+    if (g->ng > 0)
+        hipLaunchKernelGGL(k_ghost_flux, dim3(ngb), dim3(256), 0, s, ghost_view(g), fine64(g), y, g->partials);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, ngb, 1, g->sc, (int)K_MU);
     int nparts = 0;
-    hipError_t e = launch_apply_fluid(fine64(g), y, w, g->partials, &nparts, s);
+    hipError_t e = launch_apply_fluid(fine64(g), y, w, other, &g->sc->mu_v, mode + 1, g->partials, &nparts, s);
     if (e != hipSuccess) return e;
     if (g->ng > 0)
-        hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), y, w, g->g_scale, g->nx,
-                           g->ny, g->nz, g->type, 0);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, nparts, 1, g->sc, (int)K_MU);
-    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, w, other, rh, g->sc, mode,
-                       g->partials);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, op);
+        hipLaunchKernelGGL(k_apply_ghost, dim3(ngb), dim3(256), 0, s, ghost_view(g), y, w, g->g_scale, g->nx, g->ny,
+                           g->nz, g->type, 0, other, gpart);
+    hipLaunchKernelGGL(k_krylov_finalize_dots, dim3(1), dim3(256), 0, s, g->partials, nparts, mode + 1, gpart, ngb,
+                       g->sc, op);
     return hipGetLastError();
 }
 
@@ -1556,10 +1625,9 @@ hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStr
     hipLaunchKernelGGL(k_resid_fluid, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), f, x, r, g->partials);
     if (g->ng > 0)
         hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), x, r, g->g_scale, g->nx,
-                           g->ny, g->nz, g->type, 1);
+                           g->ny, g->nz, g->type, 1, (const double *)nullptr, (double *)nullptr);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 1, g->sc, (int)K_MU);
-    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, r, (const double *)nullptr, rh,
-                       g->sc, 2, g->partials);
+    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, r, rh, g->sc, 2, g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_INIT);
     return hipGetLastError();
 }
@@ -1573,10 +1641,10 @@ hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStrea
     hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc);
     double *y = nullptr, *z = nullptr;
     if ((e = precondition(g, pd, ya, yb, &y, o, s)) != hipSuccess) return e;
-    if ((e = apply_projected(g, y, v, rh, nullptr, 0, K_ALPHA, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, y, v, rh, 0, K_ALPHA, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_s_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, sv, g->sc);
     if ((e = precondition(g, sv, za, zb, &z, o, s)) != hipSuccess) return e;
-    if ((e = apply_projected(g, z, t, sv, nullptr, 1, K_OMEGA, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, z, t, sv, 1, K_OMEGA, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_xr_update, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, x, y, z, sv, t, r, rh, g->sc,
                        g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_RHO);
@@ -1585,8 +1653,8 @@ hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStrea
 
 // restart the shadow residual after a breakdown: rh = r, rho = r.r, beta = 0
 hipError_t krylov_restart(ibm_grid *g, hipStream_t s) {
-    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, g->kv[0],
-                       (const double *)nullptr, g->kv[1], g->sc, 3, g->partials);
+    hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, g->kv[0], g->kv[1], g->sc, 3,
+                       g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc,
                        (int)K_RESTART);
     return hipGetLastError();
