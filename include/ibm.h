@@ -237,6 +237,33 @@ ibm_status ibm_get_dirichlet_weights(const ibm_grid *g, void *stream, double *be
 ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, double *hu, double *hv, double *hw,
                              const ibm_momentum_opts *o, ibm_momentum_stats *s, void *stream);
 
+/* ---- moving bodies: fresh cells (Section 2.2) ---------------------------------------- */
+
+/* Move the body to new vertex positions (host; same conventions and checks as
+   ibm_set_geometry) after a previous geometry's stencils: re-classifies, rebuilds the ghost
+   stencils and the hierarchy, and lists the fresh cells, the cells that were ghost or dead
+   before and are fluid now (increasing linear index).  For each fresh cell c: BI = closest
+   point of the moved surface, image point IP = 2 x_c - BI (the centre is the midpoint of BI
+   and IP), the 8 (2D: 4) cells around IP with their trilinear weights (Eq. 2), the cell's
+   own weight kept apart.  counts_out[3] and n_fresh_out (host) receive the new type counts
+   and the fresh count.  IBM_E_NOMEM if there are more fresh cells than the bound ghost
+   capacity.  Synchronises `stream`. */
+ibm_status ibm_move_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                             void *stream, int64_t counts_out[3], int64_t *n_fresh_out);
+
+/* Set the fresh cells of three cell-centred fields (device, [nz][ny][nx], in place):
+   u_c = (u_BI + sum_{m != c} beta_m u_m) / (2 - beta_c), members read from the fields before
+   the pass; degenerate fresh cells (a dead member or no fluid member) take the mean of their
+   fluid, non-fresh 26-neighbours.  ubi: host, 3 values per fresh cell (the body velocity at
+   its intercept; NULL = 0).  Synchronises `stream`. */
+ibm_status ibm_fill_fresh(ibm_grid *g, double *u, double *v, double *w, const double *ubi, void *stream);
+
+/* Copy the fresh-cell data of the last move to host arrays (any may be NULL): cell[n],
+   bi_xyz/ip_xyz[3n], stencil[8n] (-1: unused or the cell itself), beta[8n], beta_c[n] (the
+   cell's own weight), flags[n] (bit0 degenerate, bit1 clamped image point, bit3 own box). */
+ibm_status ibm_get_fresh(const ibm_grid *g, void *stream, int32_t *cell, double *bi_xyz, double *ip_xyz,
+                         int32_t *stencil, double *beta, double *beta_c, int32_t *flags);
+
 /* ---- single-step hooks for kernel-level parity tests -------------------------------- */
 
 /* n red-black sweeps of level 0 on p (device, in/out) with right-hand side rhs and shift

@@ -169,6 +169,17 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     G->g_betaDg = P.take<double>(gm);
     G->g_ubi = P.take<double>(3 * gm);
     G->g_uscr = P.take<double>(3 * gm);
+    G->type_prev = P.take<uint8_t>(N);
+    G->f_cell = P.take<int32_t>(gm);
+    G->f_tri = P.take<int32_t>(gm);
+    G->f_st = P.take<int32_t>(8 * gm);
+    G->f_flags = P.take<int32_t>(gm);
+    G->f_bi = P.take<double>(3 * gm);
+    G->f_ip = P.take<double>(3 * gm);
+    G->f_beta = P.take<double>(8 * gm);
+    G->f_betac = P.take<double>(gm);
+    G->f_ubi = P.take<double>(3 * gm);
+    G->f_scr = P.take<double>(3 * gm);
     for (int q = 0; q < 10; ++q) G->kv[q] = P.take<double>(N);
     for (int l = 0; l < nlev; ++l) {
         LevelHost &L = lev[l];
@@ -1105,6 +1116,77 @@ ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, doubl
     }
     if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite residual in the advection-diffusion solve");
     return status;
+}
+
+// ---- moving bodies: fresh cells -----------------------------------------------------------
+
+ibm_status ibm_move_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                             void *stream, int64_t counts_out[3], int64_t *n_fresh_out) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_move_geometry: NULL handle");
+    if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_move_geometry before a first geometry's stencils");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(g->type_prev, g->type, (size_t)g->N, hipMemcpyDeviceToDevice, s), "save types");
+    g->nfresh = 0;
+    ibm_status st = ibm_set_geometry(g, verts, nv, tris, nt, stream);
+    if (st != IBM_OK) return st;
+    int64_t counts[3];
+    if ((st = ibm_classify(g, stream, counts)) != IBM_OK) return st;
+    int64_t ng = 0;
+    if ((st = ibm_build_ghost_stencils(g, stream, &ng)) != IBM_OK) return st;
+    int64_t nf = 0;
+    HIP_TRY(launch_fresh(g, s, &nf), "fresh cells");
+    if (nf > g->ghost_max)
+        return fail(g, IBM_E_NOMEM, "more fresh cells (" + std::to_string(nf) + ") than the ghost capacity " +
+                                        std::to_string(g->ghost_max) + ": move in smaller steps or bind more");
+    if (nf > 0) HIP_TRY(hipMemsetAsync(g->f_ubi, 0, sizeof(double) * 3 * nf, s), "memset");
+    HIP_TRY(hipStreamSynchronize(s), "move sync");
+    g->nfresh = nf;
+    if (counts_out)
+        for (int q = 0; q < 3; ++q) counts_out[q] = counts[q];
+    if (n_fresh_out) *n_fresh_out = nf;
+    return IBM_OK;
+}
+
+ibm_status ibm_get_fresh(const ibm_grid *gc, void *stream, int32_t *cell, double *bi_xyz, double *ip_xyz,
+                         int32_t *stencil, double *beta, double *beta_c, int32_t *flags) {
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_get_fresh: NULL handle");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    const int64_t n = g->nfresh;
+    if (n > 0) {
+        if (cell) HIP_TRY(hipMemcpyAsync(cell, g->f_cell, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s), "copy");
+        if (bi_xyz) HIP_TRY(hipMemcpyAsync(bi_xyz, g->f_bi, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s), "copy");
+        if (ip_xyz) HIP_TRY(hipMemcpyAsync(ip_xyz, g->f_ip, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s), "copy");
+        if (stencil) HIP_TRY(hipMemcpyAsync(stencil, g->f_st, sizeof(int32_t) * 8 * n, hipMemcpyDeviceToHost, s), "copy");
+        if (beta) HIP_TRY(hipMemcpyAsync(beta, g->f_beta, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s), "copy");
+        if (beta_c) HIP_TRY(hipMemcpyAsync(beta_c, g->f_betac, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy");
+        if (flags) HIP_TRY(hipMemcpyAsync(flags, g->f_flags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s), "copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "get_fresh sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_fill_fresh(ibm_grid *g, double *u, double *v, double *w, const double *ubi, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_fill_fresh: NULL handle");
+    if (!u || !v || !w) return fail(g, IBM_E_ARG, "NULL velocity array");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    const int64_t n = g->nfresh;
+    if (n > 0) {
+        if (ubi) {
+            for (int64_t q = 0; q < 3 * n; ++q)
+                if (!std::isfinite(ubi[q])) return fail(g, IBM_E_ARG, "non-finite intercept velocity");
+            HIP_TRY(hipMemcpyAsync(g->f_ubi, ubi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s), "upload");
+        } else {
+            HIP_TRY(hipMemsetAsync(g->f_ubi, 0, sizeof(double) * 3 * n, s), "memset");
+        }
+        double *uvw[3] = {u, v, w};
+        HIP_TRY(fresh_enqueue_fill(g, uvw, s), "fresh fill");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "fill sync");
+    return IBM_OK;
 }
 
 void ibm_destroy_grid(ibm_grid *g) {

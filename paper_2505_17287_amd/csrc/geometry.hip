@@ -385,28 +385,35 @@ __global__ void __launch_bounds__(MARK_NT) k_mark_ghosts(uint8_t *type, int nx, 
 // compaction of the ghost cells in increasing linear order
 constexpr int CMP_NT = 256, CMP_PER = 16, CMP_CH = CMP_NT * CMP_PER;
 
-__global__ void __launch_bounds__(CMP_NT) k_ghost_count(const uint8_t *__restrict__ type, int64_t N, int32_t *blkc) {
+// the listed cells: ghosts (prev == nullptr), or fresh cells (not fluid in prev, fluid now)
+__device__ __forceinline__ bool listed(const uint8_t *__restrict__ type, const uint8_t *__restrict__ prev, int64_t id) {
+    return prev ? (prev[id] != T_FLUID && type[id] == T_FLUID) : type[id] == T_GHOST;
+}
+
+__global__ void __launch_bounds__(CMP_NT) k_ghost_count(const uint8_t *__restrict__ type, int64_t N, int32_t *blkc,
+                                                        const uint8_t *__restrict__ prev) {
     __shared__ double sh[CMP_NT / 64];
     int tid = threadIdx.x;
     int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)tid * CMP_PER;
     int c = 0;
     for (int q = 0; q < CMP_PER; ++q) {
         int64_t id = base + q;
-        if (id < N && type[id] == T_GHOST) ++c;
+        if (id < N && listed(type, prev, id)) ++c;
     }
     double s = block_sum<CMP_NT>((double)c, sh, tid);
     if (tid == 0) blkc[blockIdx.x] = (int32_t)s;
 }
 
 __global__ void __launch_bounds__(CMP_NT) k_ghost_write(const uint8_t *__restrict__ type, int64_t N,
-                                                        const int32_t *blkoff, int32_t *gcell, int64_t gmax) {
+                                                        const int32_t *blkoff, int32_t *gcell, int64_t gmax,
+                                                        const uint8_t *__restrict__ prev) {
     __shared__ int sh[CMP_NT];
     int tid = threadIdx.x;
     int64_t base = (int64_t)blockIdx.x * CMP_CH + (int64_t)tid * CMP_PER;
     int c = 0;
     for (int q = 0; q < CMP_PER; ++q) {
         int64_t id = base + q;
-        if (id < N && type[id] == T_GHOST) ++c;
+        if (id < N && listed(type, prev, id)) ++c;
     }
     sh[tid] = c;
     __syncthreads();
@@ -419,7 +426,7 @@ __global__ void __launch_bounds__(CMP_NT) k_ghost_write(const uint8_t *__restric
     int64_t pos = (int64_t)blkoff[blockIdx.x] + sh[tid] - c;
     for (int q = 0; q < CMP_PER; ++q) {
         int64_t id = base + q;
-        if (id < N && type[id] == T_GHOST) {
+        if (id < N && listed(type, prev, id)) {
             if (pos < gmax) gcell[pos] = (int32_t)id;
             ++pos;
         }
@@ -455,11 +462,12 @@ hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
     int64_t nb = (N + CMP_CH - 1) / CMP_CH;
     int32_t *blkc = g->col_cnt;  // reuse: ncol+1 >= nb is guaranteed by the layout
     int32_t *blko = g->col_fill;
-    hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blkc);
+    hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blkc,
+                       (const uint8_t *)nullptr);
     e = scan_counts(blkc, blko, nb, (int64_t *)g->blk_cnt, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ghost_write, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blko, g->g_cell,
-                       g->ghost_max);
+                       g->ghost_max, (const uint8_t *)nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     int64_t hc[8];
@@ -836,6 +844,114 @@ hipError_t launch_ghost_h(ibm_grid *g, hipStream_t s) {
     if (g->ng == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ghost_h, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, g->ng, g->g_betag, g->g_dl,
                        g->g_data, g->g_h);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// fresh cells of a moved body (Section 2.2): not fluid before the move, fluid after it.  The
+// image point is the mirror of the intercept through the cell centre (IP = 2 x_c - BI), so
+// u_c = (u_BI + u_IP) / 2 with u_IP trilinear (Eq. 2) over the 8 (2D: 4) cells around IP;
+// the fresh cell's own weight, when it is one of them, is kept apart (beta_c) and moved to
+// the left side at fill time.  A box with a dead cell or without a fluid cell is degenerate.
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_fresh_weights(int64_t nf, const int32_t *__restrict__ fcell, int nx, int ny, int nz,
+                                const double *__restrict__ xc, const double *__restrict__ yc,
+                                const double *__restrict__ zc, const uint8_t *__restrict__ type,
+                                const double *__restrict__ fbi, double *fip, int32_t *fst, double *fbeta,
+                                double *fbetac, int32_t *fflags) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nf) return;
+    const int64_t id = fcell[q];
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
+    const bool two_d = (nz == 1);
+    const double x[3] = {xc[i], yc[j], zc[k]};
+    double ip[3];
+    for (int d = 0; d < 3; ++d) {
+        ip[d] = (x[d] + x[d]) - fbi[3 * q + d];
+        fip[3 * q + d] = ip[d];
+    }
+    const int i0 = box_lo(xc, nx, ip[0]), j0 = box_lo(yc, ny, ip[1]), k0 = two_d ? 0 : box_lo(zc, nz, ip[2]);
+    double sl[3];
+    sl[0] = (ip[0] - xc[i0]) / (xc[i0 + 1] - xc[i0]);
+    sl[1] = (ip[1] - yc[j0]) / (yc[j0 + 1] - yc[j0]);
+    sl[2] = two_d ? 0.0 : (ip[2] - zc[k0]) / (zc[k0 + 1] - zc[k0]);
+    int flags = 0;
+    for (int d = 0; d < 3; ++d) {
+        if (sl[d] < 0.0) {
+            sl[d] = 0.0;
+            flags |= GF_CLAMPED;
+        } else if (sl[d] > 1.0) {
+            sl[d] = 1.0;
+            flags |= GF_CLAMPED;
+        }
+    }
+    const int nm = two_d ? 4 : 8;
+    int nfl = 0, ndead = 0;
+    int32_t mem[8];
+    for (int m = 0; m < nm; ++m) {
+        const int a = m & 1, b = (m >> 1) & 1, c = (m >> 2) & 1;
+        const int64_t mid = ((int64_t)(k0 + c) * ny + (j0 + b)) * nx + (i0 + a);
+        mem[m] = (int32_t)mid;
+        const uint8_t ty = type[mid];
+        if (ty == T_FLUID) ++nfl;
+        if (ty == T_DEAD) ++ndead;
+    }
+    const bool degenerate = ndead > 0 || nfl == 0;
+    double bc = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        double w = 0.0;
+        int32_t st = -1;
+        if (!degenerate && m < nm) {
+            const int bits[3] = {m & 1, (m >> 1) & 1, (m >> 2) & 1};
+            w = (bits[0] ? sl[0] : 1.0 - sl[0]) * (bits[1] ? sl[1] : 1.0 - sl[1]);
+            if (!two_d) w *= bits[2] ? sl[2] : 1.0 - sl[2];
+            if (mem[m] == id) {
+                bc = w;
+                w = 0.0;
+            } else {
+                st = mem[m];
+            }
+        }
+        fst[8 * q + m] = st;
+        fbeta[8 * q + m] = w;
+    }
+    fbetac[q] = bc;
+    fflags[q] = flags | (degenerate ? GF_DEGENERATE : 0) | (bc != 0.0 ? GF_SELF : 0);
+}
+
+// the list of fresh cells (increasing linear order), their intercepts and weights;
+// *nfresh receives the count (the list holds at most ghost_max of them)
+hipError_t launch_fresh(ibm_grid *g, hipStream_t s, int64_t *nfresh) {
+    const int64_t N = g->N;
+    const int64_t nb = (N + CMP_CH - 1) / CMP_CH;
+    int32_t *blkc = g->col_cnt, *blko = g->col_fill;
+    hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blkc,
+                       (const uint8_t *)g->type_prev);
+    hipError_t e = scan_counts(blkc, blko, nb, (int64_t *)g->blk_cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ghost_write, dim3((unsigned)nb), dim3(CMP_NT), 0, s, g->type, N, blko, g->f_cell,
+                       g->ghost_max, (const uint8_t *)g->type_prev);
+    int32_t last[2];
+    if ((e = hipMemcpyAsync(&last[0], blko + nb - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&last[1], blkc + nb - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const int64_t nf = (int64_t)last[0] + last[1];
+    *nfresh = nf;
+    if (nf == 0 || nf > g->ghost_max) return hipSuccess;
+    BucketGrid G;
+    for (int d = 0; d < 3; ++d) {
+        G.bmin[d] = g->bmin[d];
+        G.bsize[d] = g->bsize[d];
+        G.nb[d] = g->nb[d];
+    }
+    hipLaunchKernelGGL(k_closest, dim3((unsigned)((nf + CLOSEST_WAVES - 1) / CLOSEST_WAVES)), dim3(64 * CLOSEST_WAVES),
+                       0, s, nf, g->f_cell, g->nx, g->ny, g->nz, g->c0[0], g->c0[1], g->c0[2], g->verts, g->tris, g->nt,
+                       g->bucket_off, g->bucket_ent, G, g->f_bi, g->f_tri);
+    hipLaunchKernelGGL(k_fresh_weights, dim3((unsigned)((nf + 127) / 128)), dim3(128), 0, s, nf, g->f_cell, g->nx,
+                       g->ny, g->nz, g->c0[0], g->c0[1], g->c0[2], g->type, g->f_bi, g->f_ip, g->f_st, g->f_beta,
+                       g->f_betac, g->f_flags);
     return hipGetLastError();
 }
 

@@ -222,6 +222,12 @@ struct ibm_grid {
     double *g_betaDg = nullptr;            // per ghost: weight of the intercept value
     double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
     double *g_uscr = nullptr;              // 3 per ghost: held-back ghost values of an in-place pass
+    // fresh cells of the last move (capacity ghost_max)
+    uint8_t *type_prev = nullptr;          // cell types before the move
+    int64_t nfresh = 0;
+    int32_t *f_cell = nullptr, *f_tri = nullptr, *f_st = nullptr, *f_flags = nullptr;
+    double *f_bi = nullptr, *f_ip = nullptr, *f_beta = nullptr, *f_betac = nullptr, *f_ubi = nullptr,
+           *f_scr = nullptr;
     double diag_max = -1.0;                // max over cells of the flux-coefficient sum (< 0: not read yet)
     std::vector<double> srj_omega;         // relaxation factors of the scheduled-Jacobi preconditioner
     // Krylov vectors (FP64, full grid)
@@ -266,6 +272,7 @@ hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]);
 hipError_t launch_stencils(ibm_grid *g, hipStream_t s);
 hipError_t launch_ghost_h(ibm_grid *g, hipStream_t s);
 hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s);
+hipError_t launch_fresh(ibm_grid *g, hipStream_t s, int64_t *nfresh);
 
 // solver launchers (solver.hip)
 hipError_t sweep0_f64(ibm_grid *g, const double *pin, double *pout, const double *f, const double *lambda,
@@ -294,5 +301,6 @@ hipError_t momentum_enqueue_prep(ibm_grid *g, double *const uvw[3], double *cons
                                  double dt, double a, int first, hipStream_t s);
 hipError_t momentum_enqueue_sweep(ibm_grid *g, double *const X[3], double *const Y[3], double *const work[6],
                                   double a, double omega, bool sum, hipStream_t s);
+hipError_t fresh_enqueue_fill(ibm_grid *g, double *const uvw[3], hipStream_t s);
 
 }  // namespace ibm

@@ -431,7 +431,66 @@ hipError_t refresh(ibm_grid *g, CV3 src, V3 dst, hipStream_t s, double *scr = nu
     return hipGetLastError();
 }
 
+// Fresh-cell values (one pass over the fresh list, members read from the field as it is):
+//   u_c = (u_BI + sum_{m != c} beta_m u_m) / (2 - beta_c);
+// a degenerate fresh cell takes the mean of its fluid, non-fresh 26-neighbours (u_BI if it
+// has none).  Results go to scr (three per fresh cell) and are scattered afterwards.
+__global__ void k_fresh_fill(int64_t nf, const int32_t *__restrict__ fcell, const int32_t *__restrict__ fst,
+                             const double *__restrict__ fbeta, const double *__restrict__ fbetac,
+                             const int32_t *__restrict__ fflags, const double *__restrict__ ubi, CV3 U,
+                             const uint8_t *__restrict__ type, const uint8_t *__restrict__ prev, int nx, int ny,
+                             int nz, double *scr) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nf) return;
+    double v[3];
+    if (fflags[q] & GF_DEGENERATE) {
+        int i, j, k;
+        unflatten(fcell[q], nx, ny, i, j, k);
+        double sm[3] = {0.0, 0.0, 0.0};
+        int n = 0;
+        for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di, jj = j + dj, kk = k + dk;
+                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                    const int64_t x = ((int64_t)kk * ny + jj) * nx + ii;
+                    if (type[x] == T_FLUID && prev[x] == T_FLUID) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sm[c] += U.c[c][x];
+                        ++n;
+                    }
+                }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = n ? sm[c] / n : ubi[3 * q + c];
+    } else {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int m = 0; m < 8; ++m) {
+            const int32_t x = fst[8 * q + m];
+            if (x < 0) continue;
+            const double b = fbeta[8 * q + m];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += b * U.c[c][x];
+        }
+        const double den = 2.0 - fbetac[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = (ubi[3 * q + c] + acc[c]) / den;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) scr[3 * q + c] = v[c];
+}
+
 }  // namespace
+
+hipError_t fresh_enqueue_fill(ibm_grid *g, double *const uvw[3], hipStream_t s) {
+    if (g->nfresh <= 0) return hipSuccess;
+    const int64_t nf = g->nfresh;
+    hipLaunchKernelGGL(k_fresh_fill, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, nf, g->f_cell, g->f_st,
+                       g->f_beta, g->f_betac, g->f_flags, g->f_ubi, cv3(uvw[0], uvw[1], uvw[2]), g->type, g->type_prev,
+                       g->nx, g->ny, g->nz, g->f_scr);
+    hipLaunchKernelGGL(k_ghost_scatter, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, nf, g->f_cell, g->f_scr,
+                       v3(uvw[0], uvw[1], uvw[2]));
+    return hipGetLastError();
+}
 
 // ---- host driver ------------------------------------------------------------------------
 // uvw: three device arrays (u, v, w) of N doubles, in: u^n (its ghost rows are applied in

@@ -112,6 +112,9 @@ def lib():
         L.ibm_set_dirichlet_data.argtypes = [vp, vp, vp]
         L.ibm_get_dirichlet_weights.argtypes = [vp, vp, vp, vp]
         L.ibm_momentum_step.argtypes = [vp] + [vp] * 6 + [C.POINTER(MomentumOpts), C.POINTER(MomentumStats), vp]
+        L.ibm_move_geometry.argtypes = [vp, dp, i64, vp, i64, vp, vp, vp]
+        L.ibm_fill_fresh.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ibm_get_fresh.argtypes = [vp, vp] + [vp] * 7
         L.ibm_destroy_grid.argtypes = [vp]
         L.ibm_last_error.restype = C.c_char_p
         L.ibm_last_error.argtypes = [vp]
@@ -119,7 +122,8 @@ def lib():
                      "ibm_build_ghost_stencils", "ibm_get_ghosts", "ibm_set_neumann_data", "ibm_get_cell_types",
                      "ibm_poisson_solve", "ibm_project", "ibm_solve_begin", "ibm_solve_step", "ibm_solve_poll",
                      "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply", "ibm_srj_schedule",
-                     "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step"):
+                     "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step",
+                     "ibm_move_geometry", "ibm_fill_fresh", "ibm_get_fresh"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -206,6 +210,7 @@ class Grid:
         self._h = h
         self.ws = None
         self.ng = 0
+        self.nfresh = 0
 
     # -- helpers -------------------------------------------------------------------------
     def _check(self, code, h=True):
@@ -413,6 +418,44 @@ class Grid:
             code = self._check(lib().ibm_momentum_step(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]), _tptr(H[0]),
                                                        _tptr(H[1]), _tptr(H[2]), C.byref(o), C.byref(st), self._s()))
         return code, st
+
+    # moving bodies
+    def move_geometry(self, verts, tris):
+        """New vertex positions (same or new triangles): re-classify, rebuild the stencils and
+        list the fresh cells.  Returns (counts, n_fresh)."""
+        self.verts = np.ascontiguousarray(verts, dtype=np.float64)
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32)
+        counts = np.zeros(3, dtype=np.int64)
+        nf = np.zeros(1, dtype=np.int64)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_move_geometry(self._h, _dp(self.verts), len(self.verts),
+                                                C.c_void_p(self.tris.ctypes.data), len(self.tris), self._s(),
+                                                C.c_void_p(counts.ctypes.data), C.c_void_p(nf.ctypes.data)))
+        self.nfresh = int(nf[0])
+        self.ng = int(counts[1])
+        return counts, self.nfresh
+
+    def fresh(self):
+        n = self.nfresh
+        d = dict(cell=np.empty(n, np.int32), bi=np.empty((n, 3)), ip=np.empty((n, 3)),
+                 stencil=np.empty((n, 8), np.int32), beta=np.empty((n, 8)), beta_c=np.empty(n),
+                 flags=np.empty(n, np.int32))
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_get_fresh(self._h, self._s(), *[C.c_void_p(d[k].ctypes.data) for k in
+                                                                   ("cell", "bi", "ip", "stencil", "beta", "beta_c",
+                                                                    "flags")]))
+        return d
+
+    def fill_fresh(self, U, ubi=None):
+        """U: (3, nz, ny, nx) float64 device tensor, fresh cells set in place."""
+        self._field(U, "U")
+        arr = None if ubi is None else np.ascontiguousarray(ubi, dtype=np.float64).reshape(-1)
+        if arr is not None and arr.size != 3 * self.nfresh:
+            raise ValueError("need 3 values per fresh cell")
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_fill_fresh(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]),
+                                             None if arr is None else C.c_void_p(arr.ctypes.data), self._s()))
+        return U
 
     # smoother timing
     def set_profiling(self, on=True):
