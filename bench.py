@@ -228,6 +228,45 @@ def paper_solver_form(wl, u0, v0, w0, args, max_steps=5000):
             "rel_residual": st.rel_residual, "jacobi_sweeps": 32 * st.cycles}
 
 
+def moving_form(wl, args, moves=5):
+    """Moving bodies on the same workload: every body translated by (0.3, -0.2, 0.1) of the
+    smallest cell width per move; a move re-classifies, rebuilds the ghost stencils and the
+    hierarchy, lists the fresh cells with their intercepts and weights (ibm_move_geometry),
+    and sets the fresh cells of the three velocity components (ibm_fill_fresh)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+
+    dev = torch.device("cuda:0")
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf)
+    g.setup(wl.verts, wl.tris)
+    U0, _ = wl.cell_fields()
+    U = torch.from_numpy(np.ascontiguousarray(U0)).to(dev)
+    del U0
+    h = float(np.min(np.diff(wl.xf)))
+    step = np.array([0.3 * h, -0.2 * h, 0.1 * h])
+    verts = wl.verts.copy()
+    verts = verts + step
+    g.move_geometry(verts, wl.tris)  # warm-up move
+    g.fill_fresh(U)
+    torch.cuda.synchronize()
+    ts, nfs = [], []
+    for _ in range(moves):
+        verts = verts + step
+        t0 = time.perf_counter()
+        counts, nf = g.move_geometry(verts, wl.tris)
+        g.fill_fresh(U)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        nfs.append(nf)
+    g.close()
+    t = float(np.median(ts))
+    return {"value": round(1.0 / t, 2), "unit": "moves/s", "ms_per_move": round(1000.0 * t, 3), "moves": moves,
+            "fresh_cells": int(np.median(nfs)), "ghosts": int(counts[1]), "dtype": "f64",
+            "includes": "classification, ghost stencils, multigrid hierarchy, fresh list + weights, fresh fill"}
+
+
 def serving_form(args):
     """Continuous batching of whole projections (grids 64^3..256^3, 1-4 bodies) against the
     same requests served one at a time in plain FP64: saturation throughput, then p50/p99
@@ -287,6 +326,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--momentum", action="store_true",
                     help="only the advection-diffusion half-step form (3 steps), one JSON line")
+    ap.add_argument("--moving", action="store_true",
+                    help="only the moving-body form (translated bodies, fresh cells), one JSON line")
     ap.add_argument("--paper-solver", action="store_true",
                     help="only the projection with the paper's pressure solver (BiCGStab + SRJ), one JSON line")
     ap.add_argument("--probe", action="store_true",
@@ -306,6 +347,11 @@ def main():
         wl = I.multibody(args.n)
         u0, v0, w0 = (torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in wl.velocity())
         print(json.dumps({"workload": wl.name, "paper_solver": paper_solver_form(wl, u0, v0, w0, args)}), flush=True)
+        return
+    if args.moving:
+        from paper_2505_17287_amd import inputs as I
+        wl = I.multibody(args.n)
+        print(json.dumps({"workload": wl.name, "moving": moving_form(wl, args)}), flush=True)
         return
     if args.momentum:
         from paper_2505_17287_amd import inputs as I
@@ -393,6 +439,7 @@ def main():
         out["forms"] = {"mixed": mixed_form(wl, u0, v0, w0, args),
                         "momentum": momentum_form(wl, args),
                         "paper_solver": paper_solver_form(wl, u0, v0, w0, args),
+                        "moving": moving_form(wl, args),
                         "serving": serving_form(args)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -326,8 +326,32 @@ ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64
     return IBM_OK;
 }
 
+// FNV-1a over the triangle indices and the vertex count: a moved body with unchanged
+// triangles needs no new topology check
+static uint64_t topology_hash(const int32_t *tris, int64_t nt, int64_t nv) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)nv);
+    mix((uint64_t)nt);
+    for (int64_t i = 0; i < 3 * nt; ++i) mix((uint64_t)(uint32_t)tris[i]);
+    return h;
+}
+
+static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                                    void *stream, bool known_topology);
+
 ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                             void *stream) {
+    return set_geometry_impl(g, verts, nv, tris, nt, stream, false);
+}
+
+static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                                    void *stream, bool known_topology) {
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_geometry: NULL handle");
     if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_set_geometry before ibm_bind_workspace");
     if (!verts || !tris || nv < 3 || nt < 1) return fail(g, IBM_E_ARG, "ibm_set_geometry: empty mesh");
@@ -336,18 +360,24 @@ ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const 
         if (!std::isfinite(verts[i])) return fail(g, IBM_E_ARG, "non-finite vertex coordinate");
     for (int64_t i = 0; i < 3 * nt; ++i)
         if (tris[i] < 0 || tris[i] >= nv) return fail(g, IBM_E_ARG, "triangle index out of range");
-    // closed and consistently oriented: every directed edge once and its reverse once
-    std::vector<int64_t> e(3 * nt);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int q = 0; q < 3; ++q) e[3 * t + q] = (int64_t)tris[3 * t + q] * nv + tris[3 * t + (q + 1) % 3];
-    std::sort(e.begin(), e.end());
-    for (size_t i = 0; i < e.size(); ++i) {
-        if (i + 1 < e.size() && e[i + 1] == e[i])
-            return fail(g, IBM_E_GEOMETRY, "mesh is not consistently oriented (directed edge used twice)");
-        int64_t a = e[i] / nv, b = e[i] % nv;
-        if (a == b) return fail(g, IBM_E_GEOMETRY, "degenerate edge");
-        if (!std::binary_search(e.begin(), e.end(), b * nv + a))
-            return fail(g, IBM_E_GEOMETRY, "mesh is not closed (edge without its reverse)");
+    const uint64_t th = topology_hash(tris, nt, nv);
+    if (!(known_topology && g->topo_valid && th == g->topo_hash)) {
+        g->topo_valid = false;
+        // closed and consistently oriented: every directed edge once and its reverse once
+        std::vector<int64_t> e(3 * nt);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int q = 0; q < 3; ++q) e[3 * t + q] = (int64_t)tris[3 * t + q] * nv + tris[3 * t + (q + 1) % 3];
+        std::sort(e.begin(), e.end());
+        for (size_t i = 0; i < e.size(); ++i) {
+            if (i + 1 < e.size() && e[i + 1] == e[i])
+                return fail(g, IBM_E_GEOMETRY, "mesh is not consistently oriented (directed edge used twice)");
+            int64_t a = e[i] / nv, b = e[i] % nv;
+            if (a == b) return fail(g, IBM_E_GEOMETRY, "degenerate edge");
+            if (!std::binary_search(e.begin(), e.end(), b * nv + a))
+                return fail(g, IBM_E_GEOMETRY, "mesh is not closed (edge without its reverse)");
+        }
+        g->topo_hash = th;
+        g->topo_valid = true;
     }
     // bucket grid over the mesh bounding box: buckets at least as large as the largest
     // triangle extent, so a triangle overlaps at most 2 buckets per axis
@@ -1128,7 +1158,7 @@ ibm_status ibm_move_geometry(ibm_grid *g, const double *verts, int64_t nv, const
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     HIP_TRY(hipMemcpyAsync(g->type_prev, g->type, (size_t)g->N, hipMemcpyDeviceToDevice, s), "save types");
     g->nfresh = 0;
-    ibm_status st = ibm_set_geometry(g, verts, nv, tris, nt, stream);
+    ibm_status st = set_geometry_impl(g, verts, nv, tris, nt, stream, true);
     if (st != IBM_OK) return st;
     int64_t counts[3];
     if ((st = ibm_classify(g, stream, counts)) != IBM_OK) return st;

@@ -222,6 +222,8 @@ struct ibm_grid {
     double *g_betaDg = nullptr;            // per ghost: weight of the intercept value
     double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
     double *g_uscr = nullptr;              // 3 per ghost: held-back ghost values of an in-place pass
+    uint64_t topo_hash = 0;                // triangle indices of the last validated mesh
+    bool topo_valid = false;
     // fresh cells of the last move (capacity ghost_max)
     uint8_t *type_prev = nullptr;          // cell types before the move
     int64_t nfresh = 0;

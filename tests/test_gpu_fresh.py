@@ -79,6 +79,11 @@ def test_fresh_cells_match_oracle(name):
         ubi = rng.uniform(-0.3, 0.3, size=(nf, 3))
         _compare(g, F, P1, U0, ubi)
         verts = new
+    # a changed triangle list is checked again: one flipped triangle is refused
+    bad = wl.tris.copy()
+    bad[0] = bad[0][::-1]
+    with pytest.raises(ibm.IBMError):
+        g.move_geometry(verts, bad)
     # a move by zero leaves no fresh cell and the fill changes nothing
     counts, nf = g.move_geometry(verts, wl.tris)
     assert nf == 0
