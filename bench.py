@@ -228,6 +228,65 @@ def paper_solver_form(wl, u0, v0, w0, args, max_steps=5000):
             "rel_residual": st.rel_residual, "jacobi_sweeps": 32 * st.cycles}
 
 
+def momentum_cpu_baseline(wl, m=8):
+    """The advection-diffusion oracle (numpy) on the same workload: ghost rows of u^n,
+    convective term and right-hand side timed in full, one scheduled-Jacobi sweep timed and
+    scaled to the m sweeps of the GPU step (the Dirichlet weights, a one-off per geometry,
+    are not timed)."""
+    import numpy as np
+    from oracle import OracleProblem
+    from oracle.momentum import MomentumOracle, srj_rho, srj_schedule
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    mo = MomentumOracle(OracleProblem.from_workload(wl))
+    U0, H0 = wl.cell_fields()
+    nu, dt = 1e-3, 0.5 * float(np.min(np.diff(wl.xf)))
+    a = 0.5 * nu * dt
+    t0 = time.perf_counter()
+    U = np.array(U0, copy=True)
+    U[:, mo.types == 2] = 0.0
+    U = mo.ghost_rows(U, None, src=U.copy())
+    H = mo.convective(U)
+    b = mo.cn_rhs(U, H, H0, nu, dt, False)
+    t1 = time.perf_counter()
+    w = srj_schedule(srj_rho(mo.m, a), m)[0]
+    mo.srj_sweep(U, b, a, w)
+    t2 = time.perf_counter()
+    t_step = (t1 - t0) + m * (t2 - t1)
+    return {"value": round(1.0 / t_step, 4), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": "ghost rows, convection and right-hand side (%.2fs) in full, one of the %d sweeps timed "
+                      "(%.2fs) and scaled" % (t1 - t0, m, t2 - t1)}
+
+
+def moving_cpu_baseline(wl):
+    """The oracle on one move of the same workload: classification of the moved bodies, the
+    fresh list with intercepts and weights, and the fill."""
+    import numpy as np
+    from oracle import OracleProblem
+    from oracle.fresh import FreshOracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    h = float(np.min(np.diff(wl.xf)))
+    P0 = OracleProblem(wl.xf, wl.yf, wl.zf)
+    P0.set_mesh(wl.verts, wl.tris)
+    P0.classify()
+    U0, _ = wl.cell_fields()
+    t0 = time.perf_counter()
+    P1 = OracleProblem(wl.xf, wl.yf, wl.zf)
+    P1.set_mesh(wl.verts + np.array([0.3 * h, -0.2 * h, 0.1 * h]), wl.tris)
+    P1.classify()
+    P1.build_stencils()
+    t1 = time.perf_counter()
+    n_sample = 200
+    F = FreshOracle(P0.types(), P1, limit=n_sample)
+    F.fill(U0)
+    t2 = time.perf_counter()
+    nf = F.n_all
+    t = (t1 - t0) + (t2 - t1) * nf / max(len(F.cells), 1)
+    return {"value": round(1.0 / t, 4), "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": "one move: classification and ghost stencils of the moved bodies (%.2fs) in full, "
+                      "%d of the %d fresh cells (intercept, weights, fill) timed (%.2fs) and scaled"
+                      % (t1 - t0, len(F.cells), nf, t2 - t1)}
+
+
 def moving_form(wl, args, moves=5):
     """Moving bodies on the same workload: every body translated by (0.3, -0.2, 0.1) of the
     smallest cell width per move; a move re-classifies, rebuilds the ghost stencils and the
@@ -444,6 +503,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, int(np.median(vcyc)))
+        if not args.no_forms:
+            log("cpu baselines of the forms (oracle) ...")
+            out["forms"]["momentum"]["cpu_baseline"] = momentum_cpu_baseline(wl)
+            out["forms"]["moving"]["cpu_baseline"] = moving_cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 
 

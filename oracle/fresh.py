@@ -34,7 +34,8 @@ T_FLUID, T_GHOST, T_DEAD = 0, 1, 2
 class FreshOracle:
     """Fresh cells of the move old_types -> P (an OracleProblem classified on the moved mesh)."""
 
-    def __init__(self, old_types: np.ndarray, P: OracleProblem):
+    def __init__(self, old_types: np.ndarray, P: OracleProblem, limit: int | None = None):
+        """limit: process only the first `limit` fresh cells (a bounded timing sample)."""
         self.P = P
         self.m = P.metrics()
         self.types = P.types()
@@ -42,6 +43,9 @@ class FreshOracle:
         self.two_d = self.nz == 1
         self.fresh_mask = (old_types != T_FLUID) & (self.types == T_FLUID)
         self.cells = np.flatnonzero(self.fresh_mask.ravel()).astype(np.int64)
+        self.n_all = len(self.cells)
+        if limit is not None:
+            self.cells = self.cells[:limit]
         n = len(self.cells)
         self.bi = np.zeros((n, 3))
         self.ip = np.zeros((n, 3))
