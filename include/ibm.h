@@ -223,7 +223,7 @@ ibm_status ibm_get_dirichlet_weights(const ibm_grid *g, void *stream, double *be
 /* One advection-diffusion half-step of the cell-centred velocity (Section 2.1: central
    differences, Adams-Bashforth convection, Crank-Nicolson viscous term solved by scheduled
    relaxed Jacobi; Section 2.2: ghost cells, here with the Dirichlet condition at BI):
-     1. dead cells of u^n are cleared and the ghost rows applied once;
+     1. the ghost rows are applied once to u^n, in place (dead cells are never read);
      2. H^n = -div(u u) in conservative form (face values by linear interpolation between
         centres; no flux through the box walls), b = u^n + dt (3/2 H^n - 1/2 H^{n-1})
         + (nu dt / 2) L u^n on fluid rows, L the pressure operator's flux Laplacian;

@@ -62,15 +62,14 @@ MomView mom_view(ibm_grid *g) {
 // before the pass).  Lane m of a group of eight takes member m; three shuffle steps sum the
 // group.  A degenerate ghost takes 2 u_BI minus the mean of its fluid 26-neighbours.
 __global__ void __launch_bounds__(DREF_NT)
-    k_dirichlet_refresh(GhostView G, const double *__restrict__ betaD, const double *__restrict__ betaDg,
-                        const double *__restrict__ ubi, CV3 src, V3 dst, int nx, int ny, int nz,
-                        const uint8_t *__restrict__ type, double *scr) {
+    k_dirichlet_refresh(GhostView G, const double *__restrict__ betaDg, const double *__restrict__ ubi, CV3 src,
+                        V3 dst, int nx, int ny, int nz, const uint8_t *__restrict__ type, double *scr) {
     const int64_t g = ((int64_t)blockIdx.x * DREF_NT + threadIdx.x) >> 3;
     const int m = threadIdx.x & 7;
     const bool live = g < G.ng;
     const int64_t gc = live ? g : 0;
     const int32_t q = G.st[8 * gc + m];
-    const double b = betaD[8 * gc + m];
+    const double b = G.beta[8 * gc + m];  // the Dirichlet weights (ghosts() below)
     const unsigned gm = G.gmask[gc];
     double t[3] = {0.0, 0.0, 0.0};
     if (live && q >= 0) {
@@ -408,6 +407,7 @@ V3 v3(double *a, double *b, double *c) {
     return v;
 }
 
+// the ghost list with the Dirichlet weights in place of the Neumann ones
 GhostView ghosts(ibm_grid *g) {
     GhostView G;
     G.ng = g->ng;
@@ -423,8 +423,7 @@ GhostView ghosts(ibm_grid *g) {
 hipError_t refresh(ibm_grid *g, CV3 src, V3 dst, hipStream_t s, double *scr = nullptr) {
     if (g->ng == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dirichlet_refresh, dim3((unsigned)((8 * g->ng + DREF_NT - 1) / DREF_NT)), dim3(DREF_NT), 0,
-                       s, ghosts(g), g->g_betaD, g->g_betaDg, g->g_ubi, src, dst, g->nx, g->ny, g->nz, g->type,
-                       scr);
+                       s, ghosts(g), g->g_betaDg, g->g_ubi, src, dst, g->nx, g->ny, g->nz, g->type, scr);
     if (scr)
         hipLaunchKernelGGL(k_ghost_scatter, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, g->ng, g->g_cell,
                            scr, dst);
