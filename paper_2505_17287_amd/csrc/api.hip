@@ -197,6 +197,13 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
             L.R64 = P.take<double>(NC);
             L.e32 = P.take<float>(NC);
             L.R32 = P.take<float>(NC);
+            if (sweepC_fused_ok(L.n)) {
+                L.e64b = P.take<double>(NC);
+                L.e32b = P.take<float>(NC);
+            } else {
+                L.e64b = nullptr;
+                L.e32b = nullptr;
+            }
         }
         if (l + 1 < nlev) {
             for (int d = 0; d < 3; ++d) {

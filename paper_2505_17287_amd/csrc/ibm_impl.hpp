@@ -61,6 +61,13 @@ struct Coarse {  // coarse-level view in precision T
 template <typename T>
 hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s);
 
+// fused red-black sweep of a coarse level (sweepc.hip): eout = one RB-GS sweep of L.e, the
+// two buffers distinct; for levels with an even row length and at least 2^19 cells
+// (sweepC_fused_ok)
+bool sweepC_fused_ok(const int n[3]);
+template <typename T>
+hipError_t launch_sweepC_fused(const Coarse<T> &L, T *eout, hipStream_t s);
+
 struct ProlongTab {  // fine index -> (lo, hi, weight of hi) per axis
     const int *lo[3], *hi[3];
     const double *t[3];
@@ -136,6 +143,10 @@ struct LevelHost {
     double *c64[3] = {nullptr, nullptr, nullptr};
     double *e64 = nullptr, *R64 = nullptr;
     float *e32 = nullptr, *R32 = nullptr;
+    // second error buffer of the out-of-place coarse sweep (levels that sweepC_fused_ok
+    // accepts); swapped with e after each sweep
+    double *e64b = nullptr;
+    float *e32b = nullptr;
     // prolongation tables of THIS level from the next coarser one
     int *plo[3] = {nullptr, nullptr, nullptr}, *phi[3] = {nullptr, nullptr, nullptr};
     double *pt[3] = {nullptr, nullptr, nullptr};

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <utility>
 
 #include "device_util.hpp"
 #include "ibm_impl.hpp"
@@ -174,6 +175,19 @@ static ProlongTab prolong_tab(ibm_grid *g, int l) {  // table of level l from le
     }
     return P;
 }
+
+template <typename T>
+static T *&level_e(LevelHost &L);
+template <>
+double *&level_e<double>(LevelHost &L) { return L.e64; }
+template <>
+float *&level_e<float>(LevelHost &L) { return L.e32; }
+template <typename T>
+static T *&level_e2(LevelHost &L);
+template <>
+double *&level_e2<double>(LevelHost &L) { return L.e64b; }
+template <>
+float *&level_e2<float>(LevelHost &L) { return L.e32b; }
 
 template <typename T>
 __device__ __forceinline__ void fine_stencil(const Fine<T> &F, const T *__restrict__ p, int i, int j, int k, int64_t id,
@@ -957,6 +971,30 @@ static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *po
     return hipSuccess;
 }
 
+// nsweeps red-black sweeps of coarse level l (more cells than the tail takes): the fused
+// out-of-place pass when the level has a second error buffer (the buffers are swapped after
+// each sweep, so every later view of the level sees the current one), else two one-colour
+// passes in place
+template <typename T>
+static hipError_t smooth_level(ibm_grid *g, int l, int nsweeps, hipStream_t s) {
+    LevelHost &H = g->lev[l];
+    if (level_e2<T>(H) != nullptr) {
+        for (int q = 0; q < nsweeps; ++q) {
+            const hipError_t e = launch_sweepC_fused<T>(coarse_view<T>(g, l), level_e2<T>(H), s);
+            if (e != hipSuccess) return e;
+            std::swap(level_e<T>(H), level_e2<T>(H));
+        }
+        return hipSuccess;
+    }
+    const Coarse<T> L = coarse_view<T>(g, l);
+    const int nbh = nblk((int64_t)((H.n[0] + 1) / 2) * H.n[1] * H.n[2]);
+    for (int q = 0; q < nsweeps; ++q) {
+        hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 0);
+        hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 1);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, const double *gh,
                               const ibm_solve_opts *o, hipStream_t s) {
@@ -991,16 +1029,12 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
                                    &g->sc->mu[1]);
         }
         for (int l = 1; l < Lb; ++l) {
-            Coarse<T> L = coarse_view<T>(g, l);
-            const int nbh = nblk((int64_t)((g->lev[l].n[0] + 1) / 2) * g->lev[l].n[1] * g->lev[l].n[2]);
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
-                if (o->nu1 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu1, &g->sc->vol[l], 0, s);
-            } else {
-                for (int q = 0; q < o->nu1; ++q) {
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 0);
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 1);
-                }
+                if (o->nu1 > 0) launch_smallC<T>(coarse_view<T>(g, l), g->lev[l].ncell(), o->nu1, &g->sc->vol[l], 0, s);
+            } else if ((e = smooth_level<T>(g, l, o->nu1, s)) != hipSuccess) {
+                return e;
             }
+            Coarse<T> L = coarse_view<T>(g, l);  // after the sweeps: the current error buffer
             Coarse<T> C = coarse_view<T>(g, l + 1);
             Halv H;
             for (int d = 0; d < 3; ++d) H.h[d] = g->lev[l + 1].halved[d];
@@ -1039,15 +1073,11 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
         for (int l = Lb - 1; l >= 1; --l) {
             Coarse<T> L = coarse_view<T>(g, l);
             int nb = nblk(g->lev[l].ncell());
-            const int nbh = nblk((int64_t)((g->lev[l].n[0] + 1) / 2) * g->lev[l].n[1] * g->lev[l].n[2]);
             hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), prolong_tab(g, l));
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
                 if (o->nu2 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu2, &g->sc->vol[l], 0, s);
-            } else {
-                for (int q = 0; q < o->nu2; ++q) {
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 0);
-                    hipLaunchKernelGGL(k_sweepC<T>, dim3(nbh), dim3(256), 0, s, L, 1);
-                }
+            } else if ((e = smooth_level<T>(g, l, o->nu2, s)) != hipSuccess) {
+                return e;
             }
         }
         {
