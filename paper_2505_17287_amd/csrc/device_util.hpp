@@ -62,6 +62,18 @@ __device__ __forceinline__ double block_max(double v, double *sh, int tid) {
     return r;
 }
 
+// two adjacent elements moved as one access (8- or 16-byte aligned pairs)
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+    using type = double2;
+};
+template <>
+struct Pair2<float> {
+    using type = float2;
+};
+
 // (i, j, k) of the flat index id = (k ny + j) nx + i.  Grids hold fewer than 2^31 cells,
 // so 32-bit unsigned arithmetic is exact (and far cheaper than 64-bit division).
 __device__ __forceinline__ void unflatten(int64_t id, int nx, int ny, int &i, int &j, int &k) {

@@ -277,6 +277,105 @@ __global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partial
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// The same for a level pair with every axis halved: a thread per coarse cell loads its
+// 2 x 2 x 2 children as x pairs (one vector access per row and array), the neighbour layers
+// around the block and the high-face transmissibilities once, all before any arithmetic,
+// instead of rebuilding each child's stencil from scalar loads.  Per child the operations
+// are those of coarse_stencil, and the children are summed in the same order (x fastest,
+// then y, then z), so the result is bitwise that of k_resrestrictC.
+template <typename T>
+__global__ void __launch_bounds__(256) k_resrestrictC8(Coarse<T> L, Coarse<T> C, double *partials) {
+    using V = typename Pair2<T>::type;
+    __shared__ double sh[4];
+    const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double Rsum = 0.0;
+    if (cid < NC) {
+        int I, J, K;
+        unflatten(cid, C.n[0], C.n[1], I, J, K);
+        const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2];
+        const int64_t sy = n0, sz = (int64_t)n0 * n1;
+        const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+        const int im = max(i0 - 1, 0), ip = min(i0 + 2, n0 - 1);
+        const int jm = max(j0 - 1, 0), jp = min(j0 + 2, n1 - 1);
+        const int km = max(k0 - 1, 0), kp = min(k0 + 2, n2 - 1);
+        auto at = [&](int j, int k) -> int64_t { return (int64_t)k * sz + (int64_t)j * sy; };
+        V E[2][2], RR[2][2], X[2][2], Y[2][2], Z[2][2];
+        T Exm[2][2], Exp[2][2], Xh[2][2];
+        uint16_t A[2][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int64_t r = at(j0 + b, k0 + c);
+                E[b][c] = *reinterpret_cast<const V *>(L.e + r + i0);
+                RR[b][c] = *reinterpret_cast<const V *>(L.R + r + i0);
+                X[b][c] = *reinterpret_cast<const V *>(L.Tl[0] + r + i0);
+                Y[b][c] = *reinterpret_cast<const V *>(L.Tl[1] + r + i0);
+                Z[b][c] = *reinterpret_cast<const V *>(L.Tl[2] + r + i0);
+                A[b][c] = *reinterpret_cast<const uint16_t *>(L.active + r + i0);
+                Exm[b][c] = L.e[r + im];
+                Exp[b][c] = L.e[r + ip];
+                Xh[b][c] = L.Tl[0][r + ip];
+            }
+        V EYm[2], EYp[2], YH[2], EZm[2], EZp[2], ZH[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            EYm[q] = *reinterpret_cast<const V *>(L.e + at(jm, k0 + q) + i0);
+            EYp[q] = *reinterpret_cast<const V *>(L.e + at(jp, k0 + q) + i0);
+            YH[q] = *reinterpret_cast<const V *>(L.Tl[1] + at(jp, k0 + q) + i0);
+            EZm[q] = *reinterpret_cast<const V *>(L.e + at(j0 + q, km) + i0);
+            EZp[q] = *reinterpret_cast<const V *>(L.e + at(j0 + q, kp) + i0);
+            ZH[q] = *reinterpret_cast<const V *>(L.Tl[2] + at(j0 + q, kp) + i0);
+        }
+        const T mu = (T)(*L.mu);
+        T R = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int i = i0 + a, j = j0 + b, k = k0 + c;
+                    const T ev = a ? E[b][c].y : E[b][c].x;
+                    const T txm = a ? X[b][c].y : X[b][c].x;
+                    const T txp = a ? ((i < n0 - 1) ? Xh[b][c] : T(0)) : X[b][c].y;
+                    const T tym = a ? Y[b][c].y : Y[b][c].x;
+                    const T typ = b ? ((j < n1 - 1) ? (a ? YH[c].y : YH[c].x) : T(0)) : (a ? Y[1][c].y : Y[1][c].x);
+                    const T tzm = a ? Z[b][c].y : Z[b][c].x;
+                    const T tzp = c ? ((k < n2 - 1) ? (a ? ZH[b].y : ZH[b].x) : T(0)) : (a ? Z[b][1].y : Z[b][1].x);
+                    const T exm = a ? E[b][c].x : Exm[b][c];
+                    const T exp = a ? Exp[b][c] : E[b][c].y;
+                    const T eym = b ? (a ? E[0][c].y : E[0][c].x) : (a ? EYm[c].y : EYm[c].x);
+                    const T eyp = b ? (a ? EYp[c].y : EYp[c].x) : (a ? E[1][c].y : E[1][c].x);
+                    const T ezm = c ? (a ? E[b][0].y : E[b][0].x) : (a ? EZm[b].y : EZm[b].x);
+                    const T ezp = c ? (a ? EZp[b].y : EZp[b].x) : (a ? E[b][1].y : E[b][1].x);
+                    T sm = 0;
+                    sm = sm + (i > 0 ? txm * exm : T(0));
+                    sm = sm + (i < n0 - 1 ? txp * exp : T(0));
+                    sm = sm + (j > 0 ? tym * eym : T(0));
+                    sm = sm + (j < n1 - 1 ? typ * eyp : T(0));
+                    sm = sm + (k > 0 ? tzm * ezm : T(0));
+                    sm = sm + (k < n2 - 1 ? tzp * ezp : T(0));
+                    T d = txm + txp;
+                    d = d + tym;
+                    d = d + typ;
+                    d = d + tzm;
+                    d = d + tzp;
+                    const T vol = (L.w[0][i] * L.w[1][j]) * L.w[2][k];
+                    const T rv = a ? RR[b][c].y : RR[b][c].x;
+                    const T rc = (rv - vol * mu) - (sm - d * ev);
+                    const bool act = ((A[b][c] >> (8 * a)) & 0xff) != 0;
+                    if (act) R += rc;
+                }
+        C.R[cid] = R;
+        C.e[cid] = T(0);
+        Rsum = (double)R;
+    }
+    double s = block_sum<256>(Rsum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // mu = sum(partials) / vol  (fixed order)
 __global__ void k_finalize_mu(const double *partials, int n, const double *vol, double *mu) {
     __shared__ double sh[4];
@@ -504,30 +603,37 @@ __device__ void tail_smooth(const Coarse<T> &L, T *es, const uint8_t *act, int n
     }
     if (up) __syncthreads();
     // a level that the first wave holds alone (cells of a thread are tid + TAIL_NT c, so with
-    // NC <= 64 only lanes of wave 0 own cells) is swept by that wave with wave-level
-    // ordering of its LDS traffic, without workgroup barriers
+    // NC <= 64 only lanes of wave 0 own cells) is swept by that wave in registers, one cell
+    // per lane: the neighbours' values arrive by lane permutation (their lanes are the cell
+    // offsets -1, +1, -sy, +sy, -sz, +sz, clamped into the wave; a missing neighbour is masked
+    // by its flag), so a colour costs one permute round trip and no LDS store or barrier
     const bool one_wave = NC <= 64;
     if (one_wave) {
         if (threadIdx.x < 64) {
+            const int id = (int)threadIdx.x;
+            const unsigned f = fl[0];
+            const bool upd = (f & 2u) && inv[0] > T(0);
+            const unsigned mycol = (f >> 2) & 1u;
+            const int lxm = max(id - 1, 0), lxp = min(id + 1, 63), lym = max(id - sy, 0), lyp = min(id + sy, 63),
+                      lzm = max(id - sz, 0), lzp = min(id + sz, 63);
+            T x = (f & 1u) ? es[id] : T(0);
             for (int sw = 0; sw < ns; ++sw) {
                 for (unsigned col = 0; col < 2; ++col) {
-                    const int id = (int)threadIdx.x;
-                    const unsigned f = fl[0];
-                    if ((f & 2u) && ((f >> 2) & 1u) == col && inv[0] > T(0)) {
+                    const T xm = __shfl(x, lxm, 64), xp = __shfl(x, lxp, 64), ym = __shfl(x, lym, 64),
+                            yp = __shfl(x, lyp, 64), zm = __shfl(x, lzm, 64), zp = __shfl(x, lzp, 64);
+                    if (upd && mycol == col) {
                         T num = 0;
-                        num = num + ((f & 8u) ? txm[0] * es[id - 1] : T(0));
-                        num = num + ((f & 16u) ? txp[0] * es[id + 1] : T(0));
-                        num = num + ((f & 32u) ? tym[0] * es[id - sy] : T(0));
-                        num = num + ((f & 64u) ? typ[0] * es[id + sy] : T(0));
-                        num = num + ((f & 128u) ? tzm[0] * es[id - sz] : T(0));
-                        num = num + ((f & 256u) ? tzp[0] * es[id + sz] : T(0));
-                        es[id] = (num - rhs[0]) * inv[0];
+                        num = num + ((f & 8u) ? txm[0] * xm : T(0));
+                        num = num + ((f & 16u) ? txp[0] * xp : T(0));
+                        num = num + ((f & 32u) ? tym[0] * ym : T(0));
+                        num = num + ((f & 64u) ? typ[0] * yp : T(0));
+                        num = num + ((f & 128u) ? tzm[0] * zm : T(0));
+                        num = num + ((f & 256u) ? tzp[0] * zp : T(0));
+                        x = (num - rhs[0]) * inv[0];
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
+            if (f & 1u) es[id] = x;
         }
         __syncthreads();
     } else {
@@ -1039,7 +1145,10 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             Halv H;
             for (int d = 0; d < 3; ++d) H.h[d] = g->lev[l + 1].halved[d];
             int nbc = nblk(g->lev[l + 1].ncell());
-            hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, H, g->partials);
+            if (H.h[0] && H.h[1] && H.h[2])
+                hipLaunchKernelGGL(k_resrestrictC8<T>, dim3(nbc), dim3(256), 0, s, L, C, g->partials);
+            else
+                hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, H, g->partials);
             nparts = nbc;
             if (!(tail && l + 1 == lt))
                 hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],

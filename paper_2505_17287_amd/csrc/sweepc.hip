@@ -30,22 +30,11 @@ namespace ibm {
 // (48 B in FP64, 24 B in FP32).
 // =======================================================================================
 
-template <typename T>
-struct CVec2;
-template <>
-struct CVec2<double> {
-    using type = double2;
-};
-template <>
-struct CVec2<float> {
-    using type = float2;
-};
-
 // one plane of a thread's two columns: old values, right-hand side, low-face
 // transmissibilities in x, y and z
 template <typename T>
 struct CPlane {
-    using V = typename CVec2<T>::type;
+    using V = typename Pair2<T>::type;
     V e, r, x, y, z;
 };
 
@@ -90,7 +79,7 @@ __global__ void __launch_bounds__(32 * BY)
     k_rbgsC_fused(Coarse<T> L, T *__restrict__ eout, int ntx, int nty, int kc, int ntiles) {
     static_assert(BY % 4 == 0, "two same-parity rows of 32 threads per wave");
     static_assert(QD == 4 || QD == 6, "planes held per thread");
-    using V = typename CVec2<T>::type;
+    using V = typename Pair2<T>::type;
     using PD = CPlane<T>;
     constexpr int NC = SWC_NC, TXC = NC - 4, TY = BY - 4;
     __shared__ T so[2][BY][NC + 1];  // old values of the plane whose red values are formed
