@@ -119,12 +119,15 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
     G->inject0 = P.take<uint8_t>(N);
     G->p2 = P.take<double>(N);
     G->frhs = P.take<double>(N);
+    G->pz = P.take<double>(N);
     if (prec == IBM_MIXED) {
         G->e32a = P.take<float>(N);
         G->e32b = P.take<float>(N);
         G->r32 = P.take<float>(N);
+        G->pz32 = P.take<float>(N);
     } else {
         G->e32a = G->e32b = G->r32 = nullptr;
+        G->pz32 = nullptr;
     }
     for (int d = 0; d < 3; ++d) {
         G->faces[d] = P.take<double>(n[d] + 1);
@@ -479,6 +482,8 @@ ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_
     HIP_TRY(launch_stencils(g, s), "ghost stencils");
     if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_data, 0, sizeof(double) * g->ng, s), "memset neumann");
     if (g->ng > 0) HIP_TRY(hipMemsetAsync(g->g_ubi, 0, sizeof(double) * 3 * g->ng, s), "memset dirichlet");
+    HIP_TRY(hipMemsetAsync(g->pz, 0, sizeof(double) * g->N, s), "memset start iterate");
+    if (g->pz32) HIP_TRY(hipMemsetAsync(g->pz32, 0, sizeof(float) * g->N, s), "memset start iterate");
     HIP_TRY(launch_ghost_h(g, s), "ghost rhs");
     HIP_TRY(launch_hierarchy(g, s), "hierarchy");
     HIP_TRY(krylov_setup(g, s), "krylov setup");

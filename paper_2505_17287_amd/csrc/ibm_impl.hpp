@@ -202,6 +202,10 @@ struct ibm_grid {
     double *p2 = nullptr;                  // second FP64 pressure buffer
     double *frhs = nullptr;                // projection right-hand side
     float *e32a = nullptr, *e32b = nullptr, *r32 = nullptr;
+    // start iterate of the Krylov preconditioner's V-cycle: zero except at the ghost cells,
+    // whose values are written before each use (cleared whenever the ghost list is rebuilt)
+    double *pz = nullptr;
+    float *pz32 = nullptr;
     double *faces[3] = {nullptr, nullptr, nullptr};
     double *c0[3] = {nullptr, nullptr, nullptr}, *w0[3] = {nullptr, nullptr, nullptr};
     double *dc0[3] = {nullptr, nullptr, nullptr};

@@ -1103,11 +1103,13 @@ static hipError_t smooth_level(ibm_grid *g, int l, int nsweeps, hipStream_t s) {
 
 template <typename T>
 static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, const double *gh,
-                              const ibm_solve_opts *o, hipStream_t s) {
+                              const ibm_solve_opts *o, hipStream_t s, const T *start = nullptr) {
+    // start (requires nu1 > 0): the iterate the first pre-smoothing sweep reads instead of
+    // bufs[*cur]; it is only read, and the sweeps continue in bufs
     const Fine<T> F = FineOf<T>::get(g);
     hipError_t e;
     for (int q = 0; q < o->nu1; ++q) {
-        T *pin = bufs[*cur], *pout = bufs[1 - *cur];
+        T *pin = (q == 0 && start) ? const_cast<T *>(start) : bufs[*cur], *pout = bufs[1 - *cur];
         if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
         if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
         *cur = 1 - *cur;
@@ -1646,9 +1648,10 @@ __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict
     if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = q;
 }
 
-// preconditioner start: e = 0, ghost right-hand sides gh = r_g / s_g and e_g = gh (the first
-// ghost refresh of a zero field).  The second buffer only needs clearing when no
-// pre-smoothing sweep (which writes every cell of it) comes first.
+// preconditioner start: ghost right-hand sides gh = r_g / s_g and e_g = gh (the first ghost
+// refresh of a zero field), every other cell 0.  k_precond_zero clears both buffers when no
+// pre-smoothing sweep comes first; otherwise the start iterate (zero except at the ghost
+// cells) is only read by the first sweep, which writes every cell of its output.
 template <typename T>
 __global__ void k_precond_zero(int64_t N, T *ea, T *eb) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1688,42 +1691,59 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
                                const ibm_solve_opts *o, hipStream_t s) {
     hipError_t e;
     const unsigned nbN = (unsigned)nblk(g->N), nbG = (unsigned)nblk(g->ng > 0 ? g->ng : 1);
+    // With pre-smoothing the cycle starts from the start iterate (zero except at the ghost
+    // cells, written here), which the first sweep only reads: no field is cleared per call.
     if (o->precision == IBM_MIXED) {
-        hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a,
-                           o->nu1 > 0 ? (float *)nullptr : g->e32b);
+        const bool st = o->nu1 > 0;
+        float *e0 = st ? g->pz32 : g->e32a;
+        if (!st) hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a, g->e32b);
         hipLaunchKernelGGL(k_narrow, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, g->r32);
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<float>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
-                               g->g_scale, r, g->g_rhs, g->e32a);
+                               g->g_scale, r, g->g_rhs, e0);
         float *eb[2] = {g->e32a, g->e32b};
         int ecur = 0;
-        if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s)) != hipSuccess) return e;
+        if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s, st ? e0 : nullptr)) !=
+            hipSuccess)
+            return e;
         hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
         *out = ya;
     } else if (o->method == IBM_BICGSTAB_SRJ) {
-        // scheduled relaxed Jacobi: every sweep writes all cells of the other buffer
-        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, (double *)nullptr);
+        // scheduled relaxed Jacobi: every sweep writes all cells of the other buffer; the first
+        // one reads the start iterate
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
-                               g->g_scale, r, g->g_rhs, ya);
+                               g->g_scale, r, g->g_rhs, g->pz);
         double *bufs[2] = {ya, yb};
         int cur = 0;
+        bool first = true;
         const Fine<double> F = fine64(g);
         for (double w : g->srj_omega) {
-            if ((e = launch_jacobi0(F, bufs[cur], r, bufs[1 - cur], w, s)) != hipSuccess) return e;
-            if ((e = launch_refresh<double>(g, bufs[cur], bufs[1 - cur], g->g_rhs, s)) != hipSuccess) return e;
+            const double *pin = first ? g->pz : bufs[cur];
+            if ((e = launch_jacobi0(F, pin, r, bufs[1 - cur], w, s)) != hipSuccess) return e;
+            if ((e = launch_refresh<double>(g, pin, bufs[1 - cur], g->g_rhs, s)) != hipSuccess) return e;
             cur = 1 - cur;
+            first = false;
+        }
+        if (first) {  // no sweep: the start iterate itself
+            hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, (double *)nullptr);
+            if (g->ng > 0)
+                hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell,
+                                   g->g_flags, g->g_scale, r, g->g_rhs, ya);
         }
         *out = bufs[cur];
     } else {
-        hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya,
-                           o->nu1 > 0 ? (double *)nullptr : yb);
+        const bool st = o->nu1 > 0;
+        double *e0 = st ? g->pz : ya;
+        if (!st) hipLaunchKernelGGL(k_precond_zero<double>, dim3(nbN), dim3(256), 0, s, g->N, ya, yb);
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<double>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
-                               g->g_scale, r, g->g_rhs, ya);
+                               g->g_scale, r, g->g_rhs, e0);
         double *bufs[2] = {ya, yb};
         int cur = 0;
-        if ((e = vcycle_impl<double>(g, bufs, &cur, r, &g->sc->zero, g->g_rhs, o, s)) != hipSuccess) return e;
+        if ((e = vcycle_impl<double>(g, bufs, &cur, r, &g->sc->zero, g->g_rhs, o, s, st ? e0 : nullptr)) !=
+            hipSuccess)
+            return e;
         *out = bufs[cur];
     }
     return hipGetLastError();
