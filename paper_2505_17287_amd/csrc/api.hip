@@ -104,6 +104,17 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
                 C.w[d][i] = C.f[d][i + 1] - C.f[d][i];
             }
         }
+        // side rule of the prolongation table (k_prolong_tab): fine i takes I = i/2 and the
+        // coarse neighbour on the side of its centre
+        bool sides = true;
+        for (int d = 0; d < 3; ++d) {
+            if (!h[d]) continue;
+            for (int i = 0; i < F.n[d]; ++i) {
+                const int I = i / 2, jn = (F.c[d][i] < C.c[d][I]) ? I - 1 : I + 1;
+                if (jn >= 0 && jn < C.n[d] && jn != ((i & 1) ? I + 1 : I - 1)) sides = false;
+            }
+        }
+        F.prolong_sides = sides;
         ++n;
     }
     *nlev = n;

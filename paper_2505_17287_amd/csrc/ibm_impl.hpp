@@ -149,6 +149,10 @@ struct LevelHost {
     float *e32b = nullptr;
     // prolongation tables of THIS level from the next coarser one
     int *plo[3] = {nullptr, nullptr, nullptr}, *phi[3] = {nullptr, nullptr, nullptr};
+    // every halved axis: the second contributor of cell 2I is I-1 and of 2I+1 is I+1 (or none
+    // at a wall), which the fully halved prolongation kernel relies on (checked on the host
+    // with the arithmetic the device tables use)
+    bool prolong_sides = false;
     double *pt[3] = {nullptr, nullptr, nullptr};
     double vol_active = 0.0;  // device-computed, copied back at hierarchy build
 };

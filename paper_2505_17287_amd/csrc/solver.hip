@@ -884,6 +884,94 @@ __global__ void k_prolongC(Coarse<T> L, Coarse<T> C, ProlongTab P) {
     L.e[id] = (T)((double)L.e[id] + prolong_value(C, P, i, j, k));
 }
 
+// The same for a level pair with every axis halved: a thread per coarse cell updates its
+// 2 x 2 x 2 children, loaded and stored as x pairs.  On a halved axis the first contributor
+// of a child is its parent and the second (if any) the parent's neighbour on the child's
+// side (the table's hi), so the 3 x 3 x 3 coarse neighbourhood, loaded once, holds every
+// contributor.  Per child the terms, their order and the fallback to the parent are those
+// of prolong_value, so the result is bitwise that of k_prolongC.
+// Smaller levels keep k_prolongC: there the longer load chain of a thread outweighs the
+// coalescing (64^3 from 32^3: 6.8 us against 6.4; 128^3 from 64^3: 13 us against 22).
+constexpr int64_t PROLONG8_MIN_CELLS = 1 << 19;
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolongC8(Coarse<T> L, Coarse<T> C, ProlongTab P) {
+    using V = typename Pair2<T>::type;
+    const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
+    const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cid >= NC) return;
+    int I, J, K;
+    unflatten(cid, C.n[0], C.n[1], I, J, K);
+    const int m0 = C.n[0], m1 = C.n[1], m2 = C.n[2];
+    const int64_t csy = m0, csz = (int64_t)m0 * m1;
+    // coarse neighbourhood, indices clamped (a clamped entry is never a contributor)
+    double ce[3][3][3];
+    uint32_t ca = 0;  // bit (dz*9 + dy*3 + dx): active
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int x = min(max(I + dx - 1, 0), m0 - 1), y = min(max(J + dy - 1, 0), m1 - 1),
+                          z = min(max(K + dz - 1, 0), m2 - 1);
+                const int64_t q = (int64_t)z * csz + (int64_t)y * csy + x;
+                ce[dz][dy][dx] = (double)C.e[q];
+                ca |= (C.active[q] != 0 ? 1u : 0u) << (dz * 9 + dy * 3 + dx);
+            }
+    // per child side (0: low, 1: high) and axis: has a second contributor, and its weight
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    bool two[3][2];
+    double tw[3][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        two[0][h] = P.lo[0][i0 + h] != P.hi[0][i0 + h];
+        two[1][h] = P.lo[1][j0 + h] != P.hi[1][j0 + h];
+        two[2][h] = P.lo[2][k0 + h] != P.hi[2][k0 + h];
+        tw[0][h] = P.t[0][i0 + h];
+        tw[1][h] = P.t[1][j0 + h];
+        tw[2][h] = P.t[2][k0 + h];
+    }
+    const int n0 = L.n[0];
+    const int64_t sy = n0, sz = (int64_t)n0 * L.n[1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t row = (int64_t)(k0 + c) * sz + (int64_t)(j0 + b) * sy + i0;
+            V ev = *reinterpret_cast<const V *>(L.e + row);
+            const uint16_t fa = *reinterpret_cast<const uint16_t *>(L.active + row);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double wx[2] = {1.0 - tw[0][a], tw[0][a]}, wy[2] = {1.0 - tw[1][b], tw[1][b]},
+                             wz[2] = {1.0 - tw[2][c], tw[2][c]};
+                // neighbourhood index of contributor (lo, hi) on each axis: 1 is the parent
+                const int hx = a ? 2 : 0, hy = b ? 2 : 0, hz = c ? 2 : 0;
+                bool all = true;
+                double sv = 0.0;
+#pragma unroll
+                for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+                    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+                        for (int cx = 0; cx < 2; ++cx) {
+                            const bool ok = (cx == 0 || two[0][a]) && (cy == 0 || two[1][b]) && (cz == 0 || two[2][c]);
+                            const int ox = cx ? hx : 1, oy = cy ? hy : 1, oz = cz ? hz : 1;
+                            const bool act = (ca >> (oz * 9 + oy * 3 + ox)) & 1u;
+                            const double term = (wx[cx] * wy[cy]) * wz[cz] * ce[oz][oy][ox];
+                            if (ok) {
+                                if (!act) all = false;
+                                sv += term;
+                            }
+                        }
+                if (!all) sv = ce[1][1][1];
+                const bool fine_act = ((fa >> (8 * a)) & 0xff) != 0;
+                T &dst = a ? ev.y : ev.x;
+                if (fine_act) dst = (T)((double)dst + sv);
+            }
+            *reinterpret_cast<V *>(L.e + row) = ev;
+        }
+}
+
 // =======================================================================================
 // residual norm on level 0 with the lambda update
 //   r = f - S p (fluid rows);  a = r - lambda_k;  partials of sum V a, sum a^2, sum a
@@ -1184,7 +1272,13 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
         for (int l = Lb - 1; l >= 1; --l) {
             Coarse<T> L = coarse_view<T>(g, l);
             int nb = nblk(g->lev[l].ncell());
-            hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), prolong_tab(g, l));
+            const ProlongTab PT = prolong_tab(g, l);
+            if (PT.halved[0] && PT.halved[1] && PT.halved[2] && g->lev[l].prolong_sides &&
+                g->lev[l].ncell() >= PROLONG8_MIN_CELLS)
+                hipLaunchKernelGGL(k_prolongC8<T>, dim3(nblk(g->lev[l + 1].ncell())), dim3(256), 0, s, L,
+                                   coarse_view<T>(g, l + 1), PT);
+            else
+                hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), PT);
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
                 if (o->nu2 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu2, &g->sc->vol[l], 0, s);
             } else if ((e = smooth_level<T>(g, l, o->nu2, s)) != hipSuccess) {
