@@ -41,13 +41,15 @@ __global__ void __launch_bounds__(REFRESH_NT)
     const double beta = G.beta[8 * gc + m];
     const unsigned gm = G.gmask[gc];
     const int32_t flags = G.flags[gc];
+    // issued with the stencil loads, so the store needs no further round trip
+    const int64_t cell = G.cell[gc];
+    const double hg = gh ? gh[gc] : 0.0;
     double term = 0.0;
     if (live && q >= 0) term = beta * (double)(((gm >> m) & 1u) ? src_ghost[q] : dst[q]);
     term += __shfl_xor(term, 1, 64);
     term += __shfl_xor(term, 2, 64);
     term += __shfl_xor(term, 4, 64);
     if (!live || m != 0) return;
-    const int64_t cell = G.cell[gc];
     double v;
     if (flags & GF_DEGENERATE) {
         int i, j, k;
@@ -67,7 +69,7 @@ __global__ void __launch_bounds__(REFRESH_NT)
                 }
         v = n ? sm / n : 0.0;
     } else {
-        v = gh ? term + gh[gc] : term;
+        v = gh ? term + hg : term;
     }
     dst[cell] = (T)v;
 }
