@@ -98,8 +98,13 @@ __global__ void __launch_bounds__(BXT *BY)
     using PD = SweepPlane<T, VEC>;
     constexpr int NC = 2 * BXT;  // columns of a tile including the 2-column halo
     constexpr int TXC = NC - 4, TY = BY - 4;
-    __shared__ T so[2][BY][NC + 1];  // old values of the plane whose red values are formed
-    __shared__ T sr[2][BY][NC + 1];  // red-updated values of the plane whose black values are formed
+    // LDS planes with a guard ring (one row above and below, one column on the left, two on
+    // the right keeping the pitch odd): tile row r, column c live at [r + 1][c + 1], so the
+    // neighbour reads of every lane (the discarded ones of the outer rings included) stay
+    // inside the arrays; the guards are zeroed once and never written again
+    constexpr int GR = BY + 2, GC = NC + 3;
+    __shared__ T so[2][GR][GC];  // old values of the plane whose red values are formed
+    __shared__ T sr[2][GR][GC];  // red-updated values of the plane whose black values are formed
     __shared__ T saz[2][SW_KC_MAX + 8];  // z coefficients of planes k0-2 .. k1+5
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs; give every
     // XCD a contiguous range of tiles so neighbouring tiles share one L2
@@ -120,6 +125,15 @@ __global__ void __launch_bounds__(BXT *BY)
         const bool kin = kk >= 0 && kk < F.nz;
         saz[0][q] = kin ? F.azm[kk] : T(0);
         saz[1][q] = kin ? F.azp[kk] : T(0);
+    }
+    for (int q = (int)threadIdx.x; q < 2 * GC + 3 * BY; q += BXT * BY) {
+        const int u = q - 2 * GC;
+        const int r = (q < GC) ? 0 : (q < 2 * GC) ? BY + 1 : 1 + u / 3;
+        const int c = (q < 2 * GC) ? q % GC : (u % 3 == 0) ? 0 : NC + u % 3;
+        so[0][r][c] = T(0);
+        so[1][r][c] = T(0);
+        sr[0][r][c] = T(0);
+        sr[1][r][c] = T(0);
     }
     const int lc = 2 * tx;              // local column of this thread's first cell
     const int ia = txi * TXC - 2 + lc;  // global column of the first cell (even); second = ia + 1
@@ -191,8 +205,8 @@ __global__ void __launch_bounds__(BXT *BY)
         const int l_ = (FR) ? lc : lc + 1;                                                                         \
         const bool live_ = (FR) ? (red0 && (C).fl0()) : (red1 && (C).fl1());                      \
         const T v_ = rb_update<T>((FR) ? axm0 : axm1, (FR) ? axp0 : axp1, aym, ayp, saz[0][(q) - k0 + 2],          \
-                                  saz[1][(q) - k0 + 2], (FR) ? dxy0 : dxy1, OB[ty][l_ - 1], OB[ty][l_ + 1],        \
-                                  OB[ty - 1][l_], OB[ty + 1][l_], (FR) ? (M).o0 : (M).o1, (FR) ? (P).o0 : (P).o1,  \
+                                  saz[1][(q) - k0 + 2], (FR) ? dxy0 : dxy1, OB[ty + 1][l_], OB[ty + 1][l_ + 2],    \
+                                  OB[ty][l_ + 1], OB[ty + 2][l_ + 1], (FR) ? (M).o0 : (M).o1, (FR) ? (P).o0 : (P).o1, \
                                   (FR) ? (C).f0 : (C).f1, lam);                                                    \
         R0 = ((FR) && live_) ? v_ : (C).o0;                                                                        \
         R1 = (!(FR) && live_) ? v_ : (C).o1;                                                                       \
@@ -205,10 +219,10 @@ __global__ void __launch_bounds__(BXT *BY)
     // loads.
 #define IBM_STEP(A, B, C, k, FR)                                                                                   \
     {                                                                                                              \
-        so[buf][ty][lc] = (B).o0;                                                                                  \
-        so[buf][ty][lc + 1] = (B).o1;                                                                              \
-        sr[buf][ty][lc] = pb0;                                                                                     \
-        sr[buf][ty][lc + 1] = pb1;                                                                                 \
+        so[buf][ty + 1][lc + 1] = (B).o0;                                                                          \
+        so[buf][ty + 1][lc + 2] = (B).o1;                                                                          \
+        sr[buf][ty + 1][lc + 1] = pb0;                                                                             \
+        sr[buf][ty + 1][lc + 2] = pb1;                                                                             \
         __syncthreads();                                                                                           \
         T pc0, pc1;                                                                                                \
         IBM_RED_PAIR((k) + 1, A, B, C, so[buf], pc0, pc1, FR);                                                     \
@@ -217,8 +231,8 @@ __global__ void __launch_bounds__(BXT *BY)
             const int l_ = (FR) ? lc : lc + 1;                                                                     \
             const bool live_ = (FR) ? (blk0 && (A).fl0()) : (blk1 && (A).fl1());                  \
             const T v_ = rb_update<T>((FR) ? axm0 : axm1, (FR) ? axp0 : axp1, aym, ayp, saz[0][(k) - k0 + 2],      \
-                                      saz[1][(k) - k0 + 2], (FR) ? dxy0 : dxy1, sr[buf][ty][l_ - 1],               \
-                                      sr[buf][ty][l_ + 1], sr[buf][ty - 1][l_], sr[buf][ty + 1][l_],               \
+                                      saz[1][(k) - k0 + 2], (FR) ? dxy0 : dxy1, sr[buf][ty + 1][l_],               \
+                                      sr[buf][ty + 1][l_ + 2], sr[buf][ty][l_ + 1], sr[buf][ty + 2][l_ + 1],       \
                                       (FR) ? pa0 : pa1, (FR) ? pc0 : pc1, (FR) ? (A).f0 : (A).f1, lam);           \
             out0 = ((FR) && live_) ? v_ : pb0;                                                                     \
             out1 = (!(FR) && live_) ? v_ : pb1;                                                                    \
@@ -252,13 +266,13 @@ __global__ void __launch_bounds__(BXT *BY)
         PD q0 = load(k0 - 2), q1 = load(k0 - 1), q2 = load(k0), q3 = load(k0 + 1), q4 = load(k0 + 2),             \
            q5 = load(k0 + 3);                                                                                      \
         T pa0, pa1, pb0, pb1; /* red-updated values of planes k-1 and k */                                         \
-        so[0][ty][lc] = q1.o0;                                                                                     \
-        so[0][ty][lc + 1] = q1.o1;                                                                                 \
+        so[0][ty + 1][lc + 1] = q1.o0;                                                                             \
+        so[0][ty + 1][lc + 2] = q1.o1;                                                                             \
         __syncthreads();                                                                                           \
         IBM_RED_PAIR(k0 - 1, q0, q1, q2, so[0], pa0, pa1, (S));                                                    \
         q0 = load(k0 + 4);                                                                                         \
-        so[1][ty][lc] = q2.o0;                                                                                     \
-        so[1][ty][lc + 1] = q2.o1;                                                                                 \
+        so[1][ty + 1][lc + 1] = q2.o0;                                                                             \
+        so[1][ty + 1][lc + 2] = q2.o1;                                                                             \
         __syncthreads();                                                                                           \
         IBM_RED_PAIR(k0, q1, q2, q3, so[1], pb0, pb1, !(S));                                                       \
         q1 = load(k0 + 5);                                                                                         \
