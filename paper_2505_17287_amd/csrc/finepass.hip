@@ -67,7 +67,8 @@ __device__ __forceinline__ void zm_block_sums_store(const double (&v)[NS], doubl
 
 // Sums of the Krylov operator passes.  DOTS 0: w = S y, sum V w.  DOTS 1 and 2: w = S y - mu
 // (the image with its volume-weighted fluid mean, known beforehand, removed), sum o w, and
-// for DOTS 2 also sum w w (o is the vector the image is dotted with: the shadow residual or s)
+// for DOTS 2 also sum w w (o is the vector the image is dotted with: the shadow residual or s).
+// DOTS 3: the residual w = o - S y (o the right-hand side), sum V w.
 template <int DOTS>
 struct ApplySums {
     static constexpr int NS = DOTS == 2 ? 2 : 1;
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(ZM_NT)
     k_apply_fluid_zm(Fine<double> F, const double *__restrict__ y, double *__restrict__ w,
                      const double *__restrict__ o, const double *__restrict__ mup, ZTiles t, double *partials) {
     constexpr int NS = ApplySums<DOTS>::NS;
-    const double mu = DOTS ? *mup : 0.0;
+    const double mu = (DOTS == 1 || DOTS == 2) ? *mup : 0.0;
     const ZPos z = zpos(t, F.nz);
     if (!z.live) {
         if (threadIdx.x == 0)
@@ -385,11 +386,13 @@ __global__ void __launch_bounds__(ZM_NT)
         zm_stencil<double>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,  \
                            (D).xp, (D).ym, (D).yp, ym1, (D).pp, num, diag);                                        \
         const bool fl = in && (D).ty == T_FLUID;                                                                   \
-        const double a = fl ? (DOTS ? (num - diag * yc) - mu : num - diag * yc) : 0.0;                             \
+        const double a = fl ? (DOTS == 3 ? (D).fv - (num - diag * yc)                                              \
+                                         : (DOTS ? (num - diag * yc) - mu : num - diag * yc))                      \
+                            : 0.0;                                                                                 \
         if (in && k_ < z.k1) {                                                                                     \
             w[(int64_t)k_ * plane + rowoff] = a;                                                                   \
-            if (DOTS == 0) acc[0] += (vxy * (D).wz) * a;                                                           \
-            if (DOTS >= 1) acc[0] += (D).fv * a;                                                                   \
+            if (DOTS == 0 || DOTS == 3) acc[0] += (vxy * (D).wz) * a;                                              \
+            if (DOTS == 1 || DOTS == 2) acc[0] += (D).fv * a;                                                      \
             if (DOTS == 2) acc[1 % NS] += a * a;                                                                   \
         }                                                                                                          \
         ym1 = yc;                                                                                                  \
@@ -623,7 +626,7 @@ __global__ void __launch_bounds__(ZP_NT)
                       const double *__restrict__ o, const double *__restrict__ mup, ZTiles t, double *partials) {
     using V = double2;
     constexpr int NS = ApplySums<DOTS>::NS;
-    const double mu = DOTS ? *mup : 0.0;
+    const double mu = (DOTS == 1 || DOTS == 2) ? *mup : 0.0;
     const ZPos2 z = zpos2(t, F.nz);
     if (!z.live) {
         if (threadIdx.x == 0)
@@ -669,20 +672,24 @@ __global__ void __launch_bounds__(ZP_NT)
                            (D).ym.x, (D).yp.x, ym1.x, (D).pp.x, n0, d0);                                           \
         zm_stencil<double>(axm1, axp1, aym, ayp, (D).azm, (D).azp, true, hx1, hy0, hy1, z0_, z1_, yc.x, (D).xp,   \
                            (D).ym.y, (D).yp.y, ym1.y, (D).pp.y, n1, d1);                                           \
-        const double a0 = (in && ((D).tt & 0xff) == T_FLUID) ? (DOTS ? (n0 - d0 * yc.x) - mu : n0 - d0 * yc.x)    \
-                                                             : 0.0;                                                \
-        const double a1 = (in && ((D).tt >> 8) == T_FLUID) ? (DOTS ? (n1 - d1 * yc.y) - mu : n1 - d1 * yc.y)      \
-                                                           : 0.0;                                                  \
+        const double a0 = (in && ((D).tt & 0xff) == T_FLUID)                                                      \
+                              ? (DOTS == 3 ? (D).fv.x - (n0 - d0 * yc.x)                                           \
+                                           : (DOTS ? (n0 - d0 * yc.x) - mu : n0 - d0 * yc.x))                      \
+                              : 0.0;                                                                               \
+        const double a1 = (in && ((D).tt >> 8) == T_FLUID)                                                        \
+                              ? (DOTS == 3 ? (D).fv.y - (n1 - d1 * yc.y)                                           \
+                                           : (DOTS ? (n1 - d1 * yc.y) - mu : n1 - d1 * yc.y))                      \
+                              : 0.0;                                                                               \
         if (in && k_ < z.k1) {                                                                                     \
             V o_;                                                                                                  \
             o_.x = a0;                                                                                             \
             o_.y = a1;                                                                                             \
             *reinterpret_cast<V *>(w + (int64_t)k_ * plane + rowoff) = o_;                                         \
-            if (DOTS == 0) {                                                                                       \
+            if (DOTS == 0 || DOTS == 3) {                                                                          \
                 acc[0] += (vxy0 * (D).wz) * a0;                                                                    \
                 acc[0] += (vxy1 * (D).wz) * a1;                                                                    \
             }                                                                                                      \
-            if (DOTS >= 1) {                                                                                       \
+            if (DOTS == 1 || DOTS == 2) {                                                                          \
                 acc[0] += (D).fv.x * a0;                                                                           \
                 acc[0] += (D).fv.y * a1;                                                                           \
             }                                                                                                      \
@@ -754,6 +761,7 @@ hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w,
                               int dots, double *partials, int *nparts, hipStream_t s) {
     if (dots == 1) return apply_fluid_dots<1>(F, y, w, o, mu, partials, nparts, s);
     if (dots == 2) return apply_fluid_dots<2>(F, y, w, o, mu, partials, nparts, s);
+    if (dots == 3) return apply_fluid_dots<3>(F, y, w, o, mu, partials, nparts, s);
     return apply_fluid_dots<0>(F, y, w, o, mu, partials, nparts, s);
 }
 

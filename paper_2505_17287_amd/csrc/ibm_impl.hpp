@@ -84,7 +84,8 @@ hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coar
                            hipStream_t s);
 // Krylov operator on fluid rows.  dots 0: w = S y, one sum per workgroup (sum V w).  dots 1
 // and 2: w = S y - *mu (device scalar: the image's volume-weighted fluid mean), sums of o w and
-// (dots 2) of w w per workgroup, stored with a stride of 1 or 2.
+// (dots 2) of w w per workgroup, stored with a stride of 1 or 2.  dots 3: the residual
+// w = o - S y (o the right-hand side; mu unused), sum V w per workgroup.
 hipError_t launch_apply_fluid(const Fine<double> &F, const double *y, double *w, const double *o, const double *mu,
                               int dots, double *partials, int *nparts, hipStream_t s);
 hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *f, double *out, double omega,

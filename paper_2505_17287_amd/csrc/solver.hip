@@ -1599,29 +1599,6 @@ __global__ void k_ghost_flux(GhostView G, Fine<double> F, const double *__restri
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// r = f - (A x) on fluid rows (ghost rows written by k_apply_ghost mode 1), partial V-sums
-__global__ void __launch_bounds__(NORM_NT) k_resid_fluid(Fine<double> F, const double *__restrict__ f,
-                                                         const double *__restrict__ x, double *r, double *partials) {
-    __shared__ double sh[NORM_NT / 64];
-    const int64_t N = (int64_t)F.nx * F.ny * F.nz;
-    double sv = 0.0;
-    for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
-        if (F.type[id] != T_FLUID) {
-            r[id] = 0.0;
-            continue;
-        }
-        int i, j, k;
-        unflatten(id, F.nx, F.ny, i, j, k);
-        double num, diag;
-        fine_stencil(F, x, i, j, k, id, num, diag);
-        const double a = f[id] - (num - diag * x[id]);
-        r[id] = a;
-        sv += ((F.wx[i] * F.wy[j]) * F.wz[k]) * a;
-    }
-    const double t = block_sum<NORM_NT>(sv, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
 // start of the Krylov recurrences on the residual v: projection of its fluid part
 // (v -= mu_v; mode 2) or none (restart, mode 3), then rh = v and the sums v.v (all) and v.v
 // (fluid).  (The operator images of a step are projected where they are formed.)
@@ -1877,11 +1854,14 @@ hipError_t krylov_setup(ibm_grid *g, hipStream_t s) {
 // r = P (b - A x), rh = r, rho = rh.r, norm of the fluid part; lambda = removed mean
 hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s) {
     double *r = g->kv[0], *rh = g->kv[1];
-    hipLaunchKernelGGL(k_resid_fluid, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), f, x, r, g->partials);
+    // fluid rows: the z-marching operator pass in its residual form, with sum V r per workgroup
+    int nparts = 0;
+    hipError_t e = launch_apply_fluid(fine64(g), x, r, f, nullptr, 3, g->partials, &nparts, s);
+    if (e != hipSuccess) return e;
     if (g->ng > 0)
         hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), x, r, g->g_scale, g->nx,
                            g->ny, g->nz, g->type, 1, (const double *)nullptr, (double *)nullptr);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, nparts, 1, g->sc, (int)K_MU);
     hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, r, rh, g->sc, 2, g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_INIT);
     return hipGetLastError();
