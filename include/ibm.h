@@ -273,10 +273,12 @@ ibm_status ibm_debug_sweep(ibm_grid *g, double *p, const double *rhs, double lam
 /* (S p) on fluid rows, 0 elsewhere (device in/out). */
 ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stream);
 
-/* Timing of the level-0 smoother: with profiling on, every fine-level red-black sweep is
-   bracketed by HIP events on its launch stream (at most 32 sweeps between two host
-   synchronisations are timed).  get_profile returns the summed milliseconds and the number
-   of timed FP64 and FP32 sweeps since profiling was switched on. */
+/* Timing of the level-0 smoother.  on = 0: off.  on = n >= 1: every n-th fine-level
+   red-black sweep (counted from this call) is bracketed by HIP events on its launch stream
+   (at most 32 sweeps between two host synchronisations are timed); a stride above one keeps
+   the events' own cost out of the timed run, and a stride coprime to the sweeps of a cycle
+   samples every position in it.  on < 0 -> IBM_E_ARG.  get_profile returns the summed
+   milliseconds and the number of timed FP64 and FP32 sweeps since profiling was switched on. */
 ibm_status ibm_set_profiling(ibm_grid *g, int on);
 ibm_status ibm_get_profile(const ibm_grid *g, double *ms_fp64, int64_t *n_fp64, double *ms_fp32, int64_t *n_fp32);
 

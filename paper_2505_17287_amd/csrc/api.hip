@@ -997,6 +997,7 @@ ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stre
 
 ibm_status ibm_set_profiling(ibm_grid *g, int on) {
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_profiling: NULL handle");
+    if (on < 0) return fail(g, IBM_E_ARG, "ibm_set_profiling: on must be >= 0");
     Prof &P = g->prof;
     if (on && P.ev.empty()) {
         HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
@@ -1005,6 +1006,8 @@ ibm_status ibm_set_profiling(ibm_grid *g, int on) {
         for (auto &e : P.ev) HIP_TRY(hipEventCreate(&e), "event create");
     }
     P.on = on != 0;
+    P.stride = on > 0 ? on : 1;
+    P.seq = 0;
     P.used = 0;
     P.ms[0] = P.ms[1] = 0.0;
     P.count[0] = P.count[1] = 0;

@@ -180,6 +180,8 @@ struct SolveState {  // in-flight solve of the step API
 // optional per-launch timing of the level-0 smoother (HIP events on the launch stream)
 struct Prof {
     bool on = false;
+    int stride = 1;              // time every stride-th level-0 sweep
+    long long seq = 0;           // level-0 sweeps launched since profiling was switched on
     std::vector<hipEvent_t> ev;  // start/stop pairs
     std::vector<int> kind;       // per pair: 0 FP64 sweep, 1 FP32 sweep
     int used = 0;

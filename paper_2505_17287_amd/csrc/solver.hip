@@ -1155,7 +1155,7 @@ template <typename T>
 static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *pout, const T *rhs, const T *lam,
                               hipStream_t s) {
     Prof &P = g->prof;
-    const bool rec = P.on && P.used + 2 <= (int)P.ev.size();
+    const bool rec = P.on && (P.seq++ % P.stride) == 0 && P.used + 2 <= (int)P.ev.size();
     hipError_t e;
     if (rec && (e = hipEventRecord(P.ev[P.used], s)) != hipSuccess) return e;
     if ((e = launch_sweep<T>(F, pin, pout, rhs, lam, s)) != hipSuccess) return e;

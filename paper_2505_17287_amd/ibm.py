@@ -458,9 +458,12 @@ class Grid:
         return U
 
     # smoother timing
-    def set_profiling(self, on=True):
+    def set_profiling(self, on=True, stride=1):
+        """on: time fine-level sweeps; stride: time every stride-th one (see ibm.h)."""
+        if stride < 1:
+            raise ValueError("stride must be >= 1")
         with self.torch.cuda.device(self.device):
-            self._check(lib().ibm_set_profiling(self._h, int(bool(on))))
+            self._check(lib().ibm_set_profiling(self._h, int(stride) if on else 0))
 
     def profile(self):
         vals = np.zeros(2, dtype=np.float64)

@@ -42,6 +42,15 @@ def test_create_grid_validates_arguments():
     assert b"strictly increasing" in L.ibm_last_error(None)
 
 
+def test_profiling_switch_validates_its_argument():
+    L = ibm.lib()
+    code, h = _create(8, 8, 8)
+    assert code == ibm.IBM_OK
+    assert L.ibm_set_profiling(h, -1) == ibm.IBM_E_ARG
+    assert L.ibm_set_profiling(h, 0) == ibm.IBM_OK  # off: no device work
+    L.ibm_destroy_grid(h)
+
+
 def test_workspace_bound_covers_every_plan():
     """The handle-free size is an upper bound of the exact size for stretched grids."""
     from paper_2505_17287_amd import inputs as I

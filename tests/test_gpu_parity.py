@@ -230,3 +230,19 @@ def test_determinism_bitwise():
     a, _ = g.poisson_solve(fd)
     b, _ = g.poisson_solve(fd)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_profiling_times_every_stride_th_sweep(stride):
+    """Two fixed V(2,2) cycles run eight level-0 sweeps; profiling with a stride times the
+    sweeps 0, stride, 2 stride, ... of them, each with a positive duration."""
+    torch = _torch()
+    wl, P, g, counts = _pair("spheres48")
+    fd = torch.from_numpy(P.rhs(*wl.velocity())).cuda()
+    g.set_profiling(True, stride=stride)
+    g.poisson_solve(fd, fixed_cycles=2, method="vcycle")
+    torch.cuda.synchronize()
+    prof = g.profile()
+    g.set_profiling(False)
+    assert prof["n_fp64"] == (8 + stride - 1) // stride
+    assert prof["ms_fp64"] > 0.0
