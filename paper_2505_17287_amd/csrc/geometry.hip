@@ -52,6 +52,9 @@ __global__ void k_level_axis(int n, const double *__restrict__ f, double *c, dou
     wf[i] = (float)(f[i + 1] - f[i]);
 }
 
+__global__ void k_prolong_tab(int nf, int nc, int halved, const double *__restrict__ fc, const double *__restrict__ cc,
+                              int *lo, int *hi, double *t);
+
 hipError_t launch_metrics(ibm_grid *g, hipStream_t s) {
     int n[3] = {g->nx, g->ny, g->nz};
     for (int d = 0; d < 3; ++d) {
@@ -64,6 +67,15 @@ hipError_t launch_metrics(ibm_grid *g, hipStream_t s) {
             // coarse faces were uploaded behind the centres array (see layout)
             hipLaunchKernelGGL(k_level_axis, dim3((L.n[d] + 127) / 128), dim3(128), 0, s, L.n[d],
                                L.c64[d] + L.n[d], L.c64[d], L.w64[d], L.w32[d]);
+        }
+    }
+    // prolongation tables: they depend on the grid alone, so they are built here once
+    for (int l = 1; l < g->nlev; ++l) {
+        LevelHost &Fh = g->lev[l - 1], &Ch = g->lev[l];
+        for (int d = 0; d < 3; ++d) {
+            const double *fc = (l == 1) ? g->c0[d] : Fh.c64[d];
+            hipLaunchKernelGGL(k_prolong_tab, dim3((Fh.n[d] + 127) / 128), dim3(128), 0, s, Fh.n[d], Ch.n[d],
+                               Ch.halved[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
         }
     }
     return hipGetLastError();
@@ -1041,9 +1053,20 @@ __global__ void k_inject0(int nx, int ny, int nz, const uint8_t *__restrict__ ty
     inject[id] = v;
 }
 
-__global__ void k_face_T(LevelDims F, LevelDims C, int d, const uint8_t *__restrict__ fine_active, bool fine_is_type,
+struct FaceAxes {  // per axis: coarse centres and the transmissibility outputs
+    const double *cc[3];
+    double *T64[3];
+    float *T32[3];
+};
+
+// the three axes in one launch: blockIdx.y is the axis
+__global__ void k_face_T(LevelDims F, LevelDims C, const uint8_t *__restrict__ fine_active, bool fine_is_type,
                          const double *__restrict__ fw0, const double *__restrict__ fw1, const double *__restrict__ fw2,
-                         const double *__restrict__ cc, double *T64, float *T32) {
+                         FaceAxes A) {
+    const int d = (int)blockIdx.y;
+    const double *__restrict__ cc = A.cc[d];
+    double *T64 = A.T64[d];
+    float *T32 = A.T32[d];
     int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= NC) return;
@@ -1131,13 +1154,13 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
         const double *fw0 = (l == 1) ? g->w0[0] : Fh.w64[0];
         const double *fw1 = (l == 1) ? g->w0[1] : Fh.w64[1];
         const double *fw2 = (l == 1) ? g->w0[2] : Fh.w64[2];
+        FaceAxes A;
         for (int d = 0; d < 3; ++d) {
-            hipLaunchKernelGGL(k_face_T, dim3(nb), dim3(256), 0, s, F, C, d, fa, fine_type, fw0, fw1, fw2, Ch.c64[d],
-                               Ch.T64[d], Ch.T32[d]);
-            const double *fc = (l == 1) ? g->c0[d] : Fh.c64[d];
-            hipLaunchKernelGGL(k_prolong_tab, dim3((Fh.n[d] + 127) / 128), dim3(128), 0, s, Fh.n[d], Ch.n[d],
-                               Ch.halved[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
+            A.cc[d] = Ch.c64[d];
+            A.T64[d] = Ch.T64[d];
+            A.T32[d] = Ch.T32[d];
         }
+        hipLaunchKernelGGL(k_face_T, dim3(nb, 3), dim3(256), 0, s, F, C, fa, fine_type, fw0, fw1, fw2, A);
     }
     if (g->nlev > 1) {
         const LevelHost &F0 = g->lev[0], &C1 = g->lev[1];
