@@ -47,6 +47,14 @@ __device__ __forceinline__ void zm_stencil(T axm, T axp, T aym, T ayp, T azm, T 
     diag = d;
 }
 
+// a full-field result nobody re-reads in this pass: non-temporal in FP64 (in FP32 the plain
+// store measured faster)
+template <typename T>
+__device__ __forceinline__ void store_stream(T *p, T v) {
+    if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <int NT>
 __device__ __forceinline__ void zm_block_sum_store(double v, double *partials) {
     __shared__ double sh[NT / 64];
@@ -226,7 +234,7 @@ __global__ void __launch_bounds__(ZM_NT)
         }                                                                                                          \
         if ((D).inj) s = (double)(D).e[0];                                                                         \
         if (in && k_ < z.k1 && (D).ty == T_FLUID) {                                                                \
-            pnext[(int64_t)k_ * plane + rowoff] = (T)((double)(D).pv + s);                                         \
+            store_stream<T>(pnext + (int64_t)k_ * plane + rowoff, (T)((double)(D).pv + s));                     \
         }                                                                                                          \
     }
     PPlane<T> qa = ld(z.k0), qb;
@@ -309,7 +317,8 @@ __global__ void __launch_bounds__(ZM_NT)
                     if (ok) s += term;
                 }
         if (D.inj) s = (double)lo.v[0];
-        if (in && k < z.k1 && D.ty == T_FLUID) pnext[(int64_t)k * plane + rowoff] = (T)((double)D.pv + s);
+        if (in && k < z.k1 && D.ty == T_FLUID)
+            store_stream<T>(pnext + (int64_t)k * plane + rowoff, (T)((double)D.pv + s));
     };
     // four coarse-plane slots and two fine-pair slots rotate by name (unrolled by four
     // pairs), so no register copy of a value still in flight stalls the queue
@@ -335,6 +344,9 @@ __global__ void __launch_bounds__(ZM_NT)
 }
 
 // ---- Krylov operator ---------------------------------------------------------------------
+// The FP64 level-0 results of the prolongation and operator passes are written with
+// non-temporal stores (store_stream): the writing pass does not read them again, and keeping
+// these full fields from displacing cached data measured faster over a whole projection.
 // w = S y on fluid rows, 0 elsewhere, with the sums of ApplySums<DOTS> over the block (the
 // fluid rows' contributions; w is 0 elsewhere).  The loads of plane k+1 are issued before
 // plane k is computed.
@@ -390,7 +402,7 @@ __global__ void __launch_bounds__(ZM_NT)
                                          : (DOTS ? (num - diag * yc) - mu : num - diag * yc))                      \
                             : 0.0;                                                                                 \
         if (in && k_ < z.k1) {                                                                                     \
-            w[(int64_t)k_ * plane + rowoff] = a;                                                                   \
+            __builtin_nontemporal_store(a, w + (int64_t)k_ * plane + rowoff);                                      \
             if (DOTS == 0 || DOTS == 3) acc[0] += (vxy * (D).wz) * a;                                              \
             if (DOTS == 1 || DOTS == 2) acc[0] += (D).fv * a;                                                      \
             if (DOTS == 2) acc[1 % NS] += a * a;                                                                   \
@@ -625,6 +637,7 @@ __global__ void __launch_bounds__(ZP_NT)
     k_apply_fluid_zm2(Fine<double> F, const double *__restrict__ y, double *__restrict__ w,
                       const double *__restrict__ o, const double *__restrict__ mup, ZTiles t, double *partials) {
     using V = double2;
+    typedef double NV __attribute__((ext_vector_type(2)));  // native pair for the streaming store
     constexpr int NS = ApplySums<DOTS>::NS;
     const double mu = (DOTS == 1 || DOTS == 2) ? *mup : 0.0;
     const ZPos2 z = zpos2(t, F.nz);
@@ -681,10 +694,8 @@ __global__ void __launch_bounds__(ZP_NT)
                                            : (DOTS ? (n1 - d1 * yc.y) - mu : n1 - d1 * yc.y))                      \
                               : 0.0;                                                                               \
         if (in && k_ < z.k1) {                                                                                     \
-            V o_;                                                                                                  \
-            o_.x = a0;                                                                                             \
-            o_.y = a1;                                                                                             \
-            *reinterpret_cast<V *>(w + (int64_t)k_ * plane + rowoff) = o_;                                         \
+            const NV o_ = {a0, a1};                                                                                \
+            __builtin_nontemporal_store(o_, reinterpret_cast<NV *>(w + (int64_t)k_ * plane + rowoff));             \
             if (DOTS == 0 || DOTS == 3) {                                                                          \
                 acc[0] += (vxy0 * (D).wz) * a0;                                                                    \
                 acc[0] += (vxy1 * (D).wz) * a1;                                                                    \

@@ -1686,15 +1686,17 @@ __global__ void k_p_update(const uint8_t *__restrict__ type, int64_t N, const do
         return;
     }
     const double beta = sc->beta, omega = sc->omega;
-    pd[id] = r[id] + beta * (pd[id] - omega * v[id]);
+    __builtin_nontemporal_store(r[id] + beta * (pd[id] - omega * v[id]), pd + id);
 }
 
+// The BiCGStab vector updates write their full-field results with non-temporal stores (see
+// the operator pass).
 // s = r - alpha v
 __global__ void k_s_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
                            const double *__restrict__ v, double *s, const Scalars *sc) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
-    s[id] = (type[id] == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id];
+    __builtin_nontemporal_store((type[id] == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id], s + id);
 }
 
 // x += alpha y + omega z ; r = s - omega t ; partials of rh.r (all) and r.r (fluid)
@@ -1709,9 +1711,9 @@ __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict
     for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
         const uint8_t ty = type[id];
         if (ty == T_DEAD) continue;
-        x[id] = x[id] + alpha * y[id] + omega * z[id];
+        __builtin_nontemporal_store(x[id] + alpha * y[id] + omega * z[id], x + id);
         const double rv = s[id] - omega * t[id];
-        r[id] = rv;
+        __builtin_nontemporal_store(rv, r + id);
         a += rh[id] * rv;
         if (ty == T_FLUID) b += rv * rv;
     }

@@ -96,6 +96,7 @@ __global__ void __launch_bounds__(BXT *BY)
     static_assert(BXT == 32 && BY % 4 == 0, "two same-parity rows of 32 threads per wave");
     using V = typename Vec2<T>::type;
     using PD = SweepPlane<T, VEC>;
+    typedef T NV __attribute__((ext_vector_type(2)));  // native pair for the streaming store
     constexpr int NC = 2 * BXT;  // columns of a tile including the 2-column halo
     constexpr int TXC = NC - 4, TY = BY - 4;
     // LDS planes with a guard ring (one row above and below, one column on the left, two on
@@ -240,15 +241,21 @@ __global__ void __launch_bounds__(BXT *BY)
         const int64_t id_ = (int64_t)(k) * plane + (int64_t)j * nx + ia;                                          \
         const bool kst_ = (k) < k1;                                                                                \
         if constexpr (VEC) { /* a pair is wholly inside or outside the tile interior: blk0 == blk1 */             \
-            if (kst_ && blk0) {                                                                                    \
-                V o_;                                                                                              \
-                o_.x = out0;                                                                                       \
-                o_.y = out1;                                                                                       \
-                *reinterpret_cast<V *>(pout + id_) = o_;                                                           \
+            if (kst_ && blk0) { /* FP64: non-temporal (the pass does not re-read it; measured faster) */       \
+                const NV o_ = {out0, out1};                                                                        \
+                if constexpr (sizeof(T) == 8)                                                                      \
+                    __builtin_nontemporal_store(o_, reinterpret_cast<NV *>(pout + id_));                           \
+                else                                                                                               \
+                    *reinterpret_cast<NV *>(pout + id_) = o_;                                                      \
             }                                                                                                      \
         } else if (kst_) {                                                                                         \
-            if (blk0) pout[id_] = out0;                                                                            \
-            if (blk1) pout[id_ + 1] = out1;                                                                        \
+            if constexpr (sizeof(T) == 8) {                                                                        \
+                if (blk0) __builtin_nontemporal_store(out0, pout + id_);                                           \
+                if (blk1) __builtin_nontemporal_store(out1, pout + id_ + 1);                                       \
+            } else {                                                                                               \
+                if (blk0) pout[id_] = out0;                                                                        \
+                if (blk1) pout[id_ + 1] = out1;                                                                    \
+            }                                                                                                      \
         }                                                                                                          \
         pa0 = pb0;                                                                                                 \
         pa1 = pb1;                                                                                                 \
