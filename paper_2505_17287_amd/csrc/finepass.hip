@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(ZM_NT)
         zm_stencil<double>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,  \
                            (D).xp, (D).ym, (D).yp, ym1, (D).pp, num, diag);                                        \
         const double v = ((D).ty == T_FLUID) ? (1.0 - omega) * yc + omega * ((num - (D).fv) / diag) : yc;         \
-        if (in && k_ < z.k1) out[(int64_t)k_ * plane + rowoff] = v;                                                \
+        if (in && k_ < z.k1) store_stream<double>(out + (int64_t)k_ * plane + rowoff, v);                          \
         ym1 = yc;                                                                                                  \
         yc = (D).pp;                                                                                               \
     }

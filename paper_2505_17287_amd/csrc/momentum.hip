@@ -260,8 +260,8 @@ __global__ void __launch_bounds__(ZM_NT)
                     if (hz0) lap -= D.azm * (fc - fzm);
                     const double hp = first ? h : D.hold[q];
                     const double b = fc + dt * (1.5 * h - 0.5 * hp) + a * lap;
-                    H.c[q][id] = h;
-                    B.c[q][id] = b;
+                    __builtin_nontemporal_store(h, H.c[q] + id);  // streaming, as in the sweep
+                    __builtin_nontemporal_store(b, B.c[q] + id);
                     acc += b * b;
                 }
             }
@@ -362,7 +362,8 @@ __global__ void __launch_bounds__(ZM_NT)
                     const double xc = cc[q];
                     const double num = D.b[q] + a * s;
                     const double r = num - den * xc;
-                    Y.c[q][id] = (1.0 - omega) * xc + omega * (num / den);
+                    // full-field result, not re-read by this pass: non-temporal (measured faster)
+                    __builtin_nontemporal_store((1.0 - omega) * xc + omega * (num / den), Y.c[q] + id);
                     acc += r * r;
                 }
             }
