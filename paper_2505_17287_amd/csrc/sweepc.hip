@@ -47,7 +47,11 @@ constexpr int SWC_KC_MIN = 8;    // shortest z chunk (each chunk re-reads four p
 constexpr int64_t SWC_MIN_CELLS = 1 << 19;
 
 // Relaxation value of one cell: the six neighbour products summed from zero in the order
-// -x, +x, -y, +y, -z, +z, the diagonal summed in the same order.
+// -x, +x, -y, +y, -z, +z, the diagonal summed in the same order.  A missing neighbour meets
+// a zero transmissibility (a wall face, or a high face masked where the level ends), so its
+// product is an exact zero; the sum starts at +0 and never becomes -0, so adding that zero
+// changes nothing, and the result has the bits of the one-colour kernel, which skips the
+// term.
 template <typename T>
 __device__ __forceinline__ T rbc_update(T txm, T txp, T tym, T typ, T tzm, T tzp, T xm, T xp, T ym, T yp, T zm, T zp,
                                         T r, T vol, T mu, T &diag) {
