@@ -67,7 +67,7 @@ typedef enum { IBM_VCYCLE = 0, IBM_BICGSTAB = 1, IBM_BICGSTAB_SRJ = 2 } ibm_meth
    srj_sweeps), each sweep followed by the ghost refresh.  FP64 only. */
 
 /* Solver options.  Defaults (ibm_default_opts): rel_tol 1e-10, max_cycles 200, V(2,2),
-   64 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested,
+   16 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested,
    BiCGStab outer iteration. */
 typedef struct {
     double rel_tol;          /* stop when ||r'||_2 <= rel_tol * ||f - Vmean(f)||_2 (fluid rows) */

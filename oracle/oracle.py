@@ -32,7 +32,7 @@ class OracleOpts(C.Structure):
                 ("method", C.c_int), ("srj_m", C.c_int), ("srj_omega", C.POINTER(C.c_double))]
 
     @staticmethod
-    def make(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, use_initial_guess=0,
+    def make(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=16, use_initial_guess=0,
              fixed_cycles=0, method="mg", srj_omega=None):
         """method "bicgstab_srj" needs srj_omega (the relaxation factors of one preconditioner
         application, kept alive by the caller for the duration of the call)."""

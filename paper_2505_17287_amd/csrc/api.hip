@@ -247,7 +247,7 @@ void ibm_default_opts(ibm_solve_opts *o) {
     o->max_cycles = 200;
     o->nu1 = 2;
     o->nu2 = 2;
-    o->coarsest_sweeps = 64;
+    o->coarsest_sweeps = 16;
     o->precision = IBM_FP64;
     o->use_initial_guess = 0;
     o->fixed_cycles = 0;

@@ -137,7 +137,7 @@ def declared_symbols(header=None):
     return sorted(set(re.findall(r"\b(ibm_[a-z_0-9]+)\s*\(", txt)))
 
 
-def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=64, precision="fp64",
+def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=16, precision="fp64",
               use_initial_guess=False, fixed_cycles=0, method="bicgstab", srj_sweeps=16):
     o = SolveOpts()
     lib().ibm_default_opts(C.byref(o))

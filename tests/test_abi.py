@@ -87,7 +87,7 @@ def test_levels_follow_semicoarsening_rule():
 
 def test_options_defaults():
     o = ibm.make_opts()
-    assert o.rel_tol == 1e-10 and o.max_cycles == 200 and (o.nu1, o.nu2, o.coarsest_sweeps) == (2, 2, 64)
+    assert o.rel_tol == 1e-10 and o.max_cycles == 200 and (o.nu1, o.nu2, o.coarsest_sweeps) == (2, 2, 16)
 
 
 def test_srj_schedule_host_call():
