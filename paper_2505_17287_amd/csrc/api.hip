@@ -644,8 +644,10 @@ static void prof_collect(ibm_grid *g) {
 }
 
 // BiCGStab driver: x lives in the second pressure buffer, the gauged result goes to p
+// sync_end: synchronise after the gauge (a caller that enqueues more work on the stream and
+// synchronises itself passes false)
 static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o,
-                               ibm_solve_stats *st, hipStream_t s) {
+                               ibm_solve_stats *st, hipStream_t s, bool sync_end) {
     const double t0 = now_s();
     double *x = g->p2;
     HIP_TRY(hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s), "memset scalars");
@@ -705,7 +707,7 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
         rel = hs->rel;
     }
     HIP_TRY(gauge_pass(g, x, p, s), "gauge");
-    HIP_TRY(hipStreamSynchronize(s), "gauge sync");
+    if (sync_end) HIP_TRY(hipStreamSynchronize(s), "gauge sync");
     if (st) {
         st->cycles = it;
         st->vcycles = 2 * it;
@@ -722,14 +724,14 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
 }
 
 static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, ibm_solve_stats *st,
-                             hipStream_t s) {
+                             hipStream_t s, bool sync_end = true) {
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "solve before ibm_build_ghost_stencils");
     ibm_status cs = check_opts(g, o);
     if (cs != IBM_OK) return cs;
     if (!rhs || !p) return fail(g, IBM_E_ARG, "NULL rhs or p");
     if (krylov_method(o->method)) {
         HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
-        return solve_krylov(g, rhs, p, o, st, s);
+        return solve_krylov(g, rhs, p, o, st, s, sync_end);
     }
     double t0 = now_s();
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
@@ -806,8 +808,11 @@ ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, 
     double t0 = now_s();
     double *f = g->frhs;
     HIP_TRY(rhs_pass(g, u, v, w, dt, f, s), "rhs");
-    ibm_status rs = solve_core(g, f, p, o, st, s);
-    if (rs < 0) return rs;
+    ibm_status rs = solve_core(g, f, p, o, st, s, false);  // synchronised after the correction
+    if (rs < 0) {
+        (void)hipStreamSynchronize(s);  // nothing of the failed solve is left in flight
+        return rs;
+    }
     double t1 = now_s();
     HIP_TRY(correct_pass(g, u, v, w, p, dt, s), "correct");
     HIP_TRY(divmax_pass(g, u, v, w, s), "divmax");
