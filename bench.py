@@ -5,9 +5,12 @@ One step = one pass of the whole ghost-cell projection on the multi-body 256^3 w
 (8 perturbed icospheres of 20,480 triangles on a stretched grid): cell classification,
 ghost-cell stencils and multigrid hierarchy, divergence right-hand side, pressure Poisson
 solve from p = 0 to relative residual 1e-10, velocity correction.  The body mesh is uploaded
-and validated once; inputs are resident in HBM before timing starts.
+and validated once; every timed step's input fields are resident in HBM before timing starts.
 
-Prints one JSON line (see the design doc for the fields).  --gpus N > 1 is not supported.
+Prints one JSON line: metric, value (projections/s), ms_per_step, the workload config, the
+fine sweep's roofline (live HIP-event timing, counter traffic) and the oracle's CPU
+baseline, plus the other forms (mixed, momentum, paper solver, moving bodies, serving).
+--gpus N > 1 is not supported.
 """
 import argparse
 import json
@@ -403,7 +406,7 @@ def main():
                          "calibration, 4 fused FP64 sweeps of level 0, one single-step projection")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.probe:
         probe(args)
