@@ -165,3 +165,77 @@ def test_wing_c2_fixed_cycles(method):
         print("steps", ncyc, "err", err, flush=True)
         assert err <= 1e-9
     g.close()
+
+
+def _check_projection(P, wl, t, uvw, p, uvw1, lam_gpu, tol):
+    """The GPU projection seen through the oracle's operators: fluid-row residual after the
+    uniform shift, ghost equations, gauge, and the correction of u* by the GPU pressure."""
+    fl, gh = t == 0, t == 1
+    V = _vol(wl)
+    f = P.rhs(*uvw, dt=1.0)
+    fm = f - np.sum(V[fl] * f[fl]) / np.sum(V[fl])
+    r = f - P.apply_S(p)
+    lam = np.sum(V[fl] * r[fl]) / np.sum(V[fl])
+    rel = np.linalg.norm(r[fl] - lam) / np.linalg.norm(fm[fl])
+    print("oracle-measured relative residual", rel, "lambda", lam, lam_gpu, flush=True)
+    assert rel <= 1.05 * tol
+    assert abs(lam - lam_gpu) <= 1e-9 * max(abs(lam), 1e-6 * np.abs(f).max())
+    q = P.ghost_refresh(p)
+    assert np.max(np.abs(q[gh] - p[gh])) <= 1e-9 * np.max(np.abs(p))
+    assert abs(np.sum(V[fl] * p[fl])) <= 1e-12 * np.sum(V[fl]) * np.max(np.abs(p))
+    for a, b in zip(uvw1, P.correct(*uvw, p, dt=1.0)):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_wing_512_mixed_and_fp64():
+    """The wing on its 512 x 256 x 256 grid (33.5M cells), the size its mixed-precision form
+    is measured at: FP64 and mixed projections to 1e-10 on one grid, each checked through
+    the oracle's operators (classification and stencils exhaustively), and the mixed solve
+    against the FP64 one on the same GPU when both are taken to 1e-12 (within 1e-8)."""
+    torch = _torch()
+    from paper_2505_17287_amd import ibm
+    wl = I.wing(512, 256, 256)
+    print("case", wl.name, flush=True)
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision="mixed")
+    counts = g.setup(wl.verts, wl.tris)
+    uvw = wl.velocity()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ud, vd, wd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in uvw)
+        pg, st = g.project(ud, vd, wd, dt=1.0, rel_tol=1e-10, precision=prec)
+        print(prec, "steps", st.cycles, "rel", st.rel_residual, flush=True)
+        assert st.status == 0 and st.rel_residual <= 1e-10
+        out[prec] = (pg.cpu().numpy(), tuple(a.cpu().numpy() for a in (ud, vd, wd)), st.lam)
+        del ud, vd, wd, pg
+    t_gpu = g.cell_types().cpu().numpy()
+    got = g.ghosts()
+
+    P = OracleProblem(wl.xf, wl.yf, wl.zf)
+    P.set_mesh(wl.verts, wl.tris)
+    P.classify()
+    t = P.types()
+    assert np.array_equal(t_gpu, t)
+    assert tuple(counts) == tuple(int((t == k).sum()) for k in range(3))
+    P.build_stencils()
+    ref = P.ghosts()
+    for key in ("cell", "flags", "stencil"):
+        assert np.array_equal(got[key], ref[key])
+    for key in ("bi", "n", "ip"):
+        assert np.max(np.abs(got[key] - ref[key]), initial=0.0) <= 1e-12
+    assert np.max(np.abs(got["beta"] - ref["beta"]), initial=0.0) <= 1e-12 * max(1.0, np.abs(ref["beta"]).max())
+    print("classification and stencils equal", flush=True)
+
+    for prec in ("fp64", "mixed"):
+        p, uvw1, lam_gpu = out[prec]
+        print("checking", prec, flush=True)
+        _check_projection(P, wl, t, uvw, p, uvw1, lam_gpu, 1e-10)
+
+    act = t != 2
+    fd = torch.from_numpy(P.rhs(*uvw, dt=1.0)).cuda()
+    p64, s64 = g.poisson_solve(fd, rel_tol=1e-12, precision="fp64", max_cycles=400)
+    p32, s32 = g.poisson_solve(fd, rel_tol=1e-12, precision="mixed", max_cycles=400)
+    assert s64.status == 0 and s32.status == 0
+    err = _err(p32.cpu().numpy(), p64.cpu().numpy(), act)
+    print("at 1e-12: steps fp64", s64.cycles, "mixed", s32.cycles, "mixed vs fp64", err, flush=True)
+    assert err <= 1e-8
+    g.close()
