@@ -314,17 +314,16 @@ __global__ void __launch_bounds__(64) k_col_pass(const double *__restrict__ V, c
     }
 }
 
-// per column: sort the crossings, mark cells strictly between crossing pairs as solid (1)
-__global__ void k_col_resolve(const int32_t *__restrict__ off, double *zs, const double *__restrict__ zc, int nx,
-                              int ny, int nz, uint8_t *type, int64_t *odd, int64_t cap) {
-    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= (int64_t)nx * ny) return;
-    if ((int64_t)off[(int64_t)nx * ny] > cap) return;  // overflowed: the host reports it
-    int64_t b = off[col];
-    int n = off[col + 1] - off[col];
-    double *z = zs + b;
-    for (int a = 1; a < n; ++a) {  // insertion sort (few crossings per column)
-        double v = z[a];
+// per column: sort the crossings in place (insertion sort: few per column) and count the
+// columns with an odd number of them (the host reports those)
+__global__ void k_col_sort(const int32_t *__restrict__ off, double *zs, int64_t ncol, int64_t *odd, int64_t cap) {
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    if ((int64_t)off[ncol] > cap) return;  // overflowed: the host reports it
+    const int n = off[col + 1] - off[col];
+    double *z = zs + off[col];
+    for (int a = 1; a < n; ++a) {
+        const double v = z[a];
         int q = a - 1;
         while (q >= 0 && z[q] > v) {
             z[q + 1] = z[q];
@@ -332,21 +331,26 @@ __global__ void k_col_resolve(const int32_t *__restrict__ off, double *zs, const
         }
         z[q + 1] = v;
     }
-    if (n & 1) {
-        atomicAdd((unsigned long long *)odd, 1ull);
-        n -= 1;
-    }
-    const int64_t plane = (int64_t)nx * ny;
-    for (int k = 0; k < nz; ++k) {
-        double zk = zc[k];
-        uint8_t solid = 0;
-        for (int m = 0; m < n; m += 2)
-            if (zk > z[m] && zk < z[m + 1]) {
-                solid = 1;
-                break;
-            }
-        type[(int64_t)k * plane + col] = solid;
-    }
+    if (n & 1) atomicAdd((unsigned long long *)odd, 1ull);
+}
+
+// one thread per cell: solid (1) iff the cell centre lies strictly between the crossings of a
+// sorted pair of its column (an odd last crossing is dropped), fluid (0) otherwise
+__global__ void k_col_fill(const int32_t *__restrict__ off, const double *__restrict__ zs,
+                           const double *__restrict__ zc, int64_t ncol, int64_t N, uint8_t *type, int64_t cap) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    if ((int64_t)off[ncol] > cap) return;
+    const uint32_t u = (uint32_t)id, k = u / (uint32_t)ncol, col = u - k * (uint32_t)ncol;  // N < 2^31
+    const int b = off[col], n = (off[col + 1] - b) & ~1;
+    const double zk = zc[k];
+    uint8_t solid = 0;
+    for (int m = 0; m < n; m += 2)
+        if (zk > zs[b + m] && zk < zs[b + m + 1]) {
+            solid = 1;
+            break;
+        }
+    type[id] = solid;
 }
 
 // ghost = solid with a fluid cell among its in-range 26 neighbours; dead = other solid.
@@ -391,6 +395,89 @@ __global__ void __launch_bounds__(MARK_NT) k_mark_ghosts(uint8_t *type, int nx, 
         long long v = 0;
         for (int q = 0; q < MARK_NT / 64; ++q) v += sh[threadIdx.x][q];
         if (v) atomicAdd((unsigned long long *)&counters[threadIdx.x], (unsigned long long)v);
+    }
+}
+
+// The same marking for rows whose length is a multiple of 16: a thread takes 16 cells of
+// one row with a single 16-byte load.  Only if one of them is solid does it load the nine
+// row segments of its 3 x 3 (y, z) neighbourhood, each with the byte before and after it,
+// all at once; bit b+1 of an 18-bit mask marks a fluid cell at x = i0 + b, so
+// m | m >> 1 | m >> 2 marks the cells with a fluid x-neighbour (or themselves fluid), and
+// the OR over the nine rows marks the solid cells whose 3 x 3 x 3 box holds a fluid cell.
+// Fluid bytes are rewritten unchanged and solid bytes stay nonzero, so concurrent
+// neighbour reads see the same fluid / solid state.
+constexpr int MARK16_NT = 256;
+
+__device__ __forceinline__ unsigned fluid_bits16(uint4 v) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    unsigned m = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) m |= (((w[q >> 2] >> (8 * (q & 3))) & 0xffu) == 0u ? 1u : 0u) << q;
+    return m;
+}
+
+__global__ void __launch_bounds__(MARK16_NT) k_mark_ghosts16(uint8_t *type, int nx, int ny, int nz, int64_t nseg,
+                                                             int64_t *counters) {
+    __shared__ long long sh[3][MARK16_NT / 64];
+    long long cf = 0, cg = 0, cd = 0;
+    const int64_t sg = (int64_t)blockIdx.x * MARK16_NT + threadIdx.x;
+    if (sg < nseg) {
+        const int segs = nx >> 4;
+        const int64_t row = sg / segs;
+        const int i0 = (int)(sg - row * segs) << 4;
+        const int k = (int)(row / ny), j = (int)(row - (int64_t)k * ny);
+        uint8_t *p0 = type + row * nx + i0;
+        const unsigned fl = fluid_bits16(*reinterpret_cast<const uint4 *>(p0));
+        const unsigned solid = ~fl & 0xffffu;
+        cf = 16 - __popc(solid);
+        if (solid) {
+            uint4 v[9];
+            uint8_t lo[9], hi[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int jj = j + q % 3 - 1, kk = k + q / 3 - 1;
+                const bool in = jj >= 0 && jj < ny && kk >= 0 && kk < nz;
+                const uint8_t *r = type + ((int64_t)(in ? kk : k) * ny + (in ? jj : j)) * nx + i0;
+                v[q] = *reinterpret_cast<const uint4 *>(r);
+                lo[q] = i0 > 0 ? r[-1] : (uint8_t)1;
+                hi[q] = i0 + 16 < nx ? r[16] : (uint8_t)1;
+                if (!in) {  // outside the grid: no fluid
+                    v[q] = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+                    lo[q] = hi[q] = 1;
+                }
+            }
+            unsigned near = 0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const unsigned m = (lo[q] == 0 ? 1u : 0u) | (fluid_bits16(v[q]) << 1) | ((hi[q] == 0 ? 1u : 0u) << 17);
+                near |= (m | (m >> 1) | (m >> 2)) & 0xffffu;
+            }
+            const unsigned ghost = solid & near, dead = solid & ~near;
+            cg = __popc(ghost);
+            cd = __popc(dead);
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t t = ((ghost >> q) & 1u) ? (uint32_t)T_GHOST : (((dead >> q) & 1u) ? (uint32_t)T_DEAD : 0u);
+                w[q >> 2] |= t << (8 * (q & 3));
+            }
+            *reinterpret_cast<uint4 *>(p0) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+    cf = wave_sum_ll(cf);
+    cg = wave_sum_ll(cg);
+    cd = wave_sum_ll(cd);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][wv] = cf;
+        sh[1][wv] = cg;
+        sh[2][wv] = cd;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        long long t = 0;
+        for (int q = 0; q < MARK16_NT / 64; ++q) t += sh[threadIdx.x][q];
+        if (t) atomicAdd((unsigned long long *)&counters[threadIdx.x], (unsigned long long)t);
     }
 }
 
@@ -466,11 +553,18 @@ hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
                            g->c0[1], nx, ny, nullptr, g->col_off, g->col_fill, g->crossings, g->cross_cap,
                            g->counters + 4);
     }
-    hipLaunchKernelGGL(k_col_resolve, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
-                       g->c0[2], nx, ny, nz, g->type, g->counters + 3, g->cross_cap);
-    hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)std::min<int64_t>((N + MARK_NT - 1) / MARK_NT, MARK_BLOCKS)),
-                       dim3(MARK_NT), 0, s, g->type, nx, ny, nz,
-                       g->counters);
+    hipLaunchKernelGGL(k_col_sort, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
+                       (int64_t)ncol, g->counters + 3, g->cross_cap);
+    hipLaunchKernelGGL(k_col_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
+                       g->c0[2], (int64_t)ncol, N, g->type, g->cross_cap);
+    if (nx % 16 == 0) {
+        const int64_t nseg = N / 16;
+        hipLaunchKernelGGL(k_mark_ghosts16, dim3((unsigned)((nseg + MARK16_NT - 1) / MARK16_NT)), dim3(MARK16_NT), 0, s,
+                           g->type, nx, ny, nz, nseg, g->counters);
+    } else {
+        hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)std::min<int64_t>((N + MARK_NT - 1) / MARK_NT, MARK_BLOCKS)),
+                           dim3(MARK_NT), 0, s, g->type, nx, ny, nz, g->counters);
+    }
     int64_t nb = (N + CMP_CH - 1) / CMP_CH;
     int32_t *blkc = g->col_cnt;  // reuse: ncol+1 >= nb is guaranteed by the layout
     int32_t *blko = g->col_fill;
