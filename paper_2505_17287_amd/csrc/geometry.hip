@@ -713,21 +713,47 @@ __global__ void __launch_bounds__(64 * CLOSEST_WAVES)
         b0[d] = bucket_coord(x[d] - r, G.bmin[d], G.bsize[d], G.nb[d]);
         b1[d] = bucket_coord(x[d] + r, G.bmin[d], G.bsize[d], G.nb[d]);
     }
-    for (int bz = b0[2]; bz <= b1[2]; ++bz)
-        for (int by = b0[1]; by <= b1[1]; ++by)
-            for (int bx = b0[0]; bx <= b1[0]; ++bx) {
-                int b = (bz * G.nb[1] + by) * G.nb[0] + bx;
-                for (int q = boff[b] + lane; q < boff[b + 1]; q += 64) {
-                    int32_t t = bent[q];
-                    double lo[3], hi[3];
-                    tri_bbox(V, T, t, lo, hi);
-                    bool far = false;
-                    for (int d = 0; d < 3; ++d)
-                        if (lo[d] > x[d] + r || hi[d] < x[d] - r) far = true;
-                    if (far) continue;
-                    consider_tri(V, T, t, x, best, bt, bq);
-                }
+    // The box's bucket entries are laid end to end: lane L of a chunk of 64 buckets holds
+    // bucket L's offset and count, a wave prefix sum gives each bucket's first position, and
+    // the lane taking position q finds its bucket as the last one starting at or before q
+    // (a binary search over lanes by shuffles).  All buckets' entries are fetched in one
+    // round instead of one bucket after another.
+    const int nbx = b1[0] - b0[0] + 1, nby = b1[1] - b0[1] + 1, nbox = nbx * nby * (b1[2] - b0[2] + 1);
+    for (int c0 = 0; c0 < nbox; c0 += 64) {
+        int start = 0, cnt = 0;
+        if (c0 + lane < nbox) {
+            const int cb = c0 + lane, bx = b0[0] + cb % nbx, by = b0[1] + (cb / nbx) % nby, bz = b0[2] + cb / (nbx * nby);
+            const int b = (bz * G.nb[1] + by) * G.nb[0] + bx;
+            start = boff[b];
+            cnt = boff[b + 1] - start;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64), excl = incl - cnt;
+        for (int q0 = 0; q0 < total; q0 += 64) {
+            const int q = q0 + lane;
+            int L = 0;  // the last lane whose first position is <= q
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int e = __shfl(excl, min(L + step, 63), 64);
+                if (L + step <= 63 && e <= q) L += step;
             }
+            const int st = __shfl(start, L, 64), ex = __shfl(excl, L, 64);
+            if (q >= total) continue;
+            const int32_t t = bent[st + (q - ex)];
+            double lo[3], hi[3];
+            tri_bbox(V, T, t, lo, hi);
+            bool far = false;
+            for (int d = 0; d < 3; ++d)
+                if (lo[d] > x[d] + r || hi[d] < x[d] - r) far = true;
+            if (far) continue;
+            consider_tri(V, T, t, x, best, bt, bq);
+        }
+    }
     closest_wave_min(best, bt, bq);
     if (bt == 0x7fffffff || !(best <= r * r)) {
         // nothing within the radius: search every triangle
