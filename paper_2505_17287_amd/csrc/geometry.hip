@@ -278,39 +278,70 @@ __device__ __forceinline__ bool ray_hits(const double *V, const int32_t *tri, do
     return true;
 }
 
-// one wave per triangle, lanes stride over the columns inside its xy bounding box
-__global__ void __launch_bounds__(64) k_col_pass(const double *__restrict__ V, const int32_t *__restrict__ T, int64_t nt,
-                                                 const double *__restrict__ xc, const double *__restrict__ yc, int nx,
-                                                 int ny, int32_t *cnt, const int32_t *off, int32_t *fill, double *zs,
-                                                 int64_t cap, int64_t *overflow) {
-    int64_t t = blockIdx.x;
-    if (t >= nt) return;
-    const int32_t *tri = T + 3 * t;
-    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
-    for (int q = 0; q < 3; ++q) {
-        double x = V[3 * tri[q]], y = V[3 * tri[q] + 1];
-        xmin = fmin(xmin, x);
-        xmax = fmax(xmax, x);
-        ymin = fmin(ymin, y);
-        ymax = fmax(ymax, y);
+// one column of a triangle: its +z crossing, counted (cnt) or stored at the column's next
+// slot (zs)
+__device__ __forceinline__ void col_cross(const double *V, const int32_t *tri, const double *xc, const double *yc,
+                                          int nx, int i, int j, int32_t *cnt, const int32_t *off, int32_t *fill,
+                                          double *zs, int64_t cap, int64_t *overflow) {
+    double z;
+    if (!ray_hits(V, tri, xc[i], yc[j], &z)) return;
+    const int64_t col = (int64_t)j * nx + i;
+    if (!zs) {
+        atomicAdd(&cnt[col], 1);
+    } else {
+        const int slot = atomicAdd(&fill[col], 1);
+        const int64_t pos = (int64_t)off[col] + slot;
+        if (pos < cap) zs[pos] = z;
+        else atomicAdd((unsigned long long *)overflow, 1ull);
     }
-    int i0 = lower_idx(xc, nx, xmin), i1 = upper_idx(xc, nx, xmax);
-    int j0 = lower_idx(yc, ny, ymin), j1 = upper_idx(yc, ny, ymax);
-    if (i1 < i0 || j1 < j0) return;
-    int64_t ni = i1 - i0 + 1, ncols = ni * (int64_t)(j1 - j0 + 1);
-    for (int64_t q = threadIdx.x; q < ncols; q += 64) {
-        int i = i0 + (int)(q % ni), j = j0 + (int)(q / ni);
-        double z;
-        if (!ray_hits(V, tri, xc[i], yc[j], &z)) continue;
-        int64_t col = (int64_t)j * nx + i;
-        if (!zs) {
-            atomicAdd(&cnt[col], 1);
-        } else {
-            int slot = atomicAdd(&fill[col], 1);
-            int64_t pos = (int64_t)off[col] + slot;
-            if (pos < cap) zs[pos] = z;
-            else atomicAdd((unsigned long long *)overflow, 1ull);
+}
+
+// One triangle per lane.  A lane visits the columns of its triangle's xy bounding box
+// itself when there are at most COL_SMALL of them (the usual case: triangles smaller than
+// a cell); triangles with more columns are then taken one at a time by the whole wave,
+// its lanes striding over the columns.
+constexpr int COL_NT = 256, COL_SMALL = 8;
+__global__ void __launch_bounds__(COL_NT) k_col_pass(const double *__restrict__ V, const int32_t *__restrict__ T,
+                                                     int64_t nt, const double *__restrict__ xc,
+                                                     const double *__restrict__ yc, int nx, int ny, int32_t *cnt,
+                                                     const int32_t *off, int32_t *fill, double *zs, int64_t cap,
+                                                     int64_t *overflow) {
+    const int64_t t = (int64_t)blockIdx.x * COL_NT + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int i0 = 0, j0 = 0, ni = 0, nj = 0;
+    if (t < nt) {
+        const int32_t *tri = T + 3 * t;
+        double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+        for (int q = 0; q < 3; ++q) {
+            const double x = V[3 * tri[q]], y = V[3 * tri[q] + 1];
+            xmin = fmin(xmin, x);
+            xmax = fmax(xmax, x);
+            ymin = fmin(ymin, y);
+            ymax = fmax(ymax, y);
         }
+        i0 = lower_idx(xc, nx, xmin);
+        j0 = lower_idx(yc, ny, ymin);
+        const int i1 = upper_idx(xc, nx, xmax), j1 = upper_idx(yc, ny, ymax);
+        if (i1 >= i0 && j1 >= j0) {
+            ni = i1 - i0 + 1;
+            nj = j1 - j0 + 1;
+        }
+    }
+    const int64_t ncols = (int64_t)ni * nj;
+    if (ncols <= COL_SMALL) {
+        for (int q = 0; q < (int)ncols; ++q)
+            col_cross(V, T + 3 * t, xc, yc, nx, i0 + q % ni, j0 + q / ni, cnt, off, fill, zs, cap, overflow);
+    }
+    uint64_t big = __ballot(ncols > COL_SMALL);
+    while (big) {
+        const int L = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        const int tl = __shfl((int)t, L, 64), il = __shfl(i0, L, 64), jl = __shfl(j0, L, 64), nil = __shfl(ni, L, 64),
+                  njl = __shfl(nj, L, 64);
+        const int64_t nc = (int64_t)nil * njl;
+        for (int64_t q = lane; q < nc; q += 64)
+            col_cross(V, T + 3 * (int64_t)tl, xc, yc, nx, il + (int)(q % nil), jl + (int)(q / nil), cnt, off, fill, zs,
+                      cap, overflow);
     }
 }
 
@@ -417,7 +448,7 @@ __device__ __forceinline__ unsigned fluid_bits16(uint4 v) {
 }
 
 __global__ void __launch_bounds__(MARK16_NT) k_mark_ghosts16(uint8_t *type, int nx, int ny, int nz, int64_t nseg,
-                                                             int64_t *counters) {
+                                                             int64_t *part) {
     __shared__ long long sh[3][MARK16_NT / 64];
     long long cf = 0, cg = 0, cd = 0;
     const int64_t sg = (int64_t)blockIdx.x * MARK16_NT + threadIdx.x;
@@ -474,10 +505,29 @@ __global__ void __launch_bounds__(MARK16_NT) k_mark_ghosts16(uint8_t *type, int 
         sh[2][wv] = cd;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 3) {  // per-block counts (same-address atomics from every block would serialise)
         long long t = 0;
         for (int q = 0; q < MARK16_NT / 64; ++q) t += sh[threadIdx.x][q];
-        if (t) atomicAdd((unsigned long long *)&counters[threadIdx.x], (unsigned long long)t);
+        part[3 * (int64_t)blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// fluid, ghost and dead totals of k_mark_ghosts16's per-block counts, in one workgroup
+constexpr int SUM3_NT = 1024;
+__global__ void __launch_bounds__(SUM3_NT) k_sum_counts3(const int64_t *__restrict__ part, int64_t nblk,
+                                                         int64_t *counters) {
+    __shared__ long long sh[3][SUM3_NT / 64];
+    long long a[3] = {0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nblk; b += SUM3_NT)
+        for (int q = 0; q < 3; ++q) a[q] += part[3 * b + q];
+    for (int q = 0; q < 3; ++q) a[q] = wave_sum_ll(a[q]);
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 3; ++q) sh[q][threadIdx.x >> 6] = a[q];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        long long t = 0;
+        for (int w = 0; w < SUM3_NT / 64; ++w) t += sh[threadIdx.x][w];
+        counters[threadIdx.x] = t;
     }
 }
 
@@ -543,24 +593,27 @@ hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
     e = hipMemsetAsync(g->col_fill, 0, sizeof(int32_t) * (ncol + 1), s);
     if (e != hipSuccess) return e;
     if (g->nt > 0) {
-        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)g->nt), dim3(64), 0, s, g->verts, g->tris, g->nt, g->c0[0],
-                           g->c0[1], nx, ny, g->col_cnt, nullptr, nullptr, nullptr, (int64_t)0, nullptr);
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((g->nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, g->verts,
+                           g->tris, g->nt, g->c0[0], g->c0[1], nx, ny, g->col_cnt, nullptr, nullptr, nullptr, (int64_t)0,
+                           nullptr);
     }
     e = scan_counts(g->col_cnt, g->col_off, ncol + 1, (int64_t *)g->blk_cnt, s);
     if (e != hipSuccess) return e;
     if (g->nt > 0) {
-        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)g->nt), dim3(64), 0, s, g->verts, g->tris, g->nt, g->c0[0],
-                           g->c0[1], nx, ny, nullptr, g->col_off, g->col_fill, g->crossings, g->cross_cap,
-                           g->counters + 4);
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((g->nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, g->verts,
+                           g->tris, g->nt, g->c0[0], g->c0[1], nx, ny, nullptr, g->col_off, g->col_fill, g->crossings,
+                           g->cross_cap, g->counters + 4);
     }
     hipLaunchKernelGGL(k_col_sort, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
                        (int64_t)ncol, g->counters + 3, g->cross_cap);
     hipLaunchKernelGGL(k_col_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
                        g->c0[2], (int64_t)ncol, N, g->type, g->cross_cap);
     if (nx % 16 == 0) {
-        const int64_t nseg = N / 16;
-        hipLaunchKernelGGL(k_mark_ghosts16, dim3((unsigned)((nseg + MARK16_NT - 1) / MARK16_NT)), dim3(MARK16_NT), 0, s,
-                           g->type, nx, ny, nz, nseg, g->counters);
+        // per-block counts go to the reduction partials (3 per block <= N / 256 + 1024 entries)
+        const int64_t nseg = N / 16, nblk = (nseg + MARK16_NT - 1) / MARK16_NT;
+        int64_t *part = reinterpret_cast<int64_t *>(g->partials);
+        hipLaunchKernelGGL(k_mark_ghosts16, dim3((unsigned)nblk), dim3(MARK16_NT), 0, s, g->type, nx, ny, nz, nseg, part);
+        hipLaunchKernelGGL(k_sum_counts3, dim3(1), dim3(SUM3_NT), 0, s, (const int64_t *)part, nblk, g->counters);
     } else {
         hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)std::min<int64_t>((N + MARK_NT - 1) / MARK_NT, MARK_BLOCKS)),
                            dim3(MARK_NT), 0, s, g->type, nx, ny, nz, g->counters);
