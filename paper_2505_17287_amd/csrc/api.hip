@@ -347,22 +347,6 @@ ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64
     return IBM_OK;
 }
 
-// FNV-1a over the triangle indices and the vertex count: a moved body with unchanged
-// triangles needs no new topology check
-static uint64_t topology_hash(const int32_t *tris, int64_t nt, int64_t nv) {
-    uint64_t h = 1469598103934665603ull;
-    auto mix = [&](uint64_t v) {
-        for (int b = 0; b < 8; ++b) {
-            h ^= (v >> (8 * b)) & 0xff;
-            h *= 1099511628211ull;
-        }
-    };
-    mix((uint64_t)nv);
-    mix((uint64_t)nt);
-    for (int64_t i = 0; i < 3 * nt; ++i) mix((uint64_t)(uint32_t)tris[i]);
-    return h;
-}
-
 static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                                     void *stream, bool known_topology);
 
@@ -377,13 +361,22 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
     if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_set_geometry before ibm_bind_workspace");
     if (!verts || !tris || nv < 3 || nt < 1) return fail(g, IBM_E_ARG, "ibm_set_geometry: empty mesh");
     if (nv > g->nv_max || nt > g->nt_max) return fail(g, IBM_E_NOMEM, "mesh larger than the bound capacities");
-    for (int64_t i = 0; i < 3 * nv; ++i)
-        if (!std::isfinite(verts[i])) return fail(g, IBM_E_ARG, "non-finite vertex coordinate");
-    for (int64_t i = 0; i < 3 * nt; ++i)
-        if (tris[i] < 0 || tris[i] >= nv) return fail(g, IBM_E_ARG, "triangle index out of range");
-    const uint64_t th = topology_hash(tris, nt, nv);
-    if (!(known_topology && g->topo_valid && th == g->topo_hash)) {
+    bool finite = true;  // no early exit: the loops vectorise
+    for (int64_t i = 0; i < 3 * nv; ++i) finite &= std::isfinite(verts[i]);
+    if (!finite) return fail(g, IBM_E_ARG, "non-finite vertex coordinate");
+    // a move that keeps the triangles (the same indices as the last validated mesh, compared
+    // exactly) skips the index and closedness checks
+    const bool same = known_topology && g->topo_valid && g->topo_nv == nv &&
+                      (int64_t)g->topo_tris.size() == 3 * nt &&
+                      std::memcmp(g->topo_tris.data(), tris, sizeof(int32_t) * 3 * nt) == 0;
+    if (!same) {
         g->topo_valid = false;
+        int32_t tmin = tris[0], tmax = tris[0];
+        for (int64_t i = 0; i < 3 * nt; ++i) {
+            tmin = std::min(tmin, tris[i]);
+            tmax = std::max(tmax, tris[i]);
+        }
+        if (tmin < 0 || tmax >= nv) return fail(g, IBM_E_ARG, "triangle index out of range");
         // closed and consistently oriented: every directed edge once and its reverse once
         std::vector<int64_t> e(3 * nt);
         for (int64_t t = 0; t < nt; ++t)
@@ -397,7 +390,8 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
             if (!std::binary_search(e.begin(), e.end(), b * nv + a))
                 return fail(g, IBM_E_GEOMETRY, "mesh is not closed (edge without its reverse)");
         }
-        g->topo_hash = th;
+        g->topo_tris.assign(tris, tris + 3 * nt);
+        g->topo_nv = nv;
         g->topo_valid = true;
     }
     // bucket grid over the mesh bounding box: buckets at least as large as the largest

@@ -244,7 +244,8 @@ struct ibm_grid {
     double *g_betaDg = nullptr;            // per ghost: weight of the intercept value
     double *g_ubi = nullptr;               // 3 per ghost: velocity at the body intercept
     double *g_uscr = nullptr;              // 3 per ghost: held-back ghost values of an in-place pass
-    uint64_t topo_hash = 0;                // triangle indices of the last validated mesh
+    std::vector<int32_t> topo_tris;        // triangle indices of the last validated mesh
+    int64_t topo_nv = 0;                   // and its vertex count
     bool topo_valid = false;
     // fresh cells of the last move (capacity ghost_max)
     uint8_t *type_prev = nullptr;          // cell types before the move
