@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ibm_impl.hpp"
+#include "mesh_check.hpp"
 
 using namespace ibm;
 
@@ -377,19 +378,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
             tmax = std::max(tmax, tris[i]);
         }
         if (tmin < 0 || tmax >= nv) return fail(g, IBM_E_ARG, "triangle index out of range");
-        // closed and consistently oriented: every directed edge once and its reverse once
-        std::vector<int64_t> e(3 * nt);
-        for (int64_t t = 0; t < nt; ++t)
-            for (int q = 0; q < 3; ++q) e[3 * t + q] = (int64_t)tris[3 * t + q] * nv + tris[3 * t + (q + 1) % 3];
-        std::sort(e.begin(), e.end());
-        for (size_t i = 0; i < e.size(); ++i) {
-            if (i + 1 < e.size() && e[i + 1] == e[i])
-                return fail(g, IBM_E_GEOMETRY, "mesh is not consistently oriented (directed edge used twice)");
-            int64_t a = e[i] / nv, b = e[i] % nv;
-            if (a == b) return fail(g, IBM_E_GEOMETRY, "degenerate edge");
-            if (!std::binary_search(e.begin(), e.end(), b * nv + a))
-                return fail(g, IBM_E_GEOMETRY, "mesh is not closed (edge without its reverse)");
-        }
+        if (const char *why = mesh_closed_oriented(tris, nt, nv)) return fail(g, IBM_E_GEOMETRY, why);
         g->topo_tris.assign(tris, tris + 3 * nt);
         g->topo_nv = nv;
         g->topo_valid = true;
