@@ -366,13 +366,19 @@ def serving_form(args):
         sweep = []
         for x in (0.5, 0.9, 1.5):
             tr = serve.make_trace(0, qps=x * mu, requests=base)
-            rs, mks = srv.run(tr)
-            rq, mkq = seq.run(tr)
-            sweep.append({"qps": round(x * mu, 3), "load_vs_seq_capacity": x,
-                          "served": serve.summarize(rs, mks), "sequential_fp64": serve.summarize(rq, mkq)})
-            log("serving qps %.2f: served p50 %.1f p99 %.1f ms, sequential p50 %.1f p99 %.1f ms"
-                % (x * mu, sweep[-1]["served"]["p50_ms"], sweep[-1]["served"]["p99_ms"],
-                   sweep[-1]["sequential_fp64"]["p50_ms"], sweep[-1]["sequential_fp64"]["p99_ms"]))
+            point = {"qps": round(x * mu, 3), "load_vs_seq_capacity": x}
+            for name, server in (("served", srv), ("sequential_fp64", seq)):
+                try:
+                    rr, mm = server.run(tr)
+                    point[name] = serve.summarize(rr, mm)
+                except Exception as e:  # a failed request ends this point; it is reported, not retried
+                    point[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+                    log("serving qps %.2f (%s) failed: %s" % (x * mu, name, e))
+            sweep.append(point)
+            if "error" not in point["served"] and "error" not in point["sequential_fp64"]:
+                log("serving qps %.2f: served p50 %.1f p99 %.1f ms, sequential p50 %.1f p99 %.1f ms"
+                    % (x * mu, point["served"]["p50_ms"], point["served"]["p99_ms"],
+                       point["sequential_fp64"]["p50_ms"], point["sequential_fp64"]["p99_ms"]))
         out["qps_sweep"] = sweep
         out["resident_GB"] = round((srv.resident_bytes() + seq.resident_bytes()) / 2 ** 30, 2)
         return out
@@ -509,7 +515,12 @@ def main():
                         "momentum": momentum_form(wl, args),
                         "paper_solver": paper_solver_form(wl, u0, v0, w0, args),
                         "moving": moving_form(wl, args),
-                        "serving": serving_form(args)}
+                        "serving": None}
+        try:
+            out["forms"]["serving"] = serving_form(args)
+        except Exception as e:  # reported in the JSON line; the other forms stand
+            out["forms"]["serving"] = {"error": "%s: %s" % (type(e).__name__, e)}
+            log("serving form failed: %s" % e)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, int(np.median(vcyc)))
