@@ -273,6 +273,19 @@ ibm_status ibm_debug_sweep(ibm_grid *g, double *p, const double *rhs, double lam
 /* (S p) on fluid rows, 0 elsewhere (device in/out). */
 ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stream);
 
+/* Copy one internal FP64 cell field of the workspace ([nz][ny][nx]) to device memory:
+   which 0..9 the Krylov vectors (r, shadow residual, search direction, A y, s, A z,
+   preconditioned search directions y and z in two buffers each), 10 the second pressure
+   buffer, 11 the preconditioner's start iterate, 12 the projection's right-hand side. */
+ibm_status ibm_debug_vector(const ibm_grid *g, int which, double *dst_device, void *stream);
+
+/* Read-before-write check: on != 0 makes every later ibm_bind_workspace of this handle fill
+   each floating-point sub-buffer of the workspace with NaN (all bits set) before it writes
+   anything.  Results on such a handle equal, bit for bit, those on a handle whose
+   workspace held any other content, unless the library reads a value it never wrote.
+   Debug only: costs one device memset per sub-buffer at bind. */
+ibm_status ibm_debug_poison(ibm_grid *g, int on);
+
 /* Timing of the level-0 smoother.  on = 0: off.  on = n >= 1: every n-th fine-level
    red-black sweep (counted from this call) is bracketed by HIP events on its launch stream
    (at most 32 sweeps between two host synchronisations are timed); a stride above one keeps

@@ -323,7 +323,13 @@ ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64
     HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
     Plan P;
     P.base = (char *)device_ptr;
+    std::vector<std::pair<size_t, size_t>> fp_spans;
+    if (g->debug_poison) P.fp_spans = &fp_spans;
     layout(g, P, g->nx, g->ny, g->nz, nv_max, nt_max, max_ghosts, prec, g->lev, g->nlev);
+    // debug: every floating-point sub-buffer starts as NaN (all bits set), so any value the
+    // library reads before writing it propagates into the results
+    for (const auto &sp : fp_spans)
+        HIP_TRY(hipMemsetAsync((char *)device_ptr + sp.first, 0xFF, sp.second, s), "poison");
     g->ws = (char *)device_ptr;
     g->ws_bytes = bytes;
     g->nv_max = nv_max;
@@ -980,6 +986,28 @@ ibm_status ibm_debug_apply(ibm_grid *g, const double *p, double *out, void *stre
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     HIP_TRY(apply0_f64(g, p, out, s), "apply");
     HIP_TRY(hipStreamSynchronize(s), "apply sync");
+    return IBM_OK;
+}
+
+ibm_status ibm_debug_vector(const ibm_grid *gc, int which, double *dst_device, void *stream) {
+    ibm_grid *g = const_cast<ibm_grid *>(gc);
+    if (!g || !dst_device) return fail(g, IBM_E_ARG, "ibm_debug_vector: NULL argument");
+    if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_debug_vector before ibm_bind_workspace");
+    const double *src = nullptr;
+    if (which >= 0 && which < 10) src = g->kv[which];
+    else if (which == 10) src = g->p2;
+    else if (which == 11) src = g->pz;
+    else if (which == 12) src = g->frhs;
+    if (!src) return fail(g, IBM_E_ARG, "ibm_debug_vector: which must be 0..12");
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(dst_device, src, sizeof(double) * g->N, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+            "copy");
+    return IBM_OK;
+}
+
+ibm_status ibm_debug_poison(ibm_grid *g, int on) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_debug_poison: NULL handle");
+    g->debug_poison = on != 0;
     return IBM_OK;
 }
 

@@ -349,7 +349,9 @@ __global__ void __launch_bounds__(ZM_NT)
 // these full fields from displacing cached data measured faster over a whole projection.
 // w = S y on fluid rows, 0 elsewhere, with the sums of ApplySums<DOTS> over the block (the
 // fluid rows' contributions; w is 0 elsewhere).  The loads of plane k+1 are issued before
-// plane k is computed.
+// plane k is computed.  Off the fluid rows o is not read into a sum at all (selected out, not
+// multiplied by the zero image): the shadow residual is never written on dead cells, so its
+// values there are whatever the workspace held, possibly NaN or Inf.
 template <int DOTS>
 __global__ void __launch_bounds__(ZM_NT)
     k_apply_fluid_zm(Fine<double> F, const double *__restrict__ y, double *__restrict__ w,
@@ -404,7 +406,7 @@ __global__ void __launch_bounds__(ZM_NT)
         if (in && k_ < z.k1) {                                                                                     \
             __builtin_nontemporal_store(a, w + (int64_t)k_ * plane + rowoff);                                      \
             if (DOTS == 0 || DOTS == 3) acc[0] += (vxy * (D).wz) * a;                                              \
-            if (DOTS == 1 || DOTS == 2) acc[0] += (D).fv * a;                                                      \
+            if (DOTS == 1 || DOTS == 2) acc[0] += fl ? (D).fv * a : 0.0;                                           \
             if (DOTS == 2) acc[1 % NS] += a * a;                                                                   \
         }                                                                                                          \
         ym1 = yc;                                                                                                  \
@@ -685,11 +687,12 @@ __global__ void __launch_bounds__(ZP_NT)
                            (D).ym.x, (D).yp.x, ym1.x, (D).pp.x, n0, d0);                                           \
         zm_stencil<double>(axm1, axp1, aym, ayp, (D).azm, (D).azp, true, hx1, hy0, hy1, z0_, z1_, yc.x, (D).xp,   \
                            (D).ym.y, (D).yp.y, ym1.y, (D).pp.y, n1, d1);                                           \
-        const double a0 = (in && ((D).tt & 0xff) == T_FLUID)                                                      \
+        const bool f0_ = in && ((D).tt & 0xff) == T_FLUID, f1_ = in && ((D).tt >> 8) == T_FLUID;                  \
+        const double a0 = f0_                                                                                      \
                               ? (DOTS == 3 ? (D).fv.x - (n0 - d0 * yc.x)                                           \
                                            : (DOTS ? (n0 - d0 * yc.x) - mu : n0 - d0 * yc.x))                      \
                               : 0.0;                                                                               \
-        const double a1 = (in && ((D).tt >> 8) == T_FLUID)                                                        \
+        const double a1 = f1_                                                                                      \
                               ? (DOTS == 3 ? (D).fv.y - (n1 - d1 * yc.y)                                           \
                                            : (DOTS ? (n1 - d1 * yc.y) - mu : n1 - d1 * yc.y))                      \
                               : 0.0;                                                                               \
@@ -701,8 +704,8 @@ __global__ void __launch_bounds__(ZP_NT)
                 acc[0] += (vxy1 * (D).wz) * a1;                                                                    \
             }                                                                                                      \
             if (DOTS == 1 || DOTS == 2) {                                                                          \
-                acc[0] += (D).fv.x * a0;                                                                           \
-                acc[0] += (D).fv.y * a1;                                                                           \
+                acc[0] += f0_ ? (D).fv.x * a0 : 0.0;                                                               \
+                acc[0] += f1_ ? (D).fv.y * a1 : 0.0;                                                               \
             }                                                                                                      \
             if (DOTS == 2) {                                                                                       \
                 acc[1 % NS] += a0 * a0;                                                                            \

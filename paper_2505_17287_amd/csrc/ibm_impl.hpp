@@ -16,6 +16,8 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/ibm.h"
@@ -267,6 +269,9 @@ struct ibm_grid {
     double vol_fluid = 0.0;
     ibm::SolveState ss;
     ibm::Prof prof;
+    // debug: fill every floating-point sub-buffer of the workspace with NaN at bind time
+    // (ibm_debug_poison), so a value read before the library wrote it shows up
+    bool debug_poison = false;
 };
 
 namespace ibm {
@@ -275,11 +280,15 @@ namespace ibm {
 struct Plan {
     size_t off = 0;
     char *base = nullptr;
+    // optional: (offset, bytes) of every floating-point sub-buffer, for the poisoned bind
+    std::vector<std::pair<size_t, size_t>> *fp_spans = nullptr;
     template <typename T>
     T *take(int64_t count) {
         off = (off + 255) & ~size_t(255);
         T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+        const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+        if (fp_spans && std::is_floating_point<T>::value) fp_spans->emplace_back(off, bytes);
+        off += bytes;
         return p;
     }
 };

@@ -103,6 +103,8 @@ def lib():
         L.ibm_get_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
         L.ibm_debug_sweep.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp]
         L.ibm_debug_apply.argtypes = [vp, vp, vp, vp]
+        L.ibm_debug_poison.argtypes = [vp, C.c_int]
+        L.ibm_debug_vector.argtypes = [vp, C.c_int, vp, vp]
         L.ibm_set_profiling.argtypes = [vp, C.c_int]
         L.ibm_get_profile.argtypes = [vp, vp, vp, vp, vp]
         L.ibm_set_profiling.restype = C.c_int
@@ -122,7 +124,7 @@ def lib():
                      "ibm_build_ghost_stencils", "ibm_get_ghosts", "ibm_set_neumann_data", "ibm_get_cell_types",
                      "ibm_poisson_solve", "ibm_project", "ibm_solve_begin", "ibm_solve_step", "ibm_solve_poll",
                      "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply", "ibm_srj_schedule",
-                     "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step",
+                     "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step", "ibm_debug_poison", "ibm_debug_vector",
                      "ibm_move_geometry", "ibm_fill_fresh", "ibm_get_fresh"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -194,7 +196,9 @@ def estimate_max_ghosts(xf, yf, zf, verts, tris):
 class Grid:
     """One problem: grid + body + workspace (a torch uint8 tensor on the device)."""
 
-    def __init__(self, xf, yf, zf, precision="fp64", device="cuda:0", stream=None):
+    def __init__(self, xf, yf, zf, precision="fp64", device="cuda:0", stream=None, poison=False):
+        """poison: every floating-point sub-buffer of each workspace bound to this grid starts
+        as NaN (ibm_debug_poison), a read-before-write check."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -208,6 +212,8 @@ class Grid:
         self._check(lib().ibm_create_grid(self.nx, self.ny, self.nz, _dp(self.xf), _dp(self.yf), _dp(self.zf),
                                           C.byref(h)), None)
         self._h = h
+        if poison:
+            self._check(lib().ibm_debug_poison(h, 1))
         self.ws = None
         self.ng = 0
         self.nfresh = 0
@@ -480,6 +486,14 @@ class Grid:
             self._check(lib().ibm_debug_sweep(self._h, _tptr(p), _tptr(rhs), float(lam), int(n), int(refresh),
                                               self._s()))
         return p
+
+    def debug_vector(self, which):
+        """Device copy of an internal FP64 cell field (see ibm_debug_vector)."""
+        out = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_debug_vector(self._h, int(which), _tptr(out), self._s()))
+            self.torch.cuda.current_stream(self.device).synchronize() if self.stream is None else self.stream.synchronize()
+        return out
 
     def debug_apply(self, p):
         out = self.torch.empty_like(p)
