@@ -128,7 +128,10 @@ ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const 
 /* Classify every cell (Section 2.2, ray tracing): a cell is solid when its centre lies
    strictly inside the body by the parity of crossings of the +z ray through the column
    centre; ghost = solid with a fluid cell among its 26 neighbours; dead = other solid.
-   counts_out[3] (host) receives the fluid, ghost and dead counts.  Synchronises `stream`. */
+   counts_out[3] (host) receives the fluid, ghost and dead counts.  A column whose ray
+   crosses the surface an odd number of times (impossible for a closed mesh under the
+   edge-ownership rule, so a broken mesh or predicate) -> IBM_E_GEOMETRY with the count in
+   the message; the classification is then not usable.  Synchronises `stream`. */
 ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]);
 
 /* Build the ghost-cell stencils (Section 2.2, Eq. 2 and 3): body intercept = closest mesh

@@ -340,7 +340,7 @@ int orc_classify(orc_problem *P, int64_t counts[3]) {
                     int64_t b = cnt[q], n = cnt[q + 1] - cnt[q];
                     if (n == 0) continue;
                     qsort(zs + b, (size_t)n, sizeof(double), cmp_double);
-                    if (n % 2) { odd++; n -= 1; } /* an unpaired crossing is ignored */
+                    if (n % 2) { odd++; n -= 1; } /* counted: the call fails below */
                     int i = (int)(q % nx), j = (int)(q / nx);
                     for (int k = 0; k < nz; ++k) {
                         double z = P->zc[k];
@@ -380,6 +380,10 @@ int orc_classify(orc_problem *P, int64_t counts[3]) {
     free_stencils(P);
     free_hierarchy(P);
     if (counts) { counts[0] = nf; counts[1] = ng; counts[2] = nd; }
+    /* a closed, consistently oriented mesh crosses every column ray an even number of
+       times under the edge-ownership rule; an odd count means a broken mesh or predicate,
+       and the classification is refused (the types stay readable for inspection) */
+    if (odd) return ORC_E_GEOMETRY;
     return ORC_OK;
 }
 

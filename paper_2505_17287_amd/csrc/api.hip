@@ -54,6 +54,8 @@ bool finite_increasing(const double *f, int n) {
 
 namespace ibm {
 
+ibm_status report_error(ibm_status st, const std::string &msg) { return fail(nullptr, st, msg); }
+
 // Semi-coarsening plan: an axis is coarsenable when its count is even and >= 4; among the
 // coarsenable axes, those whose smallest width is below 1.5x the smallest width of any
 // coarsenable axis are halved.  Coarse faces are every other fine face.
@@ -466,9 +468,13 @@ ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
         return fail(g, IBM_E_NOMEM, "ghost cells " + std::to_string(c[1]) + " exceed the bound capacity " +
                                         std::to_string(g->ghost_max));
     }
+    if (odd) {
+        g->stage = ST_GEOMETRY;
+        return fail(g, IBM_E_GEOMETRY, std::to_string(odd) +
+                                           " columns with an odd number of ray crossings (mesh not watertight)");
+    }
     if (c[0] == 0) return fail(g, IBM_E_GEOMETRY, "no fluid cell");
     g->ng = c[1];
-    (void)odd;
     g->stage = ST_CLASSIFIED;
     return IBM_OK;
 }

@@ -582,42 +582,90 @@ __global__ void __launch_bounds__(CMP_NT) k_ghost_write(const uint8_t *__restric
     }
 }
 
-hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const int64_t ncol = (int64_t)nx * ny, N = g->N;
+// zero n 32-bit words (a kernel rather than a memset, so the no-allocation entry point that
+// shares this path stays capturable in a HIP graph)
+__global__ void k_clear_words(uint32_t *p, int64_t n) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) p[id] = 0u;
+}
+
+static hipError_t clear_words(void *p, int64_t bytes, hipStream_t s) {
+    const int64_t n = bytes / 4;
+    hipLaunchKernelGGL(k_clear_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+int64_t classify_mark16_parts(int nx, int ny, int nz) {
+    if (nx % 16 != 0) return 0;
+    const int64_t nseg = (int64_t)nx * ny * nz / 16;
+    return 3 * ((nseg + MARK16_NT - 1) / MARK16_NT);
+}
+
+int64_t classify_scan_blocks(int64_t n) { return (n + SCAN_CH - 1) / SCAN_CH + 1; }
+
+// cell types of every cell and counters[0..4] = fluid, ghost, dead, odd columns, crossing
+// overflow; every buffer is the caller's (a handle's workspace or the static scratch)
+hipError_t launch_classify_cells(const ClassifyBufs &B, hipStream_t s) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int64_t ncol = (int64_t)nx * ny, N = ncol * nz;
     hipError_t e;
-    e = hipMemsetAsync(g->counters, 0, sizeof(int64_t) * 8, s);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(g->col_cnt, 0, sizeof(int32_t) * (ncol + 1), s);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(g->col_fill, 0, sizeof(int32_t) * (ncol + 1), s);
-    if (e != hipSuccess) return e;
-    if (g->nt > 0) {
-        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((g->nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, g->verts,
-                           g->tris, g->nt, g->c0[0], g->c0[1], nx, ny, g->col_cnt, nullptr, nullptr, nullptr, (int64_t)0,
-                           nullptr);
+    if ((e = clear_words(B.counters, sizeof(int64_t) * 8, s)) != hipSuccess) return e;
+    if ((e = clear_words(B.col_cnt, sizeof(int32_t) * (ncol + 1), s)) != hipSuccess) return e;
+    if ((e = clear_words(B.col_fill, sizeof(int32_t) * (ncol + 1), s)) != hipSuccess) return e;
+    if (B.nt > 0) {
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((B.nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, B.verts,
+                           B.tris, B.nt, B.xc, B.yc, nx, ny, B.col_cnt, nullptr, nullptr, nullptr, (int64_t)0, nullptr);
     }
-    e = scan_counts(g->col_cnt, g->col_off, ncol + 1, (int64_t *)g->blk_cnt, s);
+    e = scan_counts(B.col_cnt, B.col_off, ncol + 1, B.blk, s);
     if (e != hipSuccess) return e;
-    if (g->nt > 0) {
-        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((g->nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, g->verts,
-                           g->tris, g->nt, g->c0[0], g->c0[1], nx, ny, nullptr, g->col_off, g->col_fill, g->crossings,
-                           g->cross_cap, g->counters + 4);
+    if (B.nt > 0) {
+        hipLaunchKernelGGL(k_col_pass, dim3((unsigned)((B.nt + COL_NT - 1) / COL_NT)), dim3(COL_NT), 0, s, B.verts,
+                           B.tris, B.nt, B.xc, B.yc, nx, ny, nullptr, B.col_off, B.col_fill, B.crossings, B.cross_cap,
+                           B.counters + 4);
     }
-    hipLaunchKernelGGL(k_col_sort, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
-                       (int64_t)ncol, g->counters + 3, g->cross_cap);
-    hipLaunchKernelGGL(k_col_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g->col_off, g->crossings,
-                       g->c0[2], (int64_t)ncol, N, g->type, g->cross_cap);
+    hipLaunchKernelGGL(k_col_sort, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, s, B.col_off, B.crossings,
+                       (int64_t)ncol, B.counters + 3, B.cross_cap);
+    hipLaunchKernelGGL(k_col_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, B.col_off, B.crossings, B.zc,
+                       (int64_t)ncol, N, B.type, B.cross_cap);
     if (nx % 16 == 0) {
-        // per-block counts go to the reduction partials (3 per block <= N / 256 + 1024 entries)
         const int64_t nseg = N / 16, nblk = (nseg + MARK16_NT - 1) / MARK16_NT;
-        int64_t *part = reinterpret_cast<int64_t *>(g->partials);
-        hipLaunchKernelGGL(k_mark_ghosts16, dim3((unsigned)nblk), dim3(MARK16_NT), 0, s, g->type, nx, ny, nz, nseg, part);
-        hipLaunchKernelGGL(k_sum_counts3, dim3(1), dim3(SUM3_NT), 0, s, (const int64_t *)part, nblk, g->counters);
+        hipLaunchKernelGGL(k_mark_ghosts16, dim3((unsigned)nblk), dim3(MARK16_NT), 0, s, B.type, nx, ny, nz, nseg,
+                           B.mark_parts);
+        hipLaunchKernelGGL(k_sum_counts3, dim3(1), dim3(SUM3_NT), 0, s, (const int64_t *)B.mark_parts, nblk,
+                           B.counters);
     } else {
         hipLaunchKernelGGL(k_mark_ghosts, dim3((unsigned)std::min<int64_t>((N + MARK_NT - 1) / MARK_NT, MARK_BLOCKS)),
-                           dim3(MARK_NT), 0, s, g->type, nx, ny, nz, g->counters);
+                           dim3(MARK_NT), 0, s, B.type, nx, ny, nz, B.counters);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(ibm_grid *g, hipStream_t s, int64_t counts[4]) {
+    const int nx = g->nx, ny = g->ny;
+    const int64_t N = g->N;
+    ClassifyBufs B;
+    B.nx = nx;
+    B.ny = ny;
+    B.nz = g->nz;
+    B.verts = g->verts;
+    B.tris = g->tris;
+    B.nt = g->nt;
+    B.xc = g->c0[0];
+    B.yc = g->c0[1];
+    B.zc = g->c0[2];
+    B.col_cnt = g->col_cnt;
+    B.col_off = g->col_off;
+    B.col_fill = g->col_fill;
+    B.crossings = g->crossings;
+    B.cross_cap = g->cross_cap;
+    B.counters = g->counters;
+    B.blk = (int64_t *)g->blk_cnt;
+    // per-block counts of the 16-cell ghost marking go to the reduction partials
+    // (3 per block <= N / 256 + 1024 entries)
+    B.mark_parts = reinterpret_cast<int64_t *>(g->partials);
+    B.type = g->type;
+    hipError_t e = launch_classify_cells(B, s);
+    if (e != hipSuccess) return e;
     int64_t nb = (N + CMP_CH - 1) / CMP_CH;
     int32_t *blkc = g->col_cnt;  // reuse: ncol+1 >= nb is guaranteed by the layout
     int32_t *blko = g->col_fill;

@@ -299,6 +299,29 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
 size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t gmax,
               ibm_precision prec, LevelHost *lev, int nlev);
 
+// classification buffers (geometry.hip): a handle's workspace or the static scratch of the
+// no-allocation entry point
+struct ClassifyBufs {
+    int nx, ny, nz;
+    const double *verts;
+    const int32_t *tris;
+    int64_t nt;
+    const double *xc, *yc, *zc;           // cell centres per axis
+    int32_t *col_cnt, *col_off, *col_fill;  // ncol + 1 each
+    double *crossings;
+    int64_t cross_cap;
+    int64_t *counters;                    // 8
+    int64_t *blk;                         // classify_scan_blocks(ncol + 1)
+    int64_t *mark_parts;                  // classify_mark16_parts(nx, ny, nz)
+    uint8_t *type;
+};
+hipError_t launch_classify_cells(const ClassifyBufs &B, hipStream_t s);
+int64_t classify_mark16_parts(int nx, int ny, int nz);
+int64_t classify_scan_blocks(int64_t n);
+
+// error reporting shared by the entry points (api.hip): sets the thread's last error
+ibm_status report_error(ibm_status st, const std::string &msg);
+
 // kernel launchers (geometry.hip)
 hipError_t launch_metrics(ibm_grid *g, hipStream_t s);
 hipError_t launch_buckets(ibm_grid *g, hipStream_t s);
