@@ -134,6 +134,31 @@ ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const 
    the message; the classification is then not usable.  Synchronises `stream`. */
 ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]);
 
+/* ---- classification without a handle: for callers that cannot allocate ---------------
+   For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc) and have no handle or workspace: the
+   classification of ibm_classify (the same kernels, the same types and counts), with every
+   intermediate buffer in a fixed array of IBM_NOALLOC_SCRATCH_MB MiB of device memory that
+   the library holds per GPU from its first use until the process ends.  It calls no
+   hipMalloc, hipFree or other allocating routine.
+     xf[nx+1], yf[ny+1], zf[nz+1]: device, FP64 face coordinates (strictly increasing: not
+       checked, the data stay on the device);
+     verts[nv][3] FP64, tris[nt][3] int32: device, a closed, consistently oriented mesh (not
+       checked: ibm_set_geometry's check needs the mesh on the host);
+     type_out[nz][ny][nx]: device, uint8 out (0 fluid, 1 ghost, 2 dead);
+     counts_out[3]: host out, fluid, ghost and dead counts.
+   Errors: IBM_E_ARG for sizes below 2 x 2 x 1, 2^31 cells or more, NULL pointers or an
+   empty mesh; IBM_E_NOMEM when the columns do not fit the scratch (about 1.8 million
+   columns at 64 MiB) or the ray crossings overflow it; IBM_E_GEOMETRY when a column has an
+   odd number of crossings (type_out is then not valid) or no cell is fluid.  Synchronises
+   `stream`.  Every call on one GPU uses that GPU's one scratch array: calls that overlap on
+   a GPU (several host threads or streams at once) race and must be serialised by the
+   caller. */
+#define IBM_NOALLOC_SCRATCH_MB 64
+ibm_status ibm_classify_noalloc(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                                const double *verts, int64_t nv, const int32_t *tris, int64_t nt, uint8_t *type_out,
+                                int64_t counts_out[3], void *stream);
+
 /* Build the ghost-cell stencils (Section 2.2, Eq. 2 and 3): body intercept = closest mesh
    point, normal, image point = mirror of the ghost centre through the intercept, the 8 (2D:
    4) cells around the image point and the weights of Eq. 2 with the Neumann condition in

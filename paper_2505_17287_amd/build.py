@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibm.so")
-SOURCES = ["geometry.hip", "sweep.hip", "sweepc.hip", "finepass.hip", "solver.hip", "momentum.hip", "api.hip"]
+SOURCES = ["geometry.hip", "sweep.hip", "sweepc.hip", "finepass.hip", "solver.hip", "momentum.hip", "noalloc.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

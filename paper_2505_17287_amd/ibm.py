@@ -91,6 +91,7 @@ def lib():
         L.ibm_bind_workspace.argtypes = [vp, vp, C.c_size_t, i64, i64, i64, C.c_int, vp]
         L.ibm_set_geometry.argtypes = [vp, dp, i64, vp, i64, vp]
         L.ibm_classify.argtypes = [vp, vp, vp]
+        L.ibm_classify_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, i64, vp, i64, vp, vp, vp]
         L.ibm_build_ghost_stencils.argtypes = [vp, vp, vp]
         L.ibm_get_ghosts.argtypes = [vp, vp] + [vp] * 7
         L.ibm_set_neumann_data.argtypes = [vp, vp, vp]
@@ -125,6 +126,7 @@ def lib():
                      "ibm_poisson_solve", "ibm_project", "ibm_solve_begin", "ibm_solve_step", "ibm_solve_poll",
                      "ibm_get_levels", "ibm_debug_sweep", "ibm_debug_apply", "ibm_srj_schedule",
                      "ibm_set_dirichlet_data", "ibm_get_dirichlet_weights", "ibm_momentum_step", "ibm_debug_poison", "ibm_debug_vector",
+                     "ibm_classify_noalloc",
                      "ibm_move_geometry", "ibm_fill_fresh", "ibm_get_fresh"):
             getattr(L, name).restype = C.c_int
         _lib = L

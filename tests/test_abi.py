@@ -100,3 +100,20 @@ def test_srj_schedule_host_call():
     for rho, m in ((1.0, 4), (-0.1, 4), (0.5, 0), (0.5, ibm.IBM_SRJ_MAX + 1)):
         with pytest.raises(ibm.IBMError):
             ibm.srj_schedule(rho, m)
+
+
+def test_classify_noalloc_rejects_sizes_beyond_its_scratch():
+    """Argument and size checks of the no-allocation classification run on the host before
+    any device work: too many columns for the fixed scratch, too many cells, empty meshes."""
+    L = ibm.lib()
+    dummy = np.zeros(16)
+    p = C.c_void_p(dummy.ctypes.data)
+    counts = np.zeros(3, np.int64)
+    cp = C.c_void_p(counts.ctypes.data)
+    # 4096 x 4096 columns need 16.8M column counters: beyond the fixed scratch
+    assert L.ibm_classify_noalloc(4096, 4096, 1, p, p, p, p, 3, p, 1, p, cp, None) == ibm.IBM_E_NOMEM
+    assert b"scratch" in L.ibm_last_error(None)
+    assert L.ibm_classify_noalloc(2048, 2048, 1024, p, p, p, p, 3, p, 1, p, cp, None) == ibm.IBM_E_ARG
+    assert L.ibm_classify_noalloc(8, 8, 8, p, p, p, p, 2, p, 1, p, cp, None) == ibm.IBM_E_ARG
+    assert L.ibm_classify_noalloc(8, 8, 8, p, p, p, None, 3, p, 1, p, cp, None) == ibm.IBM_E_ARG
+    assert L.ibm_classify_noalloc(1, 8, 8, p, p, p, p, 3, p, 1, p, cp, None) == ibm.IBM_E_ARG
