@@ -282,12 +282,14 @@ static int ray_cross(const double *V, const int32_t *tri, double px, double py, 
     int in_ca = (wca > 0.0) || (wca == 0.0 && top_left(V, c, a));
     if (!(in_ab && in_bc && in_ca)) return 0;
     /* barycentric interpolation of z: the weight of a vertex is the edge function of the
-       opposite edge */
-    double num = wbc * V[3 * a + 2] + wca * V[3 * b + 2];
-    num = num + wab * V[3 * c + 2];
+       opposite edge; written relative to vertex a, so a horizontal facet gives its height
+       exactly (a centre on it then lies on the crossing and stays fluid) */
+    double za = V[3 * a + 2];
+    double num = wca * (V[3 * b + 2] - za);
+    num = num + wab * (V[3 * c + 2] - za);
     double den = wbc + wca;
     den = den + wab;
-    *zout = num / den;
+    *zout = za + num / den;
     return 1;
 }
 
@@ -573,7 +575,8 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
         double dist = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
         double hloc = fmin(P->wx[i], P->wy[j]);
         if (!two_d) hloc = fmin(hloc, P->wz[k]);
-        if (dist <= 1e-12 * hloc) {
+        const int on_surface = dist <= 1e-12 * hloc;
+        if (on_surface) {
             const int32_t *tri = P->tris + 3 * t;
             const double *a = P->verts + 3 * tri[0], *b = P->verts + 3 * tri[1], *c = P->verts + 3 * tri[2];
             double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
@@ -582,6 +585,9 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
             double ln = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
             for (int d = 0; d < 3; ++d) nrm[d] = nn[d] / ln;
             flags |= GF_NFALLBACK;
+            /* the ghost centre is on the surface: it is its own intercept and image point */
+            for (int d = 0; d < 3; ++d) bi[d] = xg[d];
+            dist = 0.0;
         } else {
             for (int d = 0; d < 3; ++d) nrm[d] = dvec[d] / dist;
         }
@@ -589,10 +595,22 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
         for (int d = 0; d < 3; ++d) ip[d] = (bi[d] + bi[d]) - xg[d];
         double dl = dist + dist;
         P->gdl[g] = dl;
-        /* interpolation box */
-        int i0 = P->nx > 1 ? box_lo(P->xc, P->nx, ip[0]) : 0;
-        int j0 = P->ny > 1 ? box_lo(P->yc, P->ny, ip[1]) : 0;
-        int k0 = P->nz > 1 ? box_lo(P->zc, P->nz, ip[2]) : 0;
+        /* interpolation box: around the image point; for a ghost on the surface (image point
+           = the centre itself) the cells on the side the normal points to, so its equation is
+           the one-sided normal difference into the fluid */
+        int i0, j0, k0;
+        if (on_surface) {
+            i0 = nrm[0] >= 0.0 ? i : i - 1;
+            j0 = nrm[1] >= 0.0 ? j : j - 1;
+            k0 = nrm[2] >= 0.0 ? k : k - 1;
+            i0 = i0 < 0 ? 0 : (i0 > P->nx - 2 ? P->nx - 2 : i0);
+            j0 = j0 < 0 ? 0 : (j0 > P->ny - 2 ? P->ny - 2 : j0);
+            k0 = two_d ? 0 : (k0 < 0 ? 0 : (k0 > P->nz - 2 ? P->nz - 2 : k0));
+        } else {
+            i0 = P->nx > 1 ? box_lo(P->xc, P->nx, ip[0]) : 0;
+            j0 = P->ny > 1 ? box_lo(P->yc, P->ny, ip[1]) : 0;
+            k0 = P->nz > 1 ? box_lo(P->zc, P->nz, ip[2]) : 0;
+        }
         double hx = P->xc[i0 + 1] - P->xc[i0], hy = P->yc[j0 + 1] - P->yc[j0];
         double hz = two_d ? 1.0 : P->zc[k0 + 1] - P->zc[k0];
         int cl = 0;
@@ -615,7 +633,24 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
         double *beta = P->gbeta + 8 * g;
         for (int m = 0; m < 8; ++m) { st[m] = -1; beta[m] = 0.0; }
         P->gbetag[g] = 0.0;
-        if (ndead > 0 || nfluid == 0) {
+        /* local coordinates of the body intercept in the box */
+        double lbx = (bi[0] - P->xc[i0]) / hx, lby = (bi[1] - P->yc[j0]) / hy;
+        double lbz = two_d ? 0.0 : (bi[2] - P->zc[k0]) / hz;
+        /* The Neumann row replaces the ghost's own value only when the derivative of the
+           ghost's own trilinear hat function along n at the intercept is negative, that is
+           when the one-sided difference points from the ghost into its box (always so for a
+           mirrored image point, whose box holds the intercept); otherwise the row is
+           degenerate. */
+        int bad_row = 0;
+        if (self >= 0) {
+            int sa = self & 1, sb = (self >> 1) & 1, sc = (self >> 2) & 1;
+            double fx = sa ? lbx : 1.0 - lbx, fy = sb ? lby : 1.0 - lby, fz = sc ? lbz : 1.0 - lbz;
+            double dnx = (sa ? 1.0 : -1.0) / hx, dny = (sb ? 1.0 : -1.0) / hy, dnz = (sc ? 1.0 : -1.0) / hz;
+            double dn = two_d ? nrm[0] * dnx * fy + nrm[1] * dny * fx
+                              : (nrm[0] * dnx * (fy * fz) + nrm[1] * dny * (fx * fz)) + nrm[2] * dnz * (fx * fy);
+            if (!(dn < 0.0)) bad_row = 1;
+        }
+        if (ndead > 0 || nfluid == 0 || bad_row) {
             flags |= GF_DEGENERATE;
             P->gflags[g] = flags;
             continue;
@@ -625,8 +660,6 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
            intercept.  The weights of Eq. 2 are beta = V^{-T} b(image point). */
         double A[64], rhs[8];
         double bx[8], by[8], bz[8];
-        double lbx = (bi[0] - P->xc[i0]) / hx, lby = (bi[1] - P->yc[j0]) / hy;
-        double lbz = two_d ? 0.0 : (bi[2] - P->zc[k0]) / hz;
         for (int m = 0; m < nm; ++m) {
             double row[8];
             int a = m & 1, b = (m >> 1) & 1, c = (m >> 2) & 1;
@@ -661,7 +694,9 @@ int orc_build_stencils(orc_problem *P, int64_t *ng_out) {
     }
     if (err) { free_stencils(P); return ORC_E_GEOMETRY; }
     for (int64_t g = 0; g < ng; ++g) P->gdata[g] = 0.0;
-    for (int64_t g = 0; g < ng; ++g) P->gh[g] = (P->gbetag[g] - P->gdl[g]) * P->gdata[g];
+    /* a degenerate ghost's equation (mean of its fluid neighbours) carries no Neumann term */
+    for (int64_t g = 0; g < ng; ++g)
+        P->gh[g] = (P->gflags[g] & GF_DEGENERATE) ? 0.0 : (P->gbetag[g] - P->gdl[g]) * P->gdata[g];
     P->stencils = 1;
     free_hierarchy(P);
     if (ng_out) *ng_out = ng;
@@ -674,7 +709,7 @@ int orc_set_neumann(orc_problem *P, const double *g) {
     for (int64_t q = 0; q < P->nghost; ++q) {
         P->gdata[q] = g ? g[q] : 0.0;
         /* ghost row: p_g - sum_{m != g} beta_m p_m = (beta_g - dl) * g_BI */
-        P->gh[q] = (P->gbetag[q] - P->gdl[q]) * P->gdata[q];
+        P->gh[q] = (P->gflags[q] & GF_DEGENERATE) ? 0.0 : (P->gbetag[q] - P->gdl[q]) * P->gdata[q];
     }
     return ORC_OK;
 }

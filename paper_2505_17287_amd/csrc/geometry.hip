@@ -269,12 +269,14 @@ __device__ __forceinline__ bool ray_hits(const double *V, const int32_t *tri, do
     bool in = ((wab > 0.0) || (wab == 0.0 && owns_edge(V, a, b))) && ((wbc > 0.0) || (wbc == 0.0 && owns_edge(V, b, c))) &&
               ((wca > 0.0) || (wca == 0.0 && owns_edge(V, c, a)));
     if (!in) return false;
-    // barycentric z: each vertex weighted by the edge function of the opposite edge
-    double num = wbc * V[3 * a + 2] + wca * V[3 * b + 2];
-    num = num + wab * V[3 * c + 2];
+    // barycentric z: each vertex weighted by the edge function of the opposite edge, written
+    // relative to vertex a so that a horizontal facet gives its height exactly
+    const double za = V[3 * a + 2];
+    double num = wca * (V[3 * b + 2] - za);
+    num = num + wab * (V[3 * c + 2] - za);
     double den = wbc + wca;
     den = den + wab;
-    *z = num / den;
+    *z = za + num / den;
     return true;
 }
 
@@ -881,14 +883,16 @@ __global__ void __launch_bounds__(64 * CLOSEST_WAVES)
 //     no Neumann row:  beta_m = L_m(IP)
 //     ghost g in box:  beta_g = L_g(IP) / dL_g/dn(BI)
 //                      beta_m = L_m(IP) - dL_m/dn(BI) * beta_g      (m != g)
-// dL_g/dn(BI) < 0 strictly for a mirror image point, so the form is always defined.
+// dL_g/dn(BI) < 0 strictly for a mirror image point, so the form is defined; a ghost whose
+// row would not satisfy it (on the surface next to a wall, where the box cannot lie on the
+// normal's side) is degenerate.
 // ---------------------------------------------------------------------------------------
 
 __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx, int ny, int nz,
                           const double *__restrict__ xc, const double *__restrict__ yc, const double *__restrict__ zc,
                           const double *__restrict__ wx, const double *__restrict__ wy, const double *__restrict__ wz,
                           const uint8_t *__restrict__ type, const double *__restrict__ V, const int32_t *__restrict__ T,
-                          const double *__restrict__ gbi, const int32_t *__restrict__ gtri, double *gn, double *gip,
+                          double *gbi, const int32_t *__restrict__ gtri, double *gn, double *gip,
                           double *gdl, int32_t *gst, uint8_t *gmask, double *gbeta, double *gbetag, int32_t *gflags,
                           int64_t *ndegen, double *gbetaD, double *gbetaDg) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -905,7 +909,8 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
     if (!two_d) hloc = fmin(hloc, wz[k]);
     int flags = 0;
     double n[3];
-    if (dist <= 1e-12 * hloc) {
+    const bool on_surface = dist <= 1e-12 * hloc;
+    if (on_surface) {
         const int32_t *tri = T + 3 * (int64_t)gtri[g];
         double u[3], v[3];
         for (int d = 0; d < 3; ++d) {
@@ -917,6 +922,12 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         double ln = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
         for (int d = 0; d < 3; ++d) n[d] = nn[d] / ln;
         flags |= GF_NFALLBACK;
+        // the centre is on the surface: it is its own intercept (and image point)
+        for (int d = 0; d < 3; ++d) {
+            bi[d] = xg[d];
+            gbi[3 * g + d] = xg[d];
+        }
+        dist = 0.0;
     } else {
         for (int d = 0; d < 3; ++d) n[d] = dv[d] / dist;
     }
@@ -928,9 +939,18 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
         gip[3 * g + d] = ip[d];
     }
     gdl[g] = dl;
-    int i0 = box_lo(xc, nx, ip[0]);
-    int j0 = box_lo(yc, ny, ip[1]);
-    int k0 = two_d ? 0 : box_lo(zc, nz, ip[2]);
+    // box around the image point; on the surface, the cells on the side the normal points to
+    // (the ghost's row is then the one-sided normal difference into the fluid)
+    int i0, j0, k0;
+    if (on_surface) {
+        i0 = min(max(n[0] >= 0.0 ? i : i - 1, 0), nx - 2);
+        j0 = min(max(n[1] >= 0.0 ? j : j - 1, 0), ny - 2);
+        k0 = two_d ? 0 : min(max(n[2] >= 0.0 ? k : k - 1, 0), nz - 2);
+    } else {
+        i0 = box_lo(xc, nx, ip[0]);
+        j0 = box_lo(yc, ny, ip[1]);
+        k0 = two_d ? 0 : box_lo(zc, nz, ip[2]);
+    }
     double hx = xc[i0 + 1] - xc[i0], hy = yc[j0 + 1] - yc[j0];
     double hz = two_d ? 1.0 : zc[k0 + 1] - zc[k0];
     double s[3], bl[3];
@@ -1047,11 +1067,13 @@ __global__ void k_weights(int64_t ng, const int32_t *__restrict__ gcell, int nx,
     gflags[g] = flags;
 }
 
-__global__ void k_ghost_h(int64_t ng, const double *betag, const double *dl, const double *data, double *h) {
+__global__ void k_ghost_h(int64_t ng, const double *betag, const double *dl, const double *data,
+                          const int32_t *flags, double *h) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
-    // ghost equation: p_g - sum_{m != g} beta_m p_m = (beta_g - dl) * dp/dn(BI)
-    h[g] = (betag[g] - dl[g]) * data[g];
+    // ghost equation: p_g - sum_{m != g} beta_m p_m = (beta_g - dl) * dp/dn(BI); a degenerate
+    // ghost's equation (mean of its fluid neighbours) carries no Neumann term
+    h[g] = (flags[g] & GF_DEGENERATE) ? 0.0 : (betag[g] - dl[g]) * data[g];
 }
 
 hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
@@ -1076,7 +1098,7 @@ hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
 hipError_t launch_ghost_h(ibm_grid *g, hipStream_t s) {
     if (g->ng == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ghost_h, dim3((unsigned)((g->ng + 255) / 256)), dim3(256), 0, s, g->ng, g->g_betag, g->g_dl,
-                       g->g_data, g->g_h);
+                       g->g_data, g->g_flags, g->g_h);
     return hipGetLastError();
 }
 

@@ -399,6 +399,97 @@ def sphere_small(n: int = 8, radius: float = 0.3, center=(0.07, -0.04, 0.03), le
     return Workload("sphere%d" % n, f, f.copy(), f.copy(), v, t, seed=7)
 
 
+# ----------------------------------------------------------------------------------------
+# constructed edge cases: bodies placed on the grid so that every special branch of the
+# classification and of the ghost stencils is taken (uniform n^3 grid on [-1, 1]^3, n even,
+# so cell centres -1 + (i + 1/2) h are exact binary fractions)
+# ----------------------------------------------------------------------------------------
+
+
+def aabb_mesh(lo, hi):
+    """Axis-aligned box with exactly the given corner coordinates (12 outward triangles)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    corners = np.array([[(hi if (v >> d) & 1 else lo)[d] for d in range(3)] for v in range(8)], dtype=np.float64)
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    tris = [t for a, b, c, d in quads for t in ((a, b, c), (a, c, d))]
+    return corners, np.asarray(tris, dtype=np.int32)
+
+
+def convex_hull_mesh(verts, faces):
+    """The given triangles of a convex polyhedron, each reordered to face outward (away from
+    the vertex centroid)."""
+    v = np.asarray(verts, dtype=np.float64)
+    c = v.mean(axis=0)
+    out = []
+    for a, b, d in faces:
+        nrm = np.cross(v[b] - v[a], v[d] - v[a])
+        out.append((a, b, d) if np.dot(nrm, v[a] - c) > 0 else (a, d, b))
+    return v, np.asarray(out, dtype=np.int32)
+
+
+def _centres(n):
+    h = 2.0 / n
+    return h, -1.0 + h * (np.arange(n) + 0.5)
+
+
+def edge_slot(n: int = 32) -> Workload:
+    """Two boxes separated by a slot narrower than a cell (no cell centre in it), so the
+    image points of the ghost cells along the slot mouth fall into solid boxes (degenerate
+    ghosts); the left box ends 0.7 h from the x = -1 wall, so the image points of its wall-side
+    ghosts lie beyond the outermost cell centre (clamped)."""
+    h, _ = _centres(n)
+    ylo, yhi, zlo, zhi = -1.0 + 2.3 * h, 1.0 - 3.4 * h, -1.0 + 2.6 * h, 1.0 - 2.2 * h
+    a = aabb_mesh((-1.0 + 0.7 * h, ylo, zlo), (-0.32 * h, yhi, zhi))
+    b = aabb_mesh((0.32 * h, ylo, zlo), (1.0 - 1.7 * h, yhi, zhi))
+    v, t = merge_meshes([a, b])
+    f = uniform_faces(-1.0, 1.0, n)
+    return Workload("edge_slot_%d" % n, f, f.copy(), f.copy(), v, t, seed=11)
+
+
+def edge_aligned(n: int = 32) -> Workload:
+    """Boxes whose faces pass exactly through cell centres: box 1 its x and z faces, box 2 its
+    y faces (the others between centres).  Centres on the surface are classified by the
+    edge-ownership rule (x and y faces) and the open crossing interval (z faces); the ghosts
+    on the surface take the facet normal."""
+    h, c = _centres(n)
+
+    def at(k32):  # the cell centre at k/32 of the grid
+        return c[int(k32 * n) // 32]
+
+    b1 = aabb_mesh((at(6), -1.0 + 0.29 * 2.0 + 0.3 * h, at(10)), (at(20), 1.0 - 0.27 * 2.0 - 0.4 * h, at(21)))
+    b2 = aabb_mesh((1.0 - 0.23 * 2.0 - 0.4 * h, at(7), -1.0 + 0.3 * 2.0 + 0.3 * h),
+                   (1.0 - 0.07 * 2.0 - 0.3 * h, at(23), 1.0 - 0.32 * 2.0 - 0.2 * h))
+    v, t = merge_meshes([b1, b2])
+    f = uniform_faces(-1.0, 1.0, n)
+    return Workload("edge_aligned_%d" % n, f, f.copy(), f.copy(), v, t, seed=12)
+
+
+def edge_vertices(n: int = 32) -> Workload:
+    """An octahedron and a tetrahedron whose vertices lie on column centres (x_i, y_j), with
+    z between centres, so column rays pass exactly through vertices and along projected
+    edges."""
+    h, c = _centres(n)
+
+    def at(k32):
+        return c[int(k32 * n) // 32]
+
+    i0, j0 = int(10 * n) // 32, int(9 * n) // 32
+    m = max(2, int(6 * n) // 32)  # equatorial half-width in cells
+    xo, yo, zo, a, b = c[i0], c[j0], -1.0 + 2 * (n // 5) * (2.0 / n) / 2.0, m * h, 5.37 * h * max(1, n // 32)
+    ov = [(xo + a, yo, zo), (xo - a, yo, zo), (xo, yo + a, zo), (xo, yo - a, zo), (xo, yo, zo + b), (xo, yo, zo - b)]
+    of = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    oct_ = convex_hull_mesh(ov, of)
+    tv = [(at(18), at(17), 0.23 + 0.5 * h), (at(28), at(20), 0.41), (at(20), at(28), 0.37), (at(22), at(22), 0.93 - 0.2 * h)]
+    tet = convex_hull_mesh(tv, [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)])
+    v, t = merge_meshes([oct_, tet])
+    f = uniform_faces(-1.0, 1.0, n)
+    return Workload("edge_vertices_%d" % n, f, f.copy(), f.copy(), v, t, seed=13)
+
+
+EDGE_CASES = {"slot": edge_slot, "aligned": edge_aligned, "vertices": edge_vertices}
+
+
 CONFIGS = {
     "cylinder2d": lambda: cylinder2d(128),
     "wing": lambda: wing(256, 128, 128, seed=1),
