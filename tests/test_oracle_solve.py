@@ -260,11 +260,15 @@ def _mms_error(n, stretched=False):
     pe = np.where(t == 2, 0.0, ex)
     pg = P.ghost_refresh(pe)
     gerr = np.max(np.abs(pg.ravel()[g["cell"]] - ex.ravel()[g["cell"]]))
-    # truncation error of the fluid rows at least 3 cells from every ghost
+    tau = np.abs(f - P.apply_S(pg))
+    # fluid rows next to a ghost (a face neighbour) and rows at least 3 cells from every ghost
+    face = np.zeros((3, 3, 3), bool)
+    face[1, 1, :] = face[1, :, 1] = face[:, 1, 1] = True
+    near = ndimage.binary_dilation(t == 1, structure=face) & fl
     far = ~ndimage.binary_dilation(t == 1, structure=np.ones((3, 3, 3), bool), iterations=3) & fl
-    trunc = np.max(np.abs(f[far] - P.apply_S(pg)[far]))
     return dict(h=h, l2=np.sqrt(np.sum(vol[fl] * err[fl] ** 2) / np.sum(vol[fl])), linf=np.max(np.abs(err[fl])),
-                lam=abs(st.lam), ghost=gerr, trunc=trunc)
+                lam=abs(st.lam), ghost=gerr, trunc=np.max(tau[far]), near=np.max(tau[near]),
+                near_int=np.sum(vol[near] * tau[near]))
 
 
 def _order(a, b, key):
@@ -274,19 +278,32 @@ def _order(a, b, key):
 @pytest.mark.parametrize("stretched", [False, True])
 def test_manufactured_solution_orders(stretched):
     """p = cos(pi x) cos(pi y) cos(pi z) on [-1,1]^3 (zero normal derivative on the box)
-    around a sphere, with exact normal-derivative data at the body intercepts.
+    around a sphere, with exact normal-derivative data at the body intercepts, on 32^3, 64^3
+    and 96^3.
 
-    The image-point closure of Eq. 2 (trilinear interpolation) with the central difference
-    about the intercept reproduces the exact ghost values to second order; for a Neumann
-    problem that leaves an O(h) error in the flux through the cell faces next to the body,
-    so the pressure itself, and the compatibility shift lambda, converge at first order.
-    The interior rows are second-order consistent on uniform grids."""
-    res = [_mms_error(n, stretched) for n in (16, 32, 64)]
+    The image-point closure (Eq. 2 with the Neumann row of Eq. 3) gives the ghost values to
+    second order, and the interior rows are second-order consistent on uniform grids.  But a
+    ghost value with an O(h^2) error enters the flux of the face it shares with a fluid cell
+    divided by h^2 (the flux over the cell volume), so the fluid rows next to the body keep
+    an O(1) truncation error that does not decay; it fills a layer one cell thick, of volume
+    O(h), so its integral is O(h), and the pressure error and the compatibility shift lambda
+    converge at first order.  These measured orders (and the O(1) layer that explains them)
+    are asserted within about 0.1 of their values; the second order of the interior is not
+    reachable with a trilinear (second-order) ghost closure of a Neumann condition."""
+    res = [_mms_error(n, stretched) for n in (32, 64, 96)]
     for a, b in zip(res[:-1], res[1:]):
-        assert _order(a, b, "ghost") >= 1.8
+        assert _order(a, b, "ghost") >= 1.85
         if not stretched:  # cell-centred rows on a stretched family are only supraconvergent
-            assert _order(a, b, "trunc") >= 1.8
-        assert _order(a, b, "l2") >= 0.85
-        assert _order(a, b, "linf") >= 0.5
-        assert _order(a, b, "lam") >= 0.7
-    assert res[-1]["l2"] < 0.01 and res[-1]["linf"] < 0.05
+            assert _order(a, b, "trunc") >= 1.9
+        assert 0.9 <= _order(a, b, "l2") <= 1.15
+        assert 0.75 <= _order(a, b, "linf") <= 1.15
+        assert 0.8 <= _order(a, b, "lam") <= 1.1
+        # the mechanism: O(1) truncation next to the body, O(h) once integrated over its layer
+        assert -0.25 <= _order(a, b, "near") <= 0.15
+        assert 0.7 <= _order(a, b, "near_int") <= 1.1
+    for r in res:
+        assert 3.0 <= r["near"] <= 9.0
+    # first order with a steady constant: error / h within 10 % across the family
+    c = [r["l2"] / r["h"] for r in res]
+    assert max(c) / min(c) < 1.1
+    assert res[-1]["l2"] < 0.002 and res[-1]["linf"] < 0.01
