@@ -81,3 +81,31 @@ def test_mesh_check_workload_meshes(checker):
         bad[len(bad) // 2] = bad[len(bad) // 2][::-1]
         cases += [(len(wl.verts), t), (len(wl.verts), bad)]
     assert checker(cases) == ["ok", "refused", "ok", "refused"]
+
+
+def test_oracle_mesh_check_verdicts():
+    """The oracle's own closedness check (orc_set_mesh) gives the same verdicts on the same
+    meshes: closed and consistently oriented, or refused with ORC_E_GEOMETRY (-3); indices
+    out of range are ORC_E_ARG (-1)."""
+    from oracle import OracleProblem
+    from oracle.oracle import OracleError
+    cube = _cube()
+    verts = np.array([[x, y, z] for z in (0.0, 1.0) for y in (0.0, 1.0) for x in (0.0, 1.0)])
+    verts = verts[[0, 1, 3, 2, 4, 5, 7, 6]] * 0.5 - 0.2  # vertex order of _cube's quads
+    flipped = cube.copy()
+    flipped[3] = flipped[3][::-1]
+    degenerate = cube.copy()
+    degenerate[0, 1] = degenerate[0, 0]
+    two_v = np.vstack([verts, verts + 0.6])
+    f = np.linspace(-1.0, 1.0, 9)
+    cases = [(verts, cube, 0), (verts, flipped, -3), (verts, cube[1:], -3), (verts, np.vstack([cube, cube[:1]]), -3),
+             (verts, degenerate, -3), (two_v, np.vstack([cube, cube + 8]), 0), (two_v, np.vstack([cube, cube]), -3),
+             (verts, np.where(cube == 7, 8, cube), -1)]
+    for v, t, want in cases:
+        P = OracleProblem(f, f, f)
+        try:
+            P.set_mesh(v, np.ascontiguousarray(t, dtype=np.int32))
+            got = 0
+        except OracleError as e:
+            got = e.code
+        assert got == want, (t.shape, got, want)
