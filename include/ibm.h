@@ -68,7 +68,7 @@ typedef enum { IBM_VCYCLE = 0, IBM_BICGSTAB = 1, IBM_BICGSTAB_SRJ = 2 } ibm_meth
 
 /* Solver options.  Defaults (ibm_default_opts): rel_tol 1e-10, max_cycles 200, V(2,2),
    16 sweeps on the coarsest level, FP64, zero initial guess, convergence-tested,
-   BiCGStab outer iteration. */
+   BiCGStab outer iteration, breakdown_tol 1e-12. */
 typedef struct {
     double rel_tol;          /* stop when ||r'||_2 <= rel_tol * ||f - Vmean(f)||_2 (fluid rows) */
     int max_cycles;          /* V-cycles (FP64) or refinement steps (mixed) */
@@ -79,16 +79,23 @@ typedef struct {
     int fixed_cycles;        /* > 0: run exactly this many cycles, no convergence test */
     int method;              /* IBM_VCYCLE, IBM_BICGSTAB (default) or IBM_BICGSTAB_SRJ */
     int srj_sweeps;          /* IBM_BICGSTAB_SRJ: sweeps per preconditioner application (16) */
+    double breakdown_tol;    /* BiCGStab near-breakdown: an inner product of modulus at most
+                                breakdown_tol times its factors' norms (rh.r for rho, rh.A y for
+                                alpha), or omega = 0, restarts the shadow residual (1e-12) */
 } ibm_solve_opts;
 
 typedef struct {
     int cycles;                /* outer iterations: V-cycles, refinement steps or BiCGStab steps */
     double rel_residual;       /* ||r'||_2 / ||f'||_2 after the last cycle */
-    double ghost_residual_max; /* reserved: max ghost-equation residual (0 if not computed) */
+    double ghost_residual_max; /* max over ghosts of |p_g - sum_m beta_m p_m - h_g| (degenerate:
+                                  |p_g - mean of fluid neighbours|) of the returned p */
     double lambda;             /* uniform source shift making the Neumann system consistent */
     double div_max;            /* projection only: max |D u| over fluid cells after correction */
-    double t_setup, t_solve, t_correct; /* seconds (host wall clock around the enqueue+sync) */
+    double t_setup;            /* seconds of the handle's last geometry set-up (set_geometry,
+                                  classify, build_ghost_stencils: host wall clock of the calls) */
+    double t_solve, t_correct; /* seconds (host wall clock around the enqueue+sync) */
     int vcycles;               /* V-cycles applied (BiCGStab: 2 per step) */
+    int restarts;              /* BiCGStab restarts of the shadow residual after a near-breakdown */
 } ibm_solve_stats;
 
 /* Fill `o` with the defaults listed above. */
@@ -194,10 +201,17 @@ ibm_status ibm_poisson_solve(ibm_grid *g, const double *rhs, double *p, const ib
 ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, double *p,
                        const ibm_solve_opts *o, ibm_solve_stats *s, void *stream);
 
-/* Non-blocking step API for serving: begin enqueues the initial residual, step enqueues
-   n_cycles cycles plus an asynchronous read-back of the residual norm, poll never blocks
-   (done = 1 once converged, failed or out of cycles; stats valid then).  rhs and p must stay
-   valid until done.  At completion the gauge is applied on the handle's stream. */
+/* Non-blocking step API: begin enqueues the initial residual, step enqueues n_cycles outer
+   iterations plus an asynchronous read-back of the residual norm, and poll never blocks.
+   poll sets *done to
+     1  finished: converged, failed or out of cycles; the return value is the solve's status
+        and s (host, may be NULL) holds its statistics;
+     0  work is in flight (the last step, a true-residual confirmation of a BiCGStab
+        convergence, or the final gauge): poll again later;
+    -1  idle: the previous step has completed and the solve needs more; call ibm_solve_step.
+   rhs and p (device) must stay valid until done = 1.  The iterates, step count and result are
+   those of ibm_poisson_solve with the same options, bit for bit; the gauge is applied on the
+   handle's stream at completion.  ibm_solve_step returns IBM_E_STATE while *done would be 0. */
 ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, void *stream);
 ibm_status ibm_solve_step(ibm_grid *g, int n_cycles);
 ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *s);

@@ -66,11 +66,13 @@ typedef struct {
                    2: BiCGStab preconditioned by srj_m scheduled relaxed Jacobi sweeps */
     int srj_m;                /* method 2: sweeps per preconditioner application */
     const double *srj_omega;  /* method 2: their relaxation factors, in order */
+    double breakdown_tol;     /* methods 1, 2: near-breakdown threshold (relative) */
 } orc_opts;
 
 typedef struct {
     int cycles, status;
     double rel_residual, ghost_residual_max, lambda, ref_norm, first_norm;
+    int restarts;             /* BiCGStab restarts of the shadow residual */
 } orc_stats;
 
 typedef struct {
@@ -1367,32 +1369,35 @@ static void true_residual(orc_problem *P, const double *f, const double *x, doub
     project_fluid_mean(P, r);
 }
 
+/* Near-breakdown of BiCGStab: an inner product whose modulus is at most breakdown_tol times
+   the product of its factors' norms (the shadow residual against the residual, or against
+   the image A y), or omega = 0, ends the step without the quotient (alpha = 0, beta = 0) and
+   restarts the shadow residual from the residual. */
+
 /* returns the iteration count; *rel_out = ||r_fluid|| / ref of the true residual */
 static int bicgstab(orc_problem *P, const double *f, double *x, const orc_opts *o, double ref, double *hist,
-                    int hist_len, double *rel_out, int *status) {
+                    int hist_len, double *rel_out, int *status, int *restarts) {
+    const double eps = o->breakdown_tol;
     const int64_t n = P->ncell;
     double *r = dalloc(n), *rh = dalloc(n), *pd = dalloc(n), *v = dalloc(n), *sv = dalloc(n), *t = dalloc(n);
     double *y = dalloc(n), *z = dalloc(n), *gh = dalloc(P->nghost);
     true_residual(P, f, x, r);
     memcpy(rh, r, sizeof(double) * n);
-    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    double rho = dot_active(P, rh, r), rh2 = rho;
+    double alpha = 0.0, omega = 0.0, beta = 0.0;
     const int nit = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
     double rel = norm_fluid(P, r) / ref;
     int it;
     *status = ORC_OK;
     for (it = 1; it <= nit; ++it) {
-        double rho = dot_active(P, rh, r);
-        double beta = (it == 1) ? 0.0 : (rho / rho_old) * (alpha / omega);
-        if (rho == 0.0 || !isfinite(beta)) { /* breakdown: restart the shadow residual */
-            memcpy(rh, r, sizeof(double) * n);
-            rho = dot_active(P, rh, r);
-            beta = 0.0;
-        }
+        int brk = 0;
         for (int64_t id = 0; id < n; ++id) pd[id] = r[id] + beta * (pd[id] - omega * v[id]);
         precondition(P, pd, y, gh, o);
         apply_full(P, y, v);
         project_fluid_mean(P, v);
-        alpha = rho / dot_active(P, rh, v);
+        double rv = dot_active(P, rh, v), vv = dot_active(P, v, v);
+        if (fabs(rv) > eps * sqrt(rh2 * vv)) alpha = rho / rv;
+        else { alpha = 0.0; brk = 1; }
         for (int64_t id = 0; id < n; ++id) sv[id] = r[id] - alpha * v[id];
         precondition(P, sv, z, gh, o);
         apply_full(P, z, t);
@@ -1403,15 +1408,30 @@ static int bicgstab(orc_problem *P, const double *f, double *x, const orc_opts *
             x[id] += alpha * y[id] + omega * z[id];
             r[id] = sv[id] - omega * t[id];
         }
-        rho_old = rho;
+        double rho_new = dot_active(P, rh, r), rr = dot_active(P, r, r);
+        if (omega == 0.0 || !(fabs(rho_new) > eps * sqrt(rh2 * rr))) brk = 1;
+        beta = brk ? 0.0 : (rho_new / rho) * (alpha / omega);
+        rho = rho_new;
         rel = norm_fluid(P, r) / ref;
         if (hist && it - 1 < hist_len) hist[it - 1] = rel;
-        if (!isfinite(rel)) { *status = ORC_E_NUMERIC; break; }
-        if (o->fixed_cycles <= 0 && rel <= o->rel_tol) {
+        if (!isfinite(rel) || !isfinite(beta)) { *status = ORC_E_NUMERIC; break; }
+        int restart = 0;
+        if (o->fixed_cycles > 0) {
+            if (brk) { restart = 1; ++*restarts; }
+        } else if (rel <= o->rel_tol) {
             true_residual(P, f, x, r);  /* confirm with the true residual */
             rel = norm_fluid(P, r) / ref;
             if (rel <= o->rel_tol) break;
+            restart = 1;
+        } else if (brk) {
+            restart = 1;
+            ++*restarts;
+        }
+        if (restart) { /* restart the shadow residual from the residual */
             memcpy(rh, r, sizeof(double) * n);
+            rho = dot_active(P, rh, r);
+            rh2 = rho;
+            beta = 0.0;
         }
     }
     if (it > nit) it = nit;
@@ -1451,12 +1471,16 @@ int orc_solve(orc_problem *P, const double *f, double *p, const orc_opts *o, orc
     double lambda;
     double r0 = residual_norm(P, p, f, &lambda, rbuf);
     double ref = fn > 0.0 ? fn : r0;
-    int status = ORC_OK, cyc = 0;
+    int status = ORC_OK, cyc = 0, restarts = 0;
     double rel = ref > 0.0 ? r0 / ref : 0.0;
     st->first_norm = r0;
+    if ((o->method == 1 || o->method == 2) && !(o->breakdown_tol >= 0.0 && o->breakdown_tol < 1.0)) {
+        free(rbuf);
+        return ORC_E_ARG;
+    }
     if (o->method == 2 && (o->srj_m < 1 || !o->srj_omega)) { free(rbuf); return ORC_E_ARG; }
     if (ref > 0.0 && (o->method == 1 || o->method == 2)) {
-        cyc = bicgstab(P, f, p, o, ref, hist, hist_len, &rel, &status);
+        cyc = bicgstab(P, f, p, o, ref, hist, hist_len, &rel, &status, &restarts);
         residual_norm(P, p, f, &lambda, rbuf);
     } else if (ref > 0.0) {
         int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
@@ -1488,6 +1512,7 @@ int orc_solve(orc_problem *P, const double *f, double *p, const orc_opts *o, orc
     st->lambda = lambda;
     st->ref_norm = ref;
     st->ghost_residual_max = ghost_residual_max(P, p);
+    st->restarts = restarts;
     free(rbuf);
     return status;
 }

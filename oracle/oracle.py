@@ -29,16 +29,18 @@ def build_oracle(force: bool = False) -> str:
 class OracleOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_sweeps", C.c_int), ("use_initial_guess", C.c_int), ("fixed_cycles", C.c_int),
-                ("method", C.c_int), ("srj_m", C.c_int), ("srj_omega", C.POINTER(C.c_double))]
+                ("method", C.c_int), ("srj_m", C.c_int), ("srj_omega", C.POINTER(C.c_double)),
+                ("breakdown_tol", C.c_double)]
 
     @staticmethod
     def make(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=16, use_initial_guess=0,
-             fixed_cycles=0, method="mg", srj_omega=None):
+             fixed_cycles=0, method="mg", srj_omega=None, breakdown_tol=1e-12):
         """method "bicgstab_srj" needs srj_omega (the relaxation factors of one preconditioner
         application, kept alive by the caller for the duration of the call)."""
         m = ({"mg": 0, "vcycle": 0, "bicgstab": 1, "bicgstab_srj": 2}[method] if isinstance(method, str)
              else int(method))
         o = OracleOpts(rel_tol, max_cycles, nu1, nu2, coarsest_sweeps, use_initial_guess, fixed_cycles, m)
+        o.breakdown_tol = breakdown_tol
         if srj_omega is not None:
             o.srj_m = len(srj_omega)
             o.srj_omega = srj_omega.ctypes.data_as(C.POINTER(C.c_double))
@@ -48,7 +50,7 @@ class OracleOpts(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("rel_residual", C.c_double),
                 ("ghost_residual_max", C.c_double), ("lambda_", C.c_double), ("ref_norm", C.c_double),
-                ("first_norm", C.c_double)]
+                ("first_norm", C.c_double), ("restarts", C.c_int)]
 
 
 @dataclass
@@ -60,6 +62,7 @@ class OracleStats:
     lam: float
     ref_norm: float
     history: np.ndarray
+    restarts: int = 0
 
 
 _lib = None
@@ -265,7 +268,7 @@ class OracleProblem:
         if s < 0:
             raise OracleError(s, "orc_solve")
         return p, OracleStats(st.status, st.cycles, st.rel_residual, st.ghost_residual_max, st.lambda_,
-                              st.ref_norm, hist[:st.cycles].copy())
+                              st.ref_norm, hist[:st.cycles].copy(), st.restarts)
 
     def rhs(self, u, v, w, dt=1.0):
         f = np.empty(self.shape)

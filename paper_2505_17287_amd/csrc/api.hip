@@ -256,6 +256,7 @@ void ibm_default_opts(ibm_solve_opts *o) {
     o->fixed_cycles = 0;
     o->method = IBM_BICGSTAB;
     o->srj_sweeps = 16;
+    o->breakdown_tol = 1e-12;
 }
 
 ibm_status ibm_create_grid(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
@@ -368,6 +369,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
                                     void *stream, bool known_topology) {
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_set_geometry: NULL handle");
     if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_set_geometry before ibm_bind_workspace");
+    const double t_in = now_s();
     if (!verts || !tris || nv < 3 || nt < 1) return fail(g, IBM_E_ARG, "ibm_set_geometry: empty mesh");
     if (nv > g->nv_max || nt > g->nt_max) return fail(g, IBM_E_NOMEM, "mesh larger than the bound capacities");
     bool finite = true;  // no early exit: the loops vectorise
@@ -442,12 +444,14 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
     if (bucket_overflow) return fail(g, IBM_E_NOMEM, "triangle bucket grid overflow");
     g->stage = ST_GEOMETRY;
     g->ng = 0;
+    g->t_setup = now_s() - t_in;
     return IBM_OK;
 }
 
 ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_classify: NULL handle");
     if (g->stage < ST_GEOMETRY) return fail(g, IBM_E_STATE, "ibm_classify before ibm_set_geometry");
+    const double t_in = now_s();
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     int64_t c[4];
@@ -476,12 +480,14 @@ ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
     if (c[0] == 0) return fail(g, IBM_E_GEOMETRY, "no fluid cell");
     g->ng = c[1];
     g->stage = ST_CLASSIFIED;
+    g->t_setup += now_s() - t_in;
     return IBM_OK;
 }
 
 ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_out) {
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_build_ghost_stencils: NULL handle");
     if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_build_ghost_stencils before ibm_classify");
+    const double t_in = now_s();
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     HIP_TRY(hipMemsetAsync(g->counters + 5, 0, sizeof(int64_t), s), "memset");
@@ -502,6 +508,7 @@ ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_
     for (int l = 0; l < g->nlev; ++l) g->lev[l].vol_active = g->sc_host->vol[l];
     if (n_ghost_out) *n_ghost_out = g->ng;
     g->stage = ST_STENCILS;
+    g->t_setup += now_s() - t_in;
     return IBM_OK;
 }
 
@@ -573,7 +580,7 @@ ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims) {
 static ibm_status check_opts(ibm_grid *g, const ibm_solve_opts *o) {
     if (!o) return fail(g, IBM_E_ARG, "NULL options");
     if (!(o->rel_tol >= 0.0) || o->max_cycles < 1 || o->nu1 < 0 || o->nu2 < 0 || o->coarsest_sweeps < 0 ||
-        o->fixed_cycles < 0)
+        o->fixed_cycles < 0 || !(o->breakdown_tol >= 0.0 && o->breakdown_tol < 1.0))
         return fail(g, IBM_E_ARG, "invalid solver options");
     if (o->precision == IBM_MIXED && g->prec != IBM_MIXED)
         return fail(g, IBM_E_STATE, "mixed precision needs a workspace bound with IBM_MIXED");
@@ -663,7 +670,7 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
         hs->ref = ref;
     }
     ibm_status status = IBM_OK;
-    int it = 0;
+    int it = 0, restarts = 0;
     double rel = hs->ref > 0.0 ? r0 / hs->ref : 0.0;
     bool have_true = true;  // the scalars describe the true residual of x
     if (hs->ref > 0.0 && (o->fixed_cycles > 0 || rel > o->rel_tol)) {
@@ -679,7 +686,13 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
                 status = IBM_E_NUMERIC;
                 break;
             }
-            if (o->fixed_cycles > 0) continue;
+            if (o->fixed_cycles > 0) {
+                if (hs->brk) {
+                    HIP_TRY(krylov_restart(g, s), "restart");
+                    ++restarts;
+                }
+                continue;
+            }
             if (rel <= o->rel_tol) {
                 // confirm with the true residual (this also restarts the recurrences)
                 HIP_TRY(krylov_residual(g, rhs, x, s), "true residual");
@@ -688,8 +701,9 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
                 have_true = true;
                 rel = hs->rel;
                 if (rel <= o->rel_tol) break;
-            } else if (hs->rho == 0.0) {
+            } else if (hs->brk) {
                 HIP_TRY(krylov_restart(g, s), "restart");
+                ++restarts;
             }
         }
         if (it > nit) it = nit;
@@ -702,17 +716,22 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
         rel = hs->rel;
     }
     HIP_TRY(gauge_pass(g, x, p, s), "gauge");
-    if (sync_end) HIP_TRY(hipStreamSynchronize(s), "gauge sync");
+    HIP_TRY(ghost_residual_pass(g, p, s), "ghost residual");
+    if (sync_end) {
+        HIP_TRY(hipMemcpyAsync(&hs->ghost_res, &g->sc->ghost_res, sizeof(double), hipMemcpyDeviceToHost, s), "read");
+        HIP_TRY(hipStreamSynchronize(s), "gauge sync");
+    }
     if (st) {
         st->cycles = it;
         st->vcycles = 2 * it;
         st->rel_residual = rel;
-        st->ghost_residual_max = 0.0;
+        st->ghost_residual_max = sync_end ? hs->ghost_res : 0.0;  // else filled by the caller after its sync
         st->lambda = hs->lambda;
         st->div_max = 0.0;
-        st->t_setup = 0.0;
+        st->t_setup = g->t_setup;
         st->t_solve = now_s() - t0;
         st->t_correct = 0.0;
+        st->restarts = restarts;
     }
     if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite or diverging residual");
     return status;
@@ -768,17 +787,20 @@ static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ib
         if (status == IBM_OK && o->fixed_cycles <= 0 && rel > o->rel_tol) status = IBM_NOT_CONVERGED;
     }
     HIP_TRY(gauge_pass(g, bufs[cur], p, s), "gauge");
+    HIP_TRY(ghost_residual_pass(g, p, s), "ghost residual");
+    HIP_TRY(hipMemcpyAsync(&hs->ghost_res, &g->sc->ghost_res, sizeof(double), hipMemcpyDeviceToHost, s), "read");
     HIP_TRY(hipStreamSynchronize(s), "gauge sync");
     if (st) {
         st->cycles = cycles;
         st->vcycles = cycles;
         st->rel_residual = rel;
-        st->ghost_residual_max = 0.0;
+        st->ghost_residual_max = hs->ghost_res;
         st->lambda = hs->lambda;
         st->div_max = 0.0;
-        st->t_setup = 0.0;
+        st->t_setup = g->t_setup;
         st->t_solve = now_s() - t0;
         st->t_correct = 0.0;
+        st->restarts = 0;
     }
     if (status == IBM_E_NUMERIC) return fail(g, status, "non-finite or diverging residual");
     return status;
@@ -815,8 +837,8 @@ ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, 
     HIP_TRY(hipStreamSynchronize(s), "project sync");
     if (st) {
         st->div_max = g->sc_host->div_max;
+        st->ghost_residual_max = g->sc_host->ghost_res;
         st->t_correct = now_s() - t1;
-        st->t_setup = 0.0;
         (void)t0;
     }
     return rs;
@@ -846,6 +868,7 @@ ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_
     S.t0 = now_s();
     S.finishing = false;
     S.phase = 0;
+    S.restarts = 0;
     if (!S.ev) HIP_TRY(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming), "event");
     HIP_TRY(enqueue_begin(g, rhs, p, o, S.stream), "begin");
     HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
@@ -897,10 +920,11 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
                 st->cycles = S.cycles;
                 st->vcycles = (krylov_method(S.o.method)) ? 2 * S.cycles : S.cycles;
                 st->rel_residual = hs->rel;
-                st->ghost_residual_max = 0.0;
+                st->ghost_residual_max = hs->ghost_res;
                 st->lambda = hs->lambda;
                 st->div_max = 0.0;
-                st->t_setup = 0.0;
+                st->t_setup = g->t_setup;
+                st->restarts = S.restarts;
                 st->t_solve = now_s() - S.t0;
                 st->t_correct = 0.0;
             }
@@ -942,12 +966,16 @@ ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *st) {
                 finish = true;
             } else if (krylov_method(S.o.method)) {
                 S.phase = 0;
-                if (hs->rho == 0.0) HIP_TRY(krylov_restart(g, S.stream), "restart");
+                if (hs->brk) {
+                    HIP_TRY(krylov_restart(g, S.stream), "restart");
+                    ++S.restarts;
+                }
             }
         }
         if (finish) {
             double *bufs[2] = {S.p_user, g->p2};
             HIP_TRY(gauge_pass(g, bufs[S.cur], S.p_user, S.stream), "gauge");
+            HIP_TRY(ghost_residual_pass(g, S.p_user, S.stream), "ghost residual");
             HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream), "read");
             HIP_TRY(hipEventRecord(S.ev, S.stream), "record");
             S.ev_pending = true;

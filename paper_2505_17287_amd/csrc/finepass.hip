@@ -74,12 +74,13 @@ __device__ __forceinline__ void zm_block_sums_store(const double (&v)[NS], doubl
 }
 
 // Sums of the Krylov operator passes.  DOTS 0: w = S y, sum V w.  DOTS 1 and 2: w = S y - mu
-// (the image with its volume-weighted fluid mean, known beforehand, removed), sum o w, and
-// for DOTS 2 also sum w w (o is the vector the image is dotted with: the shadow residual or s).
-// DOTS 3: the residual w = o - S y (o the right-hand side), sum V w.
+// (the image with its volume-weighted fluid mean, known beforehand, removed), sum o w and
+// sum w w (o is the vector the image is dotted with: the shadow residual or s; w w gives
+// omega, and the near-breakdown test of alpha).  DOTS 3: the residual w = o - S y (o the
+// right-hand side), sum V w.
 template <int DOTS>
 struct ApplySums {
-    static constexpr int NS = DOTS == 2 ? 2 : 1;
+    static constexpr int NS = (DOTS == 1 || DOTS == 2) ? 2 : 1;
 };
 
 // ---- residual + restriction --------------------------------------------------------------
@@ -407,7 +408,7 @@ __global__ void __launch_bounds__(ZM_NT)
             __builtin_nontemporal_store(a, w + (int64_t)k_ * plane + rowoff);                                      \
             if (DOTS == 0 || DOTS == 3) acc[0] += (vxy * (D).wz) * a;                                              \
             if (DOTS == 1 || DOTS == 2) acc[0] += fl ? (D).fv * a : 0.0;                                           \
-            if (DOTS == 2) acc[1 % NS] += a * a;                                                                   \
+            if (DOTS == 1 || DOTS == 2) acc[1 % NS] += a * a;                                                      \
         }                                                                                                          \
         ym1 = yc;                                                                                                  \
         yc = (D).pp;                                                                                               \
@@ -707,7 +708,7 @@ __global__ void __launch_bounds__(ZP_NT)
                 acc[0] += f0_ ? (D).fv.x * a0 : 0.0;                                                               \
                 acc[0] += f1_ ? (D).fv.y * a1 : 0.0;                                                               \
             }                                                                                                      \
-            if (DOTS == 2) {                                                                                       \
+            if (DOTS == 1 || DOTS == 2) {                                                                          \
                 acc[1 % NS] += a0 * a0;                                                                            \
                 acc[1 % NS] += a1 * a1;                                                                            \
             }                                                                                                      \

@@ -115,6 +115,7 @@ struct Scalars {
     double ref;         // reference norm ||f - Vmean(f)||
     double vmean;       // scratch mean
     double div_max;
+    double ghost_res;   // max ghost-equation residual of the returned pressure
     int bad;            // non-finite seen
     int pad1;
     // Krylov (BiCGStab) scalars
@@ -122,6 +123,9 @@ struct Scalars {
     double mu_v;        // volume-weighted fluid mean removed from an operator image
     double zero;        // constant 0 (shift of the preconditioner's right-hand side)
     float zero32, pad2;
+    double rh2;         // squared norm of the shadow residual (set when it is (re)started)
+    int brk;            // near-breakdown seen in the last step: the host restarts the shadow residual
+    int pad3;
     double mu[MAX_LEVELS];
     double vol[MAX_LEVELS];   // summed volume of the active cells of each level
     double mom_b2;            // advection-diffusion step: sum of b^2 over fluid rows
@@ -176,6 +180,7 @@ struct SolveState {  // in-flight solve of the step API
     int cur = 0;                // which buffer holds the iterate (0 = user p, 1 = workspace)
     bool finishing = false;     // gauge enqueued, waiting for its event
     int phase = 0;              // BiCGStab: 1 while a true-residual confirmation is in flight
+    int restarts = 0;           // BiCGStab restarts after a near-breakdown
     double t0 = 0.0;
 };
 
@@ -256,6 +261,7 @@ struct ibm_grid {
     double *f_bi = nullptr, *f_ip = nullptr, *f_beta = nullptr, *f_betac = nullptr, *f_ubi = nullptr,
            *f_scr = nullptr;
     double diag_max = -1.0;                // max over cells of the flux-coefficient sum (< 0: not read yet)
+    double t_setup = 0.0;                  // seconds of the last set_geometry + classify + stencils
     std::vector<double> srj_omega;         // relaxation factors of the scheduled-Jacobi preconditioner
     // Krylov vectors (FP64, full grid)
     double *kv[10] = {nullptr};
@@ -342,6 +348,7 @@ hipError_t vcycle_mixed(ibm_grid *g, double **bufs, int *cur, const double *f, h
 hipError_t norm_pass(ibm_grid *g, const double *p, const double *f, hipStream_t s, bool write_r32, bool first);
 hipError_t ref_norm_pass(ibm_grid *g, const double *f, hipStream_t s);
 hipError_t gauge_pass(ibm_grid *g, const double *pcur, double *pdst, hipStream_t s);
+hipError_t ghost_residual_pass(ibm_grid *g, const double *p, hipStream_t s);
 hipError_t rhs_pass(ibm_grid *g, const double *u, const double *v, const double *w, double dt, double *f,
                     hipStream_t s);
 hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt,
@@ -351,6 +358,7 @@ hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipS
 hipError_t krylov_setup(ibm_grid *g, hipStream_t s);
 hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s);
 hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s);
+// the handle's last geometry set-up time is g->t_setup (seconds, host wall clock)
 hipError_t krylov_restart(ibm_grid *g, hipStream_t s);
 
 // advection-diffusion half-step launchers (momentum.hip)

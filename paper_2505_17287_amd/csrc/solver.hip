@@ -1468,17 +1468,70 @@ __global__ void __launch_bounds__(NORM_NT) k_divmax(Fine<double> F, const double
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(256) k_max_finalize(const double *partials, int nb, Scalars *sc) {
+__global__ void __launch_bounds__(256) k_max_finalize(const double *partials, int nb, double *out) {
     __shared__ double sh[4];
     double m = 0.0;
     for (int q = threadIdx.x; q < nb; q += 256) m = fmax(m, partials[q]);
     m = block_max<256>(m, sh, threadIdx.x);
-    if (threadIdx.x == 0) sc->div_max = m;
+    if (threadIdx.x == 0) *out = m;
+}
+
+// max over ghosts of |p_g - sum_m beta_m p_m - h_g| (degenerate ghosts: |p_g - mean of the
+// fluid 26-neighbours|), one partial maximum per block
+__global__ void __launch_bounds__(256) k_ghost_res(GhostView G, const double *__restrict__ p, int nx, int ny, int nz,
+                                                   const uint8_t *__restrict__ type, double *partials) {
+    __shared__ double sh[4];
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (g < G.ng) {
+        const int64_t cell = G.cell[g];
+        double target;
+        if (G.flags[g] & GF_DEGENERATE) {
+            int i, j, k;
+            unflatten(cell, nx, ny, i, j, k);
+            double sm = 0.0;
+            int n = 0;
+            for (int dk = -1; dk <= 1; ++dk)
+                for (int dj = -1; dj <= 1; ++dj)
+                    for (int di = -1; di <= 1; ++di) {
+                        const int ii = i + di, jj = j + dj, kk = k + dk;
+                        if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                        const int64_t q = ((int64_t)kk * ny + jj) * nx + ii;
+                        if (type[q] == T_FLUID) {
+                            sm += p[q];
+                            ++n;
+                        }
+                    }
+            target = n ? sm / n : 0.0;
+        } else {
+            double sm = 0.0;
+            for (int m = 0; m < 8; ++m) {
+                const int32_t q = G.st[8 * g + m];
+                if (q >= 0) sm = sm + G.beta[8 * g + m] * p[q];
+            }
+            target = sm + G.h[g];
+        }
+        r = fabs(p[cell] - target);
+    }
+    r = block_max<256>(r, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+hipError_t ghost_residual_pass(ibm_grid *g, const double *p, hipStream_t s) {
+    if (g->ng == 0) {
+        hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, s, g->partials, 0, &g->sc->ghost_res);
+        return hipGetLastError();
+    }
+    const unsigned nb = (unsigned)((g->ng + 255) / 256);
+    hipLaunchKernelGGL(k_ghost_res, dim3(nb), dim3(256), 0, s, ghost_view(g), p, g->nx, g->ny, g->nz, g->type,
+                       g->partials);
+    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, s, g->partials, (int)nb, &g->sc->ghost_res);
+    return hipGetLastError();
 }
 
 hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s) {
     hipLaunchKernelGGL(k_divmax, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, fine64(g), u, v, w, g->partials);
-    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, g->sc);
+    hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, &g->sc->div_max);
     return hipGetLastError();
 }
 
@@ -1625,15 +1678,24 @@ __global__ void __launch_bounds__(NORM_NT) k_project(const uint8_t *__restrict__
     if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = s;
 }
 
-__global__ void k_krylov_finalize(const double *partials, int nb, int stride, Scalars *sc, int op) {
+// Near-breakdown of BiCGStab: an inner product whose modulus is at most brk_tol (the option
+// breakdown_tol) times the product of its factors' norms (the shadow residual against the
+// residual for rho, or against A y for alpha), or omega = 0.  The step then does not form the
+// quotient (alpha = 0; beta = 0) and sets sc->brk; the host restarts the shadow residual from
+// the residual.
+
+// stride 3 (K_RHO): sums of rh.r, r.r on fluid rows and r.r on every active row
+__global__ void k_krylov_finalize(const double *partials, int nb, int stride, Scalars *sc, int op, double brk_tol) {
     __shared__ double sh[4];
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int q = threadIdx.x; q < nb; q += 256) {
         a += partials[stride * q];
         if (stride > 1) b += partials[stride * q + 1];
+        if (stride > 2) c += partials[stride * q + 2];
     }
     a = block_sum<256>(a, sh, threadIdx.x);
     b = block_sum<256>(b, sh, threadIdx.x);
+    c = block_sum<256>(c, sh, threadIdx.x);
     if (threadIdx.x != 0) return;
     switch (op) {
         case K_MU: sc->mu_v = a / sc->vol[0]; break;
@@ -1643,7 +1705,16 @@ __global__ void k_krylov_finalize(const double *partials, int nb, int stride, Sc
         case K_INIT:
         case K_RESTART: {
             const double rho_new = a;
-            sc->beta = (op != K_RHO) ? 0.0 : (rho_new / sc->rho) * (sc->alpha / sc->omega);
+            if (op == K_RHO) {
+                const bool brk = sc->brk || sc->omega == 0.0 || !(fabs(rho_new) > brk_tol * sqrt(sc->rh2 * c));
+                sc->brk = brk ? 1 : 0;
+                sc->beta = brk ? 0.0 : (rho_new / sc->rho) * (sc->alpha / sc->omega);
+            } else {
+                // the shadow residual is (re)started as the residual: rho = rh.rh
+                sc->beta = 0.0;
+                sc->rh2 = rho_new;
+                sc->brk = 0;
+            }
             sc->rho_old = sc->rho;
             sc->rho = rho_new;
             sc->norm = sqrt(b);
@@ -1658,7 +1729,7 @@ __global__ void k_krylov_finalize(const double *partials, int nb, int stride, Sc
 // alpha = rho / rh.v or omega = t.s / t.t from the operator pass's sums (stride ns over nb
 // workgroups: o w, then w w) and the ghost rows' (stride 2 over ngb blocks)
 __global__ void k_krylov_finalize_dots(const double *part, int nb, int ns, const double *gpart, int ngb, Scalars *sc,
-                                       int op) {
+                                       int op, double brk_tol) {
     __shared__ double sh[4];
     double a = 0.0, b = 0.0;
     for (int q = threadIdx.x; q < nb; q += 256) {
@@ -1672,8 +1743,17 @@ __global__ void k_krylov_finalize_dots(const double *part, int nb, int ns, const
     a = block_sum<256>(a, sh, threadIdx.x);
     b = block_sum<256>(b, sh, threadIdx.x);
     if (threadIdx.x != 0) return;
-    if (op == K_ALPHA) sc->alpha = (a != 0.0) ? sc->rho / a : 0.0;
-    else sc->omega = (b > 0.0) ? a / b : 0.0;
+    if (op == K_ALPHA) {
+        // a = rh.v, b = v.v
+        if (fabs(a) > brk_tol * sqrt(sc->rh2 * b)) {
+            sc->alpha = sc->rho / a;
+        } else {
+            sc->alpha = 0.0;
+            sc->brk = 1;
+        }
+    } else {
+        sc->omega = (b > 0.0) ? a / b : 0.0;
+    }
 }
 
 // pd = r + beta (pd - omega v) on fluid + ghost cells
@@ -1699,7 +1779,7 @@ __global__ void k_s_update(const uint8_t *__restrict__ type, int64_t N, const do
     __builtin_nontemporal_store((type[id] == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id], s + id);
 }
 
-// x += alpha y + omega z ; r = s - omega t ; partials of rh.r (all) and r.r (fluid)
+// x += alpha y + omega z ; r = s - omega t ; partials of rh.r (all), r.r (fluid) and r.r (all)
 __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict__ type, int64_t N, double *x,
                                                        const double *__restrict__ y, const double *__restrict__ z,
                                                        const double *__restrict__ s, const double *__restrict__ t,
@@ -1707,7 +1787,7 @@ __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict
                                                        double *partials) {
     __shared__ double sh[NORM_NT / 64];
     const double alpha = sc->alpha, omega = sc->omega;
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t id = (int64_t)blockIdx.x * NORM_NT + threadIdx.x; id < N; id += (int64_t)gridDim.x * NORM_NT) {
         const uint8_t ty = type[id];
         if (ty == T_DEAD) continue;
@@ -1715,12 +1795,15 @@ __global__ void __launch_bounds__(NORM_NT) k_xr_update(const uint8_t *__restrict
         const double rv = s[id] - omega * t[id];
         __builtin_nontemporal_store(rv, r + id);
         a += rh[id] * rv;
+        c += rv * rv;
         if (ty == T_FLUID) b += rv * rv;
     }
     double q = block_sum<NORM_NT>(a, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[2 * blockIdx.x] = q;
+    if (threadIdx.x == 0) partials[3 * blockIdx.x] = q;
     q = block_sum<NORM_NT>(b, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = q;
+    if (threadIdx.x == 0) partials[3 * blockIdx.x + 1] = q;
+    q = block_sum<NORM_NT>(c, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[3 * blockIdx.x + 2] = q;
 }
 
 // preconditioner start: ghost right-hand sides gh = r_g / s_g and e_g = gh (the first ghost
@@ -1829,20 +1912,20 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
 // first, from the fluid-ghost faces alone (k_ghost_flux), so the operator pass writes the
 // projected image and forms its inner products in the same sweep.
 static hipError_t apply_projected(ibm_grid *g, const double *y, double *w, const double *other, int mode, int op,
-                                  hipStream_t s) {
+                                  double brk_tol, hipStream_t s) {
     const int ngb = g->ng > 0 ? nblk(g->ng) : 0;
     double *gpart = g->partials + 2 * zmarch_partials_max(g->nx, g->ny, g->nz);
     if (g->ng > 0)
         hipLaunchKernelGGL(k_ghost_flux, dim3(ngb), dim3(256), 0, s, ghost_view(g), fine64(g), y, g->partials);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, ngb, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, ngb, 1, g->sc, (int)K_MU, 0.0);
     int nparts = 0;
     hipError_t e = launch_apply_fluid(fine64(g), y, w, other, &g->sc->mu_v, mode + 1, g->partials, &nparts, s);
     if (e != hipSuccess) return e;
     if (g->ng > 0)
         hipLaunchKernelGGL(k_apply_ghost, dim3(ngb), dim3(256), 0, s, ghost_view(g), y, w, g->g_scale, g->nx, g->ny,
                            g->nz, g->type, 0, other, gpart);
-    hipLaunchKernelGGL(k_krylov_finalize_dots, dim3(1), dim3(256), 0, s, g->partials, nparts, mode + 1, gpart, ngb,
-                       g->sc, op);
+    hipLaunchKernelGGL(k_krylov_finalize_dots, dim3(1), dim3(256), 0, s, g->partials, nparts, 2, gpart, ngb, g->sc,
+                       op, brk_tol);
     return hipGetLastError();
 }
 
@@ -1863,9 +1946,10 @@ hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStr
     if (g->ng > 0)
         hipLaunchKernelGGL(k_apply_ghost, dim3(nblk(g->ng)), dim3(256), 0, s, ghost_view(g), x, r, g->g_scale, g->nx,
                            g->ny, g->nz, g->type, 1, (const double *)nullptr, (double *)nullptr);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, nparts, 1, g->sc, (int)K_MU);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, nparts, 1, g->sc, (int)K_MU, 0.0);
     hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, r, rh, g->sc, 2, g->partials);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_INIT);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_INIT,
+                       0.0);
     return hipGetLastError();
 }
 
@@ -1878,13 +1962,14 @@ hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStrea
     hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc);
     double *y = nullptr, *z = nullptr;
     if ((e = precondition(g, pd, ya, yb, &y, o, s)) != hipSuccess) return e;
-    if ((e = apply_projected(g, y, v, rh, 0, K_ALPHA, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, y, v, rh, 0, K_ALPHA, o->breakdown_tol, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_s_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, sv, g->sc);
     if ((e = precondition(g, sv, za, zb, &z, o, s)) != hipSuccess) return e;
-    if ((e = apply_projected(g, z, t, sv, 1, K_OMEGA, s)) != hipSuccess) return e;
+    if ((e = apply_projected(g, z, t, sv, 1, K_OMEGA, o->breakdown_tol, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_xr_update, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, x, y, z, sv, t, r, rh, g->sc,
                        g->partials);
-    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc, (int)K_RHO);
+    hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 3, g->sc, (int)K_RHO,
+                       o->breakdown_tol);
     return hipGetLastError();
 }
 
@@ -1893,7 +1978,7 @@ hipError_t krylov_restart(ibm_grid *g, hipStream_t s) {
     hipLaunchKernelGGL(k_project, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, g->kv[0], g->kv[1], g->sc, 3,
                        g->partials);
     hipLaunchKernelGGL(k_krylov_finalize, dim3(1), dim3(256), 0, s, g->partials, RED_BLOCKS, 2, g->sc,
-                       (int)K_RESTART);
+                       (int)K_RESTART, 0.0);
     return hipGetLastError();
 }
 

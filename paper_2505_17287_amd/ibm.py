@@ -25,13 +25,14 @@ _STATUS = {0: "IBM_OK", 1: "IBM_NOT_CONVERGED", -1: "IBM_E_ARG", -2: "IBM_E_STAT
 class SolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_cycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_sweeps", C.c_int), ("precision", C.c_int), ("use_initial_guess", C.c_int),
-                ("fixed_cycles", C.c_int), ("method", C.c_int), ("srj_sweeps", C.c_int)]
+                ("fixed_cycles", C.c_int), ("method", C.c_int), ("srj_sweeps", C.c_int),
+                ("breakdown_tol", C.c_double)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("rel_residual", C.c_double), ("ghost_residual_max", C.c_double),
                 ("lambda_", C.c_double), ("div_max", C.c_double), ("t_setup", C.c_double),
-                ("t_solve", C.c_double), ("t_correct", C.c_double), ("vcycles", C.c_int)]
+                ("t_solve", C.c_double), ("t_correct", C.c_double), ("vcycles", C.c_int), ("restarts", C.c_int)]
 
 
 IBM_VCYCLE, IBM_BICGSTAB, IBM_BICGSTAB_SRJ = 0, 1, 2
@@ -60,10 +61,14 @@ class Stats:
     t_solve: float
     t_correct: float
     vcycles: int = 0
+    ghost_residual_max: float = 0.0
+    t_setup: float = 0.0
+    restarts: int = 0
 
 
 def _stats(code, st):
-    return Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct, st.vcycles)
+    return Stats(code, st.cycles, st.rel_residual, st.lambda_, st.div_max, st.t_solve, st.t_correct, st.vcycles,
+                 st.ghost_residual_max, st.t_setup, st.restarts)
 
 
 class IBMError(RuntimeError):
@@ -142,7 +147,7 @@ def declared_symbols(header=None):
 
 
 def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=16, precision="fp64",
-              use_initial_guess=False, fixed_cycles=0, method="bicgstab", srj_sweeps=16):
+              use_initial_guess=False, fixed_cycles=0, method="bicgstab", srj_sweeps=16, breakdown_tol=None):
     o = SolveOpts()
     lib().ibm_default_opts(C.byref(o))
     o.rel_tol = rel_tol
@@ -153,6 +158,8 @@ def make_opts(rel_tol=1e-10, max_cycles=200, nu1=2, nu2=2, coarsest_sweeps=16, p
     o.fixed_cycles = fixed_cycles
     o.method = _METHODS[method] if isinstance(method, str) else int(method)
     o.srj_sweeps = int(srj_sweeps)
+    if breakdown_tol is not None:
+        o.breakdown_tol = float(breakdown_tol)
     return o
 
 

@@ -246,3 +246,78 @@ def test_profiling_times_every_stride_th_sweep(stride):
     g.set_profiling(False)
     assert prof["n_fp64"] == (8 + stride - 1) // stride
     assert prof["ms_fp64"] > 0.0
+
+
+@pytest.mark.parametrize("precision,method", [("fp64", "vcycle"), ("fp64", "bicgstab"), ("mixed", "vcycle"),
+                                              ("mixed", "bicgstab"), ("fp64", "bicgstab_srj")])
+def test_step_api_equals_blocking_solve(precision, method):
+    """ibm_solve_begin / ibm_solve_step / ibm_solve_poll give, bit for bit, the pressure of the
+    blocking ibm_poisson_solve with the same options (converged and at a fixed step count),
+    with the same step count; poll reports -1 while idle between steps and never blocks."""
+    import time
+    torch = _torch()
+    from paper_2505_17287_amd import ibm
+    wl = CASES["spheres48"]()
+    P = OracleProblem.from_workload(wl, stencils=False)
+    g, _ = _setup(wl, precision="mixed")
+    fd = torch.from_numpy(P.rhs(*wl.velocity())).cuda()
+    for kw in (dict(rel_tol=1e-10), dict(fixed_cycles=3)):
+        ref, st_ref = g.poisson_solve(fd, precision=precision, method=method, **kw)
+        p = torch.empty_like(fd)
+        g.solve_begin(fd, p, precision=precision, method=method, **kw)
+        done, idle, polls = 0, 0, 0
+        while done != 1:
+            polls += 1
+            assert polls < 200000
+            done, st = g.solve_poll()
+            if done == -1:
+                idle += 1
+                g.solve_step(1)
+            elif done == 0:
+                time.sleep(1e-4)
+        torch.cuda.synchronize()
+        assert st.status == st_ref.status and st.cycles == st_ref.cycles, (kw, st, st_ref)
+        assert idle >= 1
+        assert torch.equal(p, ref), (precision, method, kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bicgstab_restart_path_matches_oracle(precision):
+    """The near-breakdown restart forced from the host (breakdown_tol 0.3): at a fixed step
+    count the GPU takes the same restarts as the oracle (FP64) and its iterate agrees to 1e-9;
+    converged, both precisions reach the oracle's solution."""
+    torch = _torch()
+    wl, P, g, counts = _pair("spheres48")
+    if precision == "mixed":
+        g, _ = _setup(wl, precision="mixed")
+    f = P.rhs(*wl.velocity())
+    fd = torch.from_numpy(f).cuda()
+    act = P.types() != 2
+    if precision == "fp64":
+        pr, sr = P.solve(f, fixed_cycles=6, method="bicgstab", breakdown_tol=0.3)
+        pg, sg = g.poisson_solve(fd, fixed_cycles=6, method="bicgstab", breakdown_tol=0.3)
+        assert sr.restarts >= 1 and sg.restarts == sr.restarts
+        assert _rel(pg.cpu().numpy(), pr, act) <= 1e-9
+    pr, sr = P.solve(f, rel_tol=1e-12, max_cycles=400, method="bicgstab")
+    pg, sg = g.poisson_solve(fd, rel_tol=1e-12, max_cycles=400, method="bicgstab", precision=precision,
+                             breakdown_tol=0.3)
+    assert sg.status == 0 and sg.restarts >= 1
+    assert _rel(pg.cpu().numpy(), pr, act) <= (1e-9 if precision == "fp64" else 1e-8)
+
+
+def test_solve_stats_ghost_residual_and_setup_time():
+    """ghost_residual_max is the largest ghost-equation residual of the returned pressure
+    (recomputed here with the oracle's ghost equations); t_setup is the handle's last
+    geometry set-up time."""
+    torch = _torch()
+    wl, P, g, counts = _pair("spheres48")
+    fd = torch.from_numpy(P.rhs(*wl.velocity())).cuda()
+    for method in ("vcycle", "bicgstab"):
+        pg, sg = g.poisson_solve(fd, rel_tol=1e-10, method=method)
+        p = pg.cpu().numpy()
+        ref = P.ghost_refresh(p)
+        gc = P.ghost_cells()
+        want = np.max(np.abs(ref.ravel()[gc] - p.ravel()[gc]))
+        assert abs(sg.ghost_residual_max - want) <= 1e-12 * max(1.0, np.abs(p).max())
+        assert sg.ghost_residual_max <= 1e-6 * np.abs(p).max()
+        assert 0.0 < sg.t_setup < 10.0

@@ -307,3 +307,21 @@ def test_manufactured_solution_orders(stretched):
     c = [r["l2"] / r["h"] for r in res]
     assert max(c) / min(c) < 1.1
     assert res[-1]["l2"] < 0.002 and res[-1]["linf"] < 0.01
+
+
+def test_bicgstab_restarts_reach_the_same_solution():
+    """With a breakdown threshold so large that near-breakdowns are declared often, the
+    oracle's BiCGStab restarts its shadow residual several times and still converges to the
+    dense bordered solution (the restart changes the Krylov path, not the fixed point)."""
+    wl = I.sphere_small(8, level=3)
+    P = OracleProblem.from_workload(wl)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(P.shape) * (P.types() == 0)
+    p0, s0 = P.solve(f, rel_tol=1e-13, max_cycles=300, method="bicgstab")
+    p1, s1 = P.solve(f, rel_tol=1e-13, max_cycles=300, method="bicgstab", breakdown_tol=0.9)
+    assert s0.status == 0 and s1.status == 0
+    assert s0.restarts == 0 and s1.restarts >= 2
+    pd, lam = dense_bordered_solution(P, f)
+    act = P.types() != 2
+    for p in (p0, p1):
+        assert np.max(np.abs(p[act] - pd[act])) <= 1e-11 * np.max(np.abs(pd[act]))

@@ -1,6 +1,8 @@
 """Serving loop: trace generation and admission arithmetic on the CPU; on the GPU, served
-results equal the same requests run alone (bit for bit), match the oracle, and the summed
-footprint of the requests in flight never exceeds the budget."""
+results equal the same requests run alone (bit for bit), match the oracle at every
+configured grid size, the accounted device bytes (resident workspaces of every slot's grid
+cache plus what the requests in flight hold) never exceed the budget, and a failing request
+is returned as an error while the others are served."""
 import numpy as np
 import pytest
 
@@ -94,25 +96,80 @@ def test_served_projection_matches_oracle():
     assert np.max(np.abs(pg[act] - pr[act])) <= 1e-9 * np.max(np.abs(pr[act]))
 
 
+_oracle_cache = {}
+
+
+def _oracle_projection(q, u, v, w):
+    from oracle import OracleProblem
+    if q.rid not in _oracle_cache:
+        P = OracleProblem(q.xf, q.yf, q.zf)
+        P.set_mesh(q.verts, q.tris)
+        P.classify()
+        P.build_stencils()
+        u1, v1, w1, pr, sr, f = P.project(u, v, w, dt=1.0, rel_tol=1e-12, max_cycles=400, method="bicgstab")
+        assert sr.status == 0
+        _oracle_cache[q.rid] = (P.types(), u1, pr)
+    return _oracle_cache[q.rid]
+
+
 @pytest.mark.gpu
-def test_admission_keeps_footprint_within_budget():
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-8)])
+def test_served_each_size_matches_oracle(precision, tol):
+    """One request of every configured grid size (64^3 to 256^3, 1-4 bodies) served through
+    the loop in both precisions, against the oracle's projection solved to 1e-12."""
+    torch = _torch()
+    from paper_2505_17287_amd import serve
+    reqs, seen = serve.make_trace(16, qps=None), set()
+    pick = []
+    for q in reqs:
+        if q.shape[0] not in seen:
+            seen.add(q.shape[0])
+            pick.append(q)
+    assert sorted(seen) == [64, 128, 192, 256]
+    print("served sizes", [q.name for q in pick], flush=True)
+    srv = serve.Server(slots=2, precision=precision, rel_tol=1e-12, keep_results=True)
+    try:
+        res, _ = srv.run(pick)
+        fields = {}
+        for q in pick:
+            with torch.cuda.stream(srv.slots[0].stream):
+                fields[q.rid] = tuple(a.cpu().numpy() for a in srv._velocity(q))
+    finally:
+        srv.close()
+    for q, r in zip(pick, res):
+        assert r.status == 0, (q.name, r.error)
+        u, v, w = fields[q.rid]
+        t, u1, pr = _oracle_projection(q, u, v, w)
+        err_u = np.max(np.abs(r.u - u1)) / np.max(np.abs(u1))
+        act = t != 2
+        pg = r.p - r.p[act].mean()
+        pref = pr - pr[act].mean()
+        err_p = np.max(np.abs(pg[act] - pref[act])) / np.max(np.abs(pref[act]))
+        print("served", q.name, precision, "steps", r.cycles, "err_u %.2e err_p %.2e" % (err_u, err_p), flush=True)
+        assert err_u <= tol and err_p <= tol
+
+
+@pytest.mark.gpu
+def test_admission_keeps_resident_and_inflight_within_budget():
+    """A budget too small for every slot to keep its grids: the server releases cached grids
+    of idle slots (least recently used first) and the accounted bytes, resident workspaces
+    plus the requests in flight, stay within the budget at every admission and every
+    workspace change."""
     _torch()
     from paper_2505_17287_amd import serve
-    trace = serve.make_trace(6, qps=None, sizes=SMALL)
+    trace = serve.make_trace(8, qps=None, sizes=SMALL)
     fps = {q.rid: serve.footprint(q, "mixed") for q in trace}
     budget = max(fps.values()) + min(fps.values()) // 2   # room for one large or two small requests at most
     srv = serve.Server(slots=4, budget_bytes=budget, precision="mixed")
     try:
-        res, _ = srv.run(trace)
+        res, _ = srv.run(trace, log_events=True)
+        assert srv.resident_bytes() <= budget
     finally:
         srv.close()
-    events = sorted([(r.admitted, fps[r.rid]) for r in res] + [(r.done, -fps[r.rid]) for r in res],
-                    key=lambda e: (e[0], e[1]))
-    live = 0
-    for _, d in events:
-        live += d
-        assert live <= budget
     assert all(r.status == 0 for r in res)
+    assert any(e[0] == "evict" for e in srv.events)
+    for what, total, resident, inflight in srv.events:
+        assert total <= budget, (what, total, budget)
     # a request larger than the whole budget is refused before anything runs
     small = serve.Server(slots=1, budget_bytes=min(fps.values()) - 1, precision="mixed")
     try:
@@ -120,3 +177,31 @@ def test_admission_keeps_footprint_within_budget():
             small.run(trace[:1])
     finally:
         small.close()
+
+
+@pytest.mark.gpu
+def test_failed_request_is_isolated():
+    """A request whose mesh is not closed fails with IBM_E_GEOMETRY and is returned as an
+    error result; the requests before and after it, on the same slots, are served and equal
+    the same requests served without it."""
+    _torch()
+    from paper_2505_17287_amd import ibm, serve
+    trace = serve.make_trace(5, qps=None, sizes=SMALL)
+    bad = trace[2]
+    tris = bad.tris.copy()
+    tris[7] = tris[7][::-1]
+    broken = serve.Request(bad.rid, bad.arrival, bad.xf, bad.yf, bad.zf, bad.verts, tris, bad.vel_seed, "broken")
+    mixed = trace[:2] + [broken] + trace[3:]
+    srv = serve.Server(slots=2, precision="mixed", keep_results=True)
+    try:
+        res, _ = srv.run(mixed)
+        ok = [q for q in trace if q.rid != bad.rid]
+        ref, _ = srv.run(ok)
+    finally:
+        srv.close()
+    by = {r.rid: r for r in res}
+    assert by[bad.rid].status == ibm.IBM_E_GEOMETRY and "IBM_E_GEOMETRY" in by[bad.rid].error
+    for r in ref:
+        assert by[r.rid].status == 0 and np.array_equal(by[r.rid].p, r.p)
+    summary = serve.summarize(res, 1.0)
+    assert summary["failed"] == 1 and not summary["all_converged"]
