@@ -51,33 +51,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, cycles_needed, n_sample_cycles=3):
-    """The oracle as it stands on the same workload: classification, stencils, right-hand
-    side, a sample of V-cycles and the correction, timed on the host; the V-cycle time is
-    scaled to the number of cycles the full solve needs."""
+def oracle_reference(wl):
+    """The oracle as it stands, on the same workload, as the CPU baseline and as the accuracy
+    reference of the timed results.  Timed: classification, ghost stencils and multigrid
+    hierarchy (once), then the whole projection (right-hand side, BiCGStab preconditioned by
+    one V-cycle to relative residual 1e-10 from p = 0, the same solver and tolerance as the GPU
+    step, correction), median of 3.  Not timed: a converged solve (1e-12) as the accuracy
+    reference, one BiCGStab step on one thread (per-step time against all threads), and the
+    host's STREAM triad bandwidth.  The converged solve starts from the 1e-10 result."""
     import numpy as np
     from oracle import OracleProblem
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    P = OracleProblem(wl.xf, wl.yf, wl.zf)
-    P.set_mesh(wl.verts, wl.tris)
+    from oracle.oracle import set_threads, stream_triad_gbs, threads
+    nthr = threads()
     u, v, w = wl.velocity()
     t0 = time.perf_counter()
+    P = OracleProblem(wl.xf, wl.yf, wl.zf)
+    P.set_mesh(wl.verts, wl.tris)
     P.classify()
     P.build_stencils()
-    t1 = time.perf_counter()
-    f = P.rhs(u, v, w)
+    P.levels()  # the multigrid hierarchy
+    t_setup = time.perf_counter() - t0
+    runs = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        u1, v1, w1, p10, st10, f = P.project(u, v, w, dt=1.0, rel_tol=1e-10, method="bicgstab")
+        runs.append(time.perf_counter() - t1)
+    t_proj = float(np.median(runs))
+    pc, stc = P.solve(f, p0=p10, rel_tol=1e-12, max_cycles=400, method="bicgstab")
     t2 = time.perf_counter()
-    p, st = P.solve(f, fixed_cycles=n_sample_cycles)
-    t3 = time.perf_counter()
-    P.correct(u, v, w, p)
-    t4 = time.perf_counter()
-    per_cycle = (t3 - t2) / n_sample_cycles
-    t_step = (t1 - t0) + (t2 - t1) + per_cycle * cycles_needed + (t4 - t3)
-    del np
-    return {"value": 1.0 / t_step, "unit": "projections/s", "cores": threads, "kind": "oracle",
-            "sample": "one projection of the same 256^3 workload with %d of its %d V-cycles timed "
-                      "(classification %.2fs, stencils+hierarchy, %.3fs per V-cycle, scaled)"
-                      % (n_sample_cycles, cycles_needed, t1 - t0, per_cycle)}
+    P.solve(f, fixed_cycles=1, method="bicgstab")
+    t_step_all = time.perf_counter() - t2
+    set_threads(1)
+    try:
+        t3 = time.perf_counter()
+        P.solve(f, fixed_cycles=1, method="bicgstab")
+        t_step_one = time.perf_counter() - t3
+    finally:
+        set_threads(nthr)
+    triad = stream_triad_gbs()
+    t_step = t_setup + t_proj
+    base = {"value": round(1.0 / t_step, 4), "unit": "projections/s", "cores": nthr, "kind": "oracle",
+            "sample": "the oracle's whole projection of the same %s workload: classification, ghost stencils and "
+                      "hierarchy %.2fs (once), then right-hand side + BiCGStab to rel-res 1e-10 (%d steps, V-cycle "
+                      "preconditioner) + correction, median of 3 runs %.2fs (runs %s)"
+                      % (wl.name, t_setup, st10.cycles, t_proj, ", ".join("%.2f" % r for r in runs)),
+            "setup_s": round(t_setup, 3), "projection_s_median": round(t_proj, 3), "steps": st10.cycles,
+            "one_thread": {"bicgstab_step_s": round(t_step_one, 3), "all_threads_step_s": round(t_step_all, 3),
+                           "speedup": round(t_step_one / t_step_all, 2)},
+            "stream_triad_GBs": round(triad, 1)}
+    refs = {"types": P.types(), "p10": p10, "u10": (u1, v1, w1), "steps10": st10.cycles, "pconv": pc,
+            "steps_conv": stc.cycles, "rel_conv": stc.rel_residual}
+    return base, refs
+
+
+def rel_err(p, pr, act):
+    """Max-norm relative difference of two pressures after aligning their gauges on the
+    active (fluid and ghost) cells."""
+    import numpy as np
+    a = p - p[act].mean()
+    b = pr - pr[act].mean()
+    return float(np.max(np.abs(a[act] - b[act])) / np.max(np.abs(b[act])))
 
 
 def probe(args):
@@ -139,7 +172,7 @@ def mixed_form(wl, u0, v0, w0, args):
         return g.project(*uvw, dt=1.0, p=p, rel_tol=1e-10, precision="mixed", method=args.method)[1]
 
     steps = max(1, min(args.steps, 5))
-    step(fresh_inputs(u0, v0, w0, 1)[0])
+    require_ok("mixed warmup", [step(fresh_inputs(u0, v0, w0, 1)[0])])
     inputs = fresh_inputs(u0, v0, w0, steps)
     torch.cuda.synchronize()
     g.set_profiling(True, stride=PROFILE_STRIDE)
@@ -149,15 +182,101 @@ def mixed_form(wl, u0, v0, w0, args):
     ms = (time.perf_counter() - t0) * 1000.0 / steps
     prof = g.profile()
     g.set_profiling(False)
+    require_ok("mixed timed", sts)
+    last = (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
     avg = prof["ms_fp32"] / max(prof["n_fp32"], 1)
     ach = SWEEP_BYTES["fp32"] * wl.ncells / (avg * 1e-3) / 1e9
     g.close()
     return {"value": round(1000.0 / ms, 3), "unit": "projections/s", "ms_per_step": round(ms, 3), "steps": steps,
             "dtype": "f32+f64", "outer_steps": int(np.median([s.cycles for s in sts])),
             "vcycles": int(np.median([s.vcycles for s in sts])),
-            "max_rel_residual": max(s.rel_residual for s in sts),
+            "max_rel_residual": max(s.rel_residual for s in sts), "all_status_ok": True,
             "sweep_fp32": {"achieved_GBs": round(ach, 1), "avg_launch_ms": round(avg, 5),
-                           "frac": round(ach / HBM_PEAK_GBS, 4), "launches_timed": prof["n_fp32"]}}
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "launches_timed": prof["n_fp32"]}}, last
+
+
+def require_ok(what, sts):
+    """Every projection of a timed (or warm-up) run must have converged: a failed solve is
+    not a measurement."""
+    bad = [(i, s.status, s.rel_residual) for i, s in enumerate(sts) if s.status != 0]
+    if bad:
+        raise SystemExit("bench: %s projections did not converge (index, status, rel-res): %s" % (what, bad))
+
+
+def tolerance_sweep(g, u0, v0, w0, tols=(1e-10, 1e-11, 1e-12), steps=3):
+    """The headline projection (FP64 grid) at tighter tolerances: outer steps, ms per
+    projection (median of `steps`, driver-timed) and the pressure of the last run, to set
+    the error against the converged oracle beside the cost."""
+    import numpy as np
+    import torch
+    p = torch.empty(g.shape, dtype=torch.float64, device=u0.device)
+    out = []
+    for tol in tols:
+        ts, sts = [], []
+        for uvw in fresh_inputs(u0, v0, w0, steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.classify()
+            g.build_ghost_stencils()
+            _, st = g.project(*uvw, dt=1.0, p=p, rel_tol=tol, precision="fp64", max_cycles=400)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            sts.append(st)
+        require_ok("tolerance %.0e" % tol, sts)
+        out.append(({"rel_tol": tol, "ms_per_step": round(1000.0 * float(np.median(ts)), 3),
+                     "outer_steps": int(np.median([s.cycles for s in sts])),
+                     "rel_residual": max(s.rel_residual for s in sts)}, p.cpu().numpy()))
+        log("tolerance %.0e: %.2f ms, %d steps" % (tol, out[-1][0]["ms_per_step"], out[-1][0]["outer_steps"]))
+    return out
+
+
+def large_form(args, n=384, steps=3):
+    """The same projection on the multi-body 384^3 workload (56.6M cells), FP64 and mixed:
+    projections/s timed by the driver (synchronised wall clock around `steps` projections)
+    and the fine sweep's algorithmic bandwidth from its HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2505_17287_amd import ibm
+    from paper_2505_17287_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    wl = I.multibody(n)
+    u0, v0, w0 = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in wl.velocity())
+    out = {"workload": wl.name, "cells": wl.ncells}
+    for prec in ("fp64", "mixed"):
+        g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision=prec)
+        g.set_geometry(wl.verts, wl.tris)
+        p = torch.empty(g.shape, dtype=torch.float64, device=dev)
+
+        def step(uvw):
+            g.classify()
+            g.build_ghost_stencils()
+            return g.project(*uvw, dt=1.0, p=p, rel_tol=1e-10, precision=prec)[1]
+
+        require_ok("%d^3 %s warmup" % (n, prec), [step(fresh_inputs(u0, v0, w0, 1)[0])])
+        inputs = fresh_inputs(u0, v0, w0, steps)
+        torch.cuda.synchronize()
+        g.set_profiling(True, stride=PROFILE_STRIDE)
+        t0 = time.perf_counter()
+        sts = [step(inputs[q]) for q in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        prof = g.profile()
+        g.set_profiling(False)
+        require_ok("%d^3 %s timed" % (n, prec), sts)
+        del inputs
+        kind = "fp64" if prec == "fp64" else "fp32"
+        avg = prof["ms_" + kind] / max(prof["n_" + kind], 1)
+        ach = SWEEP_BYTES[kind] * wl.ncells / (avg * 1e-3) / 1e9
+        out[prec] = {"value": round(1000.0 / ms, 3), "unit": "projections/s", "ms_per_step": round(ms, 3),
+                     "steps": steps, "outer_steps": int(np.median([s.cycles for s in sts])),
+                     "max_rel_residual": max(s.rel_residual for s in sts),
+                     "sweep_" + kind: {"achieved_GBs": round(ach, 1), "avg_launch_ms": round(avg, 5),
+                                       "frac": round(ach / HBM_PEAK_GBS, 4), "launches_timed": prof["n_" + kind]}}
+        log("%d^3 %s: %.2f ms/projection, sweep %.0f GB/s" % (n, prec, ms, ach))
+        g.close()
+    return out
 
 
 # Every PROFILE_STRIDE-th level-0 sweep of the timed steps is bracketed by HIP events (on its
@@ -460,20 +579,25 @@ def main():
     for q in range(args.warmup):
         counts, ng, st = step(fresh_inputs(u0, v0, w0, 1)[0])
         log("warmup", q, "steps", st.cycles, "vcycles", st.vcycles, "rel", st.rel_residual, "status", st.status)
+        require_ok("warmup", [st])
     inputs = fresh_inputs(u0, v0, w0, args.steps)
     torch.cuda.synchronize()
     g.set_profiling(True, stride=PROFILE_STRIDE)
     t0 = time.perf_counter()
-    cyc, vcyc = [], []
+    sts = []
     for q in range(args.steps):
         counts, ng, st = step(inputs[q])
-        cyc.append(st.cycles)
-        vcyc.append(st.vcycles)
+        sts.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    del inputs
     prof = g.profile()
     g.set_profiling(False)
+    require_ok("timed", sts)
+    cyc, vcyc = [s.cycles for s in sts], [s.vcycles for s in sts]
+    # the last timed projection's results, compared with the oracle below
+    last = (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
+    types_gpu = g.cell_types().cpu().numpy()
+    del inputs
     ms = (t1 - t0) * 1000.0 / args.steps
     value = 1000.0 / ms
 
@@ -506,24 +630,55 @@ def main():
         "config": {"workload": wl.name, "cells": wl.ncells, "triangles": int(len(wl.tris)),
                    "fluid_ghost_dead": [int(x) for x in counts], "ghosts": int(ng),
                    "method": args.method, "outer_steps": int(np.median(cyc)), "vcycles": int(np.median(vcyc)),
-                   "rel_tol": 1e-10, "precision": args.precision,
+                   "rel_tol": 1e-10, "precision": args.precision, "all_status_ok": True,
+                   "max_rel_residual": max(s.rel_residual for s in sts),
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
+    mixed_last, sweep = None, []
     if not args.no_forms:
-        out["forms"] = {"mixed": mixed_form(wl, u0, v0, w0, args),
-                        "momentum": momentum_form(wl, args),
-                        "paper_solver": paper_solver_form(wl, u0, v0, w0, args),
-                        "moving": moving_form(wl, args),
-                        "serving": None}
+        out["forms"] = {}
+        out["forms"]["mixed"], mixed_last = mixed_form(wl, u0, v0, w0, args)
+        if args.precision == "fp64":
+            sweep = tolerance_sweep(g, u0, v0, w0)
+        out["forms"]["momentum"] = momentum_form(wl, args)
+        out["forms"]["paper_solver"] = paper_solver_form(wl, u0, v0, w0, args)
+        out["forms"]["moving"] = moving_form(wl, args)
+        out["forms"]["serving"] = None
         try:
             out["forms"]["serving"] = serving_form(args)
         except Exception as e:  # reported in the JSON line; the other forms stand
             out["forms"]["serving"] = {"error": "%s: %s" % (type(e).__name__, e)}
             log("serving form failed: %s" % e)
+        g.close()
+        del u0, v0, w0, p
+        torch.cuda.empty_cache()
+        if args.n == 256:
+            out["forms"]["large_384"] = large_form(args)
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, int(np.median(vcyc)))
+        log("cpu baseline and accuracy reference (oracle) ...")
+        base, refs = oracle_reference(wl)
+        out["cpu_baseline"] = base
+        act = refs["types"] != 2
+        uref = refs["u10"][0]
+
+        def errs(pu):
+            pg, ug = pu
+            return {"p_vs_oracle_same_tol": rel_err(pg, refs["p10"], act),
+                    "p_vs_oracle_converged": rel_err(pg, refs["pconv"], act),
+                    "u_vs_oracle_same_tol": float(np.max(np.abs(ug - uref)) / np.max(np.abs(uref)))}
+
+        out["err_vs_oracle"] = errs(last)
+        out["err_vs_oracle"].update({"types_equal": bool(np.array_equal(types_gpu, refs["types"])),
+                                     "oracle_steps_same_tol": refs["steps10"],
+                                     "oracle_converged": {"rel_tol": 1e-12, "rel_residual": refs["rel_conv"],
+                                                          "extra_steps_from_1e-10": refs["steps_conv"]}})
+        if mixed_last is not None:
+            out["forms"]["mixed"]["err_vs_oracle"] = errs(mixed_last)
+        if sweep:
+            out["tolerance_sweep"] = [dict(row, p_vs_oracle_converged=rel_err(pt, refs["pconv"], act))
+                                      for row, pt in sweep]
+        log("accuracy:", json.dumps(out["err_vs_oracle"]))
         if not args.no_forms:
             log("cpu baselines of the forms (oracle) ...")
             out["forms"]["momentum"]["cpu_baseline"] = momentum_cpu_baseline(wl)

@@ -1591,3 +1591,35 @@ int orc_project(orc_problem *P, double *u, double *v, double *w, double dt, doub
     if (div_max) *div_max = orc_div_max(P, u, v, w);
     return s;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* host memory bandwidth for the CPU baseline's context: STREAM triad a = b + s c over n  */
+/* doubles with the OpenMP threads in use; returns the best of `reps` runs in GB/s        */
+/* (24 bytes moved per element).                                                        */
+/* ------------------------------------------------------------------------------------ */
+#include <omp.h>
+
+double orc_stream_triad(int64_t n, int reps) {
+    double *a = (double *)malloc(sizeof(double) * (size_t)n);
+    double *b = (double *)malloc(sizeof(double) * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!a || !b || !c) { free(a); free(b); free(c); return -1.0; }
+#pragma omp parallel for
+    for (int64_t i = 0; i < n; ++i) { a[i] = 0.0; b[i] = 1.0; c[i] = 2.0; }
+    double best = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        double t0 = omp_get_wtime();
+#pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) a[i] = b[i] + 3.0 * c[i];
+        double t = omp_get_wtime() - t0;
+        double gbs = 24.0 * (double)n / t / 1e9;
+        if (gbs > best) best = gbs;
+    }
+    volatile double sink = a[n / 2];
+    (void)sink;
+    free(a); free(b); free(c);
+    return best;
+}
+
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n); }

@@ -80,6 +80,10 @@ def _L():
         lib.orc_destroy.argtypes = [P]
         lib.orc_set_mesh.argtypes = [P, dp, C.c_int64, C.c_void_p, C.c_int64]
         lib.orc_classify.argtypes = [P, C.c_void_p]
+        lib.orc_stream_triad.restype = C.c_double
+        lib.orc_stream_triad.argtypes = [C.c_int64, C.c_int]
+        lib.orc_threads.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_odd_columns.restype = C.c_int64
         lib.orc_odd_columns.argtypes = [P]
         lib.orc_num_ghosts.restype = C.c_int64
@@ -290,3 +294,18 @@ class OracleProblem:
         p, st = self.solve(f, **kw)
         u2, v2, w2 = self.correct(u, v, w, p, dt)
         return u2, v2, w2, p, st, f
+
+
+def stream_triad_gbs(n: int = 1 << 27, reps: int = 5) -> float:
+    """Host memory bandwidth (STREAM triad, GB/s) with the oracle's OpenMP threads."""
+    return float(_L().orc_stream_triad(int(n), int(reps)))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_L().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the oracle's OpenMP thread count (process-wide)."""
+    _L().orc_set_threads(int(n))
