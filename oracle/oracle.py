@@ -12,7 +12,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-lib_path = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c to load instead (the sanitizer test's build)
+_OVERRIDE = os.environ.get("ORACLE_LIB")
+lib_path = _OVERRIDE or os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 
@@ -24,6 +26,16 @@ def build_oracle(force: bool = False) -> str:
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, lib_path)
     return lib_path
+
+
+def build_oracle_sanitized(out: str, src: str = _SRC) -> str:
+    """Compile oracle.c (or another C file, `src`) with AddressSanitizer and
+    UndefinedBehaviorSanitizer (gcc, -O1, every UB report fatal) into `out`; load it with
+    ORACLE_LIB=out in a process that has gcc's libasan preloaded."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", out, src, "-lm"])
+    return out
 
 
 class OracleOpts(C.Structure):
@@ -71,7 +83,8 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        build_oracle()
+        if not _OVERRIDE:
+            build_oracle()
         lib = C.CDLL(lib_path)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)

@@ -48,5 +48,43 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str) -> str:
+    """The library with its host code (argument checks, level planning, workspace layout,
+    mesh validation, schedules) built with AddressSanitizer and UndefinedBehaviorSanitizer;
+    the device code is built as usual (at -O1) and is not instrumented.  Load it with
+    IBM_LIB=<path> in a process that preloads clang's ASan runtime (asan_runtime()); it is
+    meant for the host entry points, on a machine without a GPU."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split()
+    host = ["-O1", "-g", "-fPIC", "-std=c++17", "-ffp-contract=off", "--offload-arch=gfx950",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", *san]
+
+    def compile_one(src):
+        obj = os.path.join(out_dir, src.replace(".hip", ".san.o"))
+        r = subprocess.run([HIPCC, *host, "-c", os.path.join(SRC, src), "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc (sanitized host) failed for %s:\n%s" % (src, r.stderr))
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    out = os.path.join(out_dir, "libibm_san.so")
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *san,
+                        "-Xarch_host", "-shared-libsan", "-o", out, *objs], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n%s" % r.stderr)
+    return out
+
+
+def asan_runtime() -> str:
+    """clang's shared ASan runtime of the ROCm toolchain (preloaded for build_host_sanitized)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found under /opt/rocm/llvm")
+    return hits[-1]
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

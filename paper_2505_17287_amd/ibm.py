@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libibm.so")
+# IBM_LIB names another build of the library to load instead (the sanitized host build)
+LIB_PATH = os.environ.get("IBM_LIB") or os.path.join(_HERE, "libibm.so")
 
 IBM_OK, IBM_NOT_CONVERGED = 0, 1
 IBM_E_ARG, IBM_E_STATE, IBM_E_GEOMETRY, IBM_E_NOMEM, IBM_E_DEVICE, IBM_E_NUMERIC = -1, -2, -3, -4, -5, -6

@@ -1,6 +1,7 @@
 """Host logic: the library's check that a body mesh is closed and consistently oriented
 (every undirected edge used by exactly two triangles, once in each direction), compiled
-from its header with the host compiler and run on small meshes with known answers."""
+from its header with the host compiler (plain, and with AddressSanitizer and
+UndefinedBehaviorSanitizer) and run on small meshes with known answers."""
 import os
 import shutil
 import subprocess
@@ -37,8 +38,14 @@ def _cube():
     return np.array(tris, dtype=np.int32)
 
 
-@pytest.fixture(scope="module")
-def checker(tmp_path_factory):
+# the plain build, and one with AddressSanitizer (leak detection on) and
+# UndefinedBehaviorSanitizer, every report fatal
+BUILDS = {"plain": [], "asan_ubsan": ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                                      "-fno-sanitize-recover=undefined"]}
+
+
+@pytest.fixture(scope="module", params=sorted(BUILDS))
+def checker(tmp_path_factory, request):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no host C++ compiler")
@@ -46,7 +53,8 @@ def checker(tmp_path_factory):
     src = d / "drv.cpp"
     src.write_text(DRIVER)
     exe = d / "drv"
-    subprocess.run([gxx, "-O1", "-std=c++17", "-I", os.path.dirname(HDR), str(src), "-o", str(exe)], check=True)
+    subprocess.run([gxx, "-O1", "-std=c++17", *BUILDS[request.param], "-I", os.path.dirname(HDR), str(src),
+                    "-o", str(exe)], check=True)
 
     def run(cases):
         text = "".join("%d %d %s\n" % (nv, len(t), " ".join(map(str, np.asarray(t).ravel()))) for nv, t in cases)
