@@ -3,6 +3,8 @@
 // Kept in a file of its own: it is the kernel the bandwidth figures are quoted for.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "ibm_impl.hpp"
 
@@ -284,12 +286,17 @@ __global__ void __launch_bounds__(BXT *BY)
         IBM_RED_PAIR(k0, q1, q2, q3, so[1], pb0, pb1, !(S));                                                       \
         q1 = load(k0 + 5);                                                                                         \
         int buf = 0;                                                                                               \
-        for (int k = k0; k < k1; k += SW_QD) {                                                                     \
+        for (int k = k0; k < k1; k += SW_QD) { /* leaves as soon as plane k1 - 1 is done */                     \
             IBM_STEP(q2, q3, q4, k, (S));                                                                          \
+            if (k + 1 >= k1) break;                                                                                \
             IBM_STEP(q3, q4, q5, k + 1, !(S));                                                                     \
+            if (k + 2 >= k1) break;                                                                                \
             IBM_STEP(q4, q5, q0, k + 2, (S));                                                                      \
+            if (k + 3 >= k1) break;                                                                                \
             IBM_STEP(q5, q0, q1, k + 3, !(S));                                                                     \
+            if (k + 4 >= k1) break;                                                                                \
             IBM_STEP(q0, q1, q2, k + 4, (S));                                                                      \
+            if (k + 5 >= k1) break;                                                                                \
             IBM_STEP(q1, q2, q3, k + 5, !(S));                                                                     \
         }                                                                                                          \
     }
@@ -301,6 +308,7 @@ __global__ void __launch_bounds__(BXT *BY)
 }
 
 constexpr int SW_BXT = 32;
+constexpr int SW_CHUNK_COST = 4;  // plane steps a z chunk costs beyond its own planes
 
 // Tiles of 64 x BY columns (interior 60 x (BY - 4)).  The paired path (nx even) uses 32 rows:
 // one 1024-thread workgroup per CU, 12 % fewer halo rows re-read than two 16-row tiles; the
@@ -310,16 +318,29 @@ static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, T *pout, co
     constexpr int TXC = 2 * SW_BXT - 4, TY = BY - 4;
     const int ntx = (F.nx + TXC - 1) / TXC, nty = (F.ny + TY - 1) / TY;
     const int64_t per_slab = (int64_t)ntx * nty;
-    // Chunk the z range so the whole launch is resident at once (1024 threads per CU):
-    // each chunk re-reads three planes it shares with its neighbours, so chunks are made as
-    // long as the residency allows, and a second partial round of workgroups never forms.
-    const int slots = (1024 / (SW_BXT * BY)) * device_cu_count();
-    int nchunk = (int)(slots / per_slab);
-    if (nchunk > F.nz) nchunk = F.nz;
-    if (nchunk < 1) nchunk = 1;
-    int kc = (F.nz + nchunk - 1) / nchunk;
-    if (kc < 16 && F.nz >= 16) kc = 16;
-    if (kc > SW_KC_MAX) kc = SW_KC_MAX;
+    // Z chunks: a launch is rounds of resident workgroups (1024 threads per CU); a chunk of kc
+    // planes costs about kc + SW_CHUNK_COST plane steps (three planes shared with its
+    // neighbours, the two red planes of the prologue, the pipeline fill).  The chunk count
+    // minimises rounds x (kc + SW_CHUNK_COST): one round when the tiles fill the CUs, else
+    // several rounds of shorter chunks rather than a partly idle single round.  Workgroups
+    // are ordered chunk by chunk, so those running together on one XCD are neighbouring tiles
+    // at the same depth and share their halo lines in its L2.
+    const int64_t slots = (int64_t)(1024 / (SW_BXT * BY)) * device_cu_count();
+    const int kmin = std::min(16, F.nz);
+    int nchunk = 1;
+    int64_t best = -1;
+    for (int c = 1; c <= F.nz; ++c) {
+        const int kcc = (F.nz + c - 1) / c;
+        if (kcc > SW_KC_MAX) continue;
+        if (kcc < kmin) break;
+        const int64_t rounds = (per_slab * c + slots - 1) / slots;
+        const int64_t cost = rounds * (kcc + SW_CHUNK_COST);
+        if (best < 0 || cost < best) {
+            best = cost;
+            nchunk = c;
+        }
+    }
+    const int kc = (F.nz + nchunk - 1) / nchunk;
     nchunk = (F.nz + kc - 1) / kc;
     const int ntiles = (int)(per_slab * nchunk);
     const int grid = ((ntiles + 7) / 8) * 8;
