@@ -62,6 +62,9 @@ struct Coarse {  // coarse-level view in precision T
 // fused red-black sweep of level 0 (sweep.hip): pout = one RB-GS sweep of pin
 template <typename T>
 hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s);
+// the same FP32 sweep writing its result widened to FP64, dead cells zero
+hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *pout, const float *f, const float *lam,
+                              hipStream_t s);
 
 // fused red-black sweep of a coarse level (sweepc.hip): eout = one RB-GS sweep of L.e, the
 // two buffers distinct; for levels with an even row length and at least 2^19 cells

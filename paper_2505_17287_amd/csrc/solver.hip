@@ -8,6 +8,8 @@
 // pass writes.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <utility>
 
@@ -29,9 +31,11 @@ namespace ibm {
 // group sums its terms with three shuffle steps.  Degenerate ghosts (mean of the fluid
 // 26-neighbours) are handled by the group's first lane.
 constexpr int REFRESH_NT = 256;
-template <typename T>
+// T: precision of the cycle (each new value is rounded to it); TS, TD: types of the two
+// buffers (TD wider than T only after the widening last sweep of the mixed cycle).
+template <typename T, typename TS = T, typename TD = T>
 __global__ void __launch_bounds__(REFRESH_NT)
-    k_ghost_refresh(GhostView G, const T *__restrict__ src_ghost, T *dst, int nx, int ny, int nz,
+    k_ghost_refresh(GhostView G, const TS *__restrict__ src_ghost, TD *dst, int nx, int ny, int nz,
                     const uint8_t *__restrict__ type, const double *__restrict__ gh) {
     const int64_t g = ((int64_t)blockIdx.x * REFRESH_NT + threadIdx.x) >> 3;
     const int m = threadIdx.x & 7;
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(REFRESH_NT)
     } else {
         v = gh ? term + hg : term;
     }
-    dst[cell] = (T)v;
+    dst[cell] = (TD)(T)v;
 }
 
 static GhostView ghost_view(ibm_grid *g) {
@@ -92,6 +96,16 @@ static hipError_t launch_refresh(ibm_grid *g, const T *src_ghost, T *dst, const 
     hipLaunchKernelGGL(k_ghost_refresh<T>, dim3((unsigned)((8 * g->ng + REFRESH_NT - 1) / REFRESH_NT)),
                        dim3(REFRESH_NT), 0, s, ghost_view(g),
                        src_ghost, dst, g->nx, g->ny, g->nz, g->type, gh);
+    return hipGetLastError();
+}
+
+// the refresh after the widening last sweep of the mixed cycle: FP32 arithmetic as in
+// launch_refresh<float>, members read from the FP32 input and the FP64 result
+static hipError_t launch_refresh_widen(ibm_grid *g, const float *src_ghost, double *dst, const double *gh,
+                                       hipStream_t s) {
+    if (g->ng == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ghost_refresh<float, float, double>), dim3((unsigned)((8 * g->ng + REFRESH_NT - 1) / REFRESH_NT)),
+                       dim3(REFRESH_NT), 0, s, ghost_view(g), src_ghost, dst, g->nx, g->ny, g->nz, g->type, gh);
     return hipGetLastError();
 }
 
@@ -1193,9 +1207,13 @@ static hipError_t smooth_level(ibm_grid *g, int l, int nsweeps, hipStream_t s) {
 
 template <typename T>
 static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, const T *lam, const double *gh,
-                              const ibm_solve_opts *o, hipStream_t s, const T *start = nullptr) {
+                              const ibm_solve_opts *o, hipStream_t s, const T *start = nullptr,
+                              double *wide = nullptr) {
     // start (requires nu1 > 0): the iterate the first pre-smoothing sweep reads instead of
     // bufs[*cur]; it is only read, and the sweeps continue in bufs
+    // wide (FP32 cycle with nu2 > 0): the last post-smoothing sweep and its ghost refresh
+    // write the result widened to FP64 there instead of into bufs (that sweep is not timed:
+    // it moves 17 bytes per cell, not 13)
     const Fine<T> F = FineOf<T>::get(g);
     hipError_t e;
     for (int q = 0; q < o->nu1; ++q) {
@@ -1297,6 +1315,12 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
     }
     for (int q = 0; q < o->nu2; ++q) {
         T *pin = bufs[*cur], *pout = bufs[1 - *cur];
+        if constexpr (std::is_same<T, float>::value) {
+            if (wide && q + 1 == o->nu2) {
+                if ((e = launch_sweep_widen(F, pin, wide, rhs, lam, s)) != hipSuccess) return e;
+                return launch_refresh_widen(g, pin, wide, gh, s);
+            }
+        }
         if ((e = timed_sweep<T>(g, F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
         if ((e = launch_refresh<T>(g, pin, pout, gh, s)) != hipSuccess) return e;
         *cur = 1 - *cur;
@@ -1757,26 +1781,35 @@ __global__ void k_krylov_finalize_dots(const double *part, int nb, int ns, const
 }
 
 // pd = r + beta (pd - omega v) on fluid + ghost cells
+// r32 (mixed precision, else null): the FP32 right-hand side of the preconditioner, the
+// fluid part of the result rounded to FP32 and zero elsewhere
 __global__ void k_p_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
-                           const double *__restrict__ v, double *pd, const Scalars *sc) {
+                           const double *__restrict__ v, double *pd, const Scalars *sc, float *r32) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
-    if (type[id] == T_DEAD) {
+    const uint8_t ty = type[id];
+    if (ty == T_DEAD) {
         pd[id] = 0.0;
+        if (r32) r32[id] = 0.0f;
         return;
     }
     const double beta = sc->beta, omega = sc->omega;
-    __builtin_nontemporal_store(r[id] + beta * (pd[id] - omega * v[id]), pd + id);
+    const double pv = r[id] + beta * (pd[id] - omega * v[id]);
+    __builtin_nontemporal_store(pv, pd + id);
+    if (r32) r32[id] = (ty == T_FLUID) ? (float)pv : 0.0f;
 }
 
 // The BiCGStab vector updates write their full-field results with non-temporal stores (see
 // the operator pass).
 // s = r - alpha v
 __global__ void k_s_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
-                           const double *__restrict__ v, double *s, const Scalars *sc) {
+                           const double *__restrict__ v, double *s, const Scalars *sc, float *r32) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
-    __builtin_nontemporal_store((type[id] == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id], s + id);
+    const uint8_t ty = type[id];
+    const double sv = (ty == T_DEAD) ? 0.0 : r[id] - sc->alpha * v[id];
+    __builtin_nontemporal_store(sv, s + id);
+    if (r32) r32[id] = (ty == T_FLUID) ? (float)sv : 0.0f;
 }
 
 // x += alpha y + omega z ; r = s - omega t ; partials of rh.r (all), r.r (fluid) and r.r (all)
@@ -1828,12 +1861,6 @@ __global__ void k_precond_ghosts(int64_t ng, const int32_t *__restrict__ gcell, 
     // a degenerate ghost takes the mean of its (zero) fluid neighbours
     ea[cell] = (flags[g] & GF_DEGENERATE) ? T(0) : (T)h;
 }
-// FP32 right-hand side of the mixed preconditioner
-__global__ void k_narrow(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r, float *r32) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    r32[id] = (type[id] == T_FLUID) ? (float)r[id] : 0.0f;
-}
 __global__ void k_widen(const uint8_t *__restrict__ type, int64_t N, const float *__restrict__ e, double *y) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
@@ -1853,18 +1880,21 @@ static hipError_t precondition(ibm_grid *g, const double *r, double *ya, double 
     // cells, written here), which the first sweep only reads: no field is cleared per call.
     if (o->precision == IBM_MIXED) {
         const bool st = o->nu1 > 0;
+        // g->r32 already holds the FP32 fluid part of r: the update kernel that formed r
+        // (k_p_update, k_s_update) wrote it beside r
         float *e0 = st ? g->pz32 : g->e32a;
         if (!st) hipLaunchKernelGGL(k_precond_zero<float>, dim3(nbN), dim3(256), 0, s, g->N, g->e32a, g->e32b);
-        hipLaunchKernelGGL(k_narrow, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, g->r32);
         if (g->ng > 0)
             hipLaunchKernelGGL(k_precond_ghosts<float>, dim3(nbG), dim3(256), 0, s, g->ng, g->g_cell, g->g_flags,
                                g->g_scale, r, g->g_rhs, e0);
         float *eb[2] = {g->e32a, g->e32b};
         int ecur = 0;
-        if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s, st ? e0 : nullptr)) !=
-            hipSuccess)
+        // with post-smoothing, the last sweep writes the FP64 result itself
+        double *wide = o->nu2 > 0 ? ya : nullptr;
+        if ((e = vcycle_impl<float>(g, eb, &ecur, g->r32, &g->sc->zero32, g->g_rhs, o, s, st ? e0 : nullptr,
+                                    wide)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
+        if (!wide) hipLaunchKernelGGL(k_widen, dim3(nbN), dim3(256), 0, s, g->type, g->N, eb[ecur], ya);
         *out = ya;
     } else if (o->method == IBM_BICGSTAB_SRJ) {
         // scheduled relaxed Jacobi: every sweep writes all cells of the other buffer; the first
@@ -1959,11 +1989,12 @@ hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStrea
     double *ya = g->kv[6], *yb = g->kv[7], *za = g->kv[8], *zb = g->kv[9];
     const unsigned nbN = (unsigned)nblk(g->N);
     hipError_t e;
-    hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc);
+    float *r32 = o->precision == IBM_MIXED ? g->r32 : nullptr;  // FP32 right-hand side of the mixed cycle
+    hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc, r32);
     double *y = nullptr, *z = nullptr;
     if ((e = precondition(g, pd, ya, yb, &y, o, s)) != hipSuccess) return e;
     if ((e = apply_projected(g, y, v, rh, 0, K_ALPHA, o->breakdown_tol, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_s_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, sv, g->sc);
+    hipLaunchKernelGGL(k_s_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, sv, g->sc, r32);
     if ((e = precondition(g, sv, za, zb, &z, o, s)) != hipSuccess) return e;
     if ((e = apply_projected(g, z, t, sv, 1, K_OMEGA, o->breakdown_tol, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_xr_update, dim3(RED_BLOCKS), dim3(NORM_NT), 0, s, g->type, g->N, x, y, z, sv, t, r, rh, g->sc,

@@ -53,6 +53,8 @@ struct SweepPlane<T, true> {
     uint16_t tt;
     __device__ __forceinline__ bool fl0() const { return (uint8_t)tt == T_FLUID; }
     __device__ __forceinline__ bool fl1() const { return tt < 256; }
+    __device__ __forceinline__ bool dd0() const { return (uint8_t)tt == T_DEAD; }
+    __device__ __forceinline__ bool dd1() const { return (tt >> 8) == T_DEAD; }
 };
 template <typename T>
 struct SweepPlane<T, false> {
@@ -60,6 +62,8 @@ struct SweepPlane<T, false> {
     uint8_t t0, t1;
     __device__ __forceinline__ bool fl0() const { return t0 == T_FLUID; }
     __device__ __forceinline__ bool fl1() const { return t1 == T_FLUID; }
+    __device__ __forceinline__ bool dd0() const { return t0 == T_DEAD; }
+    __device__ __forceinline__ bool dd1() const { return t1 == T_DEAD; }
 };
 
 constexpr int SW_KC_MAX = 512;  // longest z chunk of one workgroup
@@ -91,14 +95,18 @@ __device__ __forceinline__ T rb_update(T am, T ap, T bm, T bp, T cm, T cp, T dxy
 // Every thread issues the same loads for every plane (addresses clamped into the grid,
 // values of cells outside it replaced by zero), which keeps the in-order memory counter
 // exact: the loads of a plane are issued four plane steps before they are first used.
-template <typename T, int BXT, int BY, bool VEC>
+// TO: type of the result.  A wider TO than T (FP32 sweep, FP64 result) is the last sweep of
+// the mixed-precision cycle, whose result the FP64 outer iteration takes as it is: each value
+// is widened exactly and dead cells are written as zero.
+template <typename T, typename TO, int BXT, int BY, bool VEC>
 __global__ void __launch_bounds__(BXT *BY)
-    k_rbgs_fused(Fine<T> F, const T *__restrict__ pin, T *__restrict__ pout, const T *__restrict__ f,
+    k_rbgs_fused(Fine<T> F, const T *__restrict__ pin, TO *__restrict__ pout, const T *__restrict__ f,
                  const T *__restrict__ lamp, int ntx, int nty, int kc, int ntiles) {
     static_assert(BXT == 32 && BY % 4 == 0, "two same-parity rows of 32 threads per wave");
     using V = typename Vec2<T>::type;
     using PD = SweepPlane<T, VEC>;
-    typedef T NV __attribute__((ext_vector_type(2)));  // native pair for the streaming store
+    typedef TO NV __attribute__((ext_vector_type(2)));  // native pair for the streaming store
+    constexpr bool WIDEN = sizeof(TO) != sizeof(T);
     constexpr int NC = 2 * BXT;  // columns of a tile including the 2-column halo
     constexpr int TXC = NC - 4, TY = BY - 4;
     // LDS planes with a guard ring (one row above and below, one column on the left, two on
@@ -244,19 +252,24 @@ __global__ void __launch_bounds__(BXT *BY)
         const bool kst_ = (k) < k1;                                                                                \
         if constexpr (VEC) { /* a pair is wholly inside or outside the tile interior: blk0 == blk1 */             \
             if (kst_ && blk0) { /* FP64: non-temporal (the pass does not re-read it; measured faster) */       \
-                const NV o_ = {out0, out1};                                                                        \
-                if constexpr (sizeof(T) == 8)                                                                      \
+                NV o_;                                                                                             \
+                if constexpr (WIDEN)                                                                               \
+                    o_ = NV{(A).dd0() ? TO(0) : (TO)out0, (A).dd1() ? TO(0) : (TO)out1};                           \
+                else                                                                                               \
+                    o_ = NV{out0, out1};                                                                           \
+                if constexpr (sizeof(TO) == 8)                                                                     \
                     __builtin_nontemporal_store(o_, reinterpret_cast<NV *>(pout + id_));                           \
                 else                                                                                               \
                     *reinterpret_cast<NV *>(pout + id_) = o_;                                                      \
             }                                                                                                      \
         } else if (kst_) {                                                                                         \
-            if constexpr (sizeof(T) == 8) {                                                                        \
-                if (blk0) __builtin_nontemporal_store(out0, pout + id_);                                           \
-                if (blk1) __builtin_nontemporal_store(out1, pout + id_ + 1);                                       \
+            const TO w0_ = (WIDEN && (A).dd0()) ? TO(0) : (TO)out0, w1_ = (WIDEN && (A).dd1()) ? TO(0) : (TO)out1; \
+            if constexpr (sizeof(TO) == 8) {                                                                       \
+                if (blk0) __builtin_nontemporal_store(w0_, pout + id_);                                            \
+                if (blk1) __builtin_nontemporal_store(w1_, pout + id_ + 1);                                        \
             } else {                                                                                               \
-                if (blk0) pout[id_] = out0;                                                                        \
-                if (blk1) pout[id_ + 1] = out1;                                                                    \
+                if (blk0) pout[id_] = w0_;                                                                         \
+                if (blk1) pout[id_ + 1] = w1_;                                                                     \
             }                                                                                                      \
         }                                                                                                          \
         pa0 = pb0;                                                                                                 \
@@ -313,8 +326,8 @@ constexpr int SW_CHUNK_COST = 4;  // plane steps a z chunk costs beyond its own 
 // Tiles of 64 x BY columns (interior 60 x (BY - 4)).  The paired path (nx even) uses 32 rows:
 // one 1024-thread workgroup per CU, 12 % fewer halo rows re-read than two 16-row tiles; the
 // unpaired path keeps 16 rows (its larger register set would spill at 1024 threads).
-template <typename T, int BY, bool VEC>
-static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
+template <typename T, typename TO, int BY, bool VEC>
+static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, TO *pout, const T *f, const T *lam, hipStream_t s) {
     constexpr int TXC = 2 * SW_BXT - 4, TY = BY - 4;
     const int ntx = (F.nx + TXC - 1) / TXC, nty = (F.ny + TY - 1) / TY;
     const int64_t per_slab = (int64_t)ntx * nty;
@@ -344,15 +357,21 @@ static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, T *pout, co
     nchunk = (F.nz + kc - 1) / kc;
     const int ntiles = (int)(per_slab * nchunk);
     const int grid = ((ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_rbgs_fused<T, SW_BXT, BY, VEC>), dim3(grid), dim3(SW_BXT * BY), 0, s, F, pin, pout, f, lam,
+    hipLaunchKernelGGL((k_rbgs_fused<T, TO, SW_BXT, BY, VEC>), dim3(grid), dim3(SW_BXT * BY), 0, s, F, pin, pout, f, lam,
                        ntx, nty, kc, ntiles);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
-    if ((F.nx & 1) == 0) return launch_sweep_tiles<T, 32, true>(F, pin, pout, f, lam, s);
-    return launch_sweep_tiles<T, 16, false>(F, pin, pout, f, lam, s);
+    if ((F.nx & 1) == 0) return launch_sweep_tiles<T, T, 32, true>(F, pin, pout, f, lam, s);
+    return launch_sweep_tiles<T, T, 16, false>(F, pin, pout, f, lam, s);
+}
+
+hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *pout, const float *f, const float *lam,
+                              hipStream_t s) {
+    if ((F.nx & 1) == 0) return launch_sweep_tiles<float, double, 32, true>(F, pin, pout, f, lam, s);
+    return launch_sweep_tiles<float, double, 16, false>(F, pin, pout, f, lam, s);
 }
 
 template hipError_t launch_sweep<double>(const Fine<double> &, const double *, double *, const double *,
