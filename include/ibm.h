@@ -279,6 +279,26 @@ ibm_status ibm_get_dirichlet_weights(const ibm_grid *g, void *stream, double *be
 ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, double *hu, double *hv, double *hw,
                              const ibm_momentum_opts *o, ibm_momentum_stats *s, void *stream);
 
+/* ---- fractional step: momentum half-step then projection (Section 2.1) ----------------
+   The half-step advances cell-centred components and the projection corrects face-normal
+   velocities.  A whole step is: ibm_momentum_step (u*), ibm_cell_to_faces (U* on the faces),
+   ibm_project (p, corrected U), ibm_correct_cells (the cell-centred u^{n+1}). */
+
+/* Face-normal velocities from cell-centred components: on every interior face the linear
+   interpolation between the two centres, (w_b u_a + w_a u_b) / (w_a + w_b) with w the cell
+   widths across the face (the interpolation of the convective term); faces on the box walls
+   0.  u, v, w: device [nz][ny][nx]; uf [nz][ny][nx+1], vf [nz][ny+1][nx], wf [nz+1][ny][nx]:
+   device, out.  Needs a bound workspace.  Enqueued on `stream`, no synchronisation. */
+ibm_status ibm_cell_to_faces(ibm_grid *g, const double *u, const double *v, const double *w, double *uf, double *vf,
+                             double *wf, void *stream);
+
+/* Cell-centred velocity correction matching the projection's face correction: on fluid
+   cells u_c -= (delta_{c-1/2} + delta_{c+1/2}) / 2 along x (v along y, w along z), where
+   delta_f = dt (p_b - p_a) / d_f is what ibm_project subtracts on face f (0 on box walls);
+   ghost and dead cells unchanged.  u, v, w: device [nz][ny][nx], in place; p: device, the
+   projection's pressure.  Needs classification.  Enqueued on `stream`, no synchronisation. */
+ibm_status ibm_correct_cells(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt, void *stream);
+
 /* ---- moving bodies: fresh cells (Section 2.2) ---------------------------------------- */
 
 /* Move the body to new vertex positions (host; same conventions and checks as

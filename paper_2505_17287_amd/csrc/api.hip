@@ -844,6 +844,30 @@ ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, 
     return rs;
 }
 
+// ---- fractional-step composition ---------------------------------------------------------
+
+ibm_status ibm_cell_to_faces(ibm_grid *g, const double *u, const double *v, const double *w, double *uf, double *vf,
+                             double *wf, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_cell_to_faces: NULL handle");
+    if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_cell_to_faces before ibm_bind_workspace");
+    if (!u || !v || !w || !uf || !vf || !wf) return fail(g, IBM_E_ARG, "ibm_cell_to_faces: NULL field");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(cell_to_faces_pass(g, u, v, w, uf, vf, wf, s), "cell to faces");
+    return IBM_OK;
+}
+
+ibm_status ibm_correct_cells(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt, void *stream) {
+    if (!g) return fail(nullptr, IBM_E_ARG, "ibm_correct_cells: NULL handle");
+    if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_correct_cells before ibm_classify");
+    if (!u || !v || !w || !p) return fail(g, IBM_E_ARG, "ibm_correct_cells: NULL field");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(g, IBM_E_ARG, "dt must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+    HIP_TRY(correct_cells_pass(g, u, v, w, p, dt, s), "correct cells");
+    return IBM_OK;
+}
+
 // ---- step API --------------------------------------------------------------------------
 
 ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, void *stream) {

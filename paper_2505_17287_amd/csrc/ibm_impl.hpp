@@ -354,6 +354,10 @@ hipError_t gauge_pass(ibm_grid *g, const double *pcur, double *pdst, hipStream_t
 hipError_t ghost_residual_pass(ibm_grid *g, const double *p, hipStream_t s);
 hipError_t rhs_pass(ibm_grid *g, const double *u, const double *v, const double *w, double dt, double *f,
                     hipStream_t s);
+hipError_t cell_to_faces_pass(ibm_grid *g, const double *u, const double *v, const double *w, double *uf,
+                              double *vf, double *wf, hipStream_t s);
+hipError_t correct_cells_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt,
+                              hipStream_t s);
 hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt,
                         hipStream_t s);
 hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const double *w, hipStream_t s);

@@ -1469,6 +1469,69 @@ hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const doub
     return hipGetLastError();
 }
 
+// Fractional-step composition (cell-centred momentum, face-normal projection).
+// Face velocities from cell-centred components: on every interior face along d the linear
+// interpolation between the two centres, (w_b u_a + w_a u_b) / (w_a + w_b) with w the cell
+// widths along d; box-wall faces 0 (no flux through the box, as in the convective term).
+__global__ void k_cell_to_faces(int nx, int ny, int nz, int d, const double *__restrict__ wd,
+                                const double *__restrict__ uc, double *uf) {
+    const int fx = nx + (d == 0), fy = ny + (d == 1), fz = nz + (d == 2);
+    const int64_t NF = (int64_t)fx * fy * fz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= NF) return;
+    int i, j, k;
+    unflatten(id, fx, fy, i, j, k);
+    const int q = (d == 0) ? i : (d == 1) ? j : k;
+    const int n = (d == 0) ? nx : (d == 1) ? ny : nz;
+    if (q == 0 || q == n) {
+        uf[id] = 0.0;
+        return;
+    }
+    const int64_t b = ((int64_t)k * ny + j) * nx + i;
+    const int64_t a = b - ((d == 0) ? 1 : (d == 1) ? (int64_t)nx : (int64_t)nx * ny);
+    const double wa = wd[q - 1], wb = wd[q];
+    uf[id] = (wb * uc[a] + wa * uc[b]) / (wa + wb);
+}
+
+// Cell-centred correction: on fluid cells u_c -= (delta_{c-1/2} + delta_{c+1/2}) / 2, where
+// delta_f = dt (p_b - p_a) / d_f is the correction the projection applies to face f (the
+// same arithmetic as k_correct) and 0 on box walls.
+__global__ void k_correct_cells(const uint8_t *__restrict__ type, int nx, int ny, int nz, int d,
+                                const double *__restrict__ dc, const double *__restrict__ p, double dt, double *uc) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N || type[id] != T_FLUID) return;
+    int i, j, k;
+    unflatten(id, nx, ny, i, j, k);
+    const int q = (d == 0) ? i : (d == 1) ? j : k;
+    const int n = (d == 0) ? nx : (d == 1) ? ny : nz;
+    const int64_t st = (d == 0) ? 1 : (d == 1) ? (int64_t)nx : (int64_t)nx * ny;
+    const double dm = (q > 0) ? dt * (p[id] - p[id - st]) / dc[q] : 0.0;
+    const double dp = (q < n - 1) ? dt * (p[id + st] - p[id]) / dc[q + 1] : 0.0;
+    uc[id] -= 0.5 * (dm + dp);
+}
+
+hipError_t cell_to_faces_pass(ibm_grid *g, const double *u, const double *v, const double *w, double *uf,
+                              double *vf, double *wf, hipStream_t s) {
+    const double *c[3] = {u, v, w};
+    double *f[3] = {uf, vf, wf};
+    for (int d = 0; d < 3; ++d) {
+        const int64_t NF = (int64_t)(g->nx + (d == 0)) * (g->ny + (d == 1)) * (g->nz + (d == 2));
+        hipLaunchKernelGGL(k_cell_to_faces, dim3(nblk(NF)), dim3(256), 0, s, g->nx, g->ny, g->nz, d, g->w0[d], c[d],
+                           f[d]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t correct_cells_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt,
+                              hipStream_t s) {
+    double *c[3] = {u, v, w};
+    for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL(k_correct_cells, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, d,
+                           g->dc0[d], p, dt, c[d]);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(NORM_NT) k_divmax(Fine<double> F, const double *__restrict__ u,
                                                     const double *__restrict__ v, const double *__restrict__ w,
                                                     double *partials) {

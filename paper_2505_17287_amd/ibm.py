@@ -123,6 +123,8 @@ def lib():
         L.ibm_momentum_step.argtypes = [vp] + [vp] * 6 + [C.POINTER(MomentumOpts), C.POINTER(MomentumStats), vp]
         L.ibm_move_geometry.argtypes = [vp, dp, i64, vp, i64, vp, vp, vp]
         L.ibm_fill_fresh.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ibm_cell_to_faces.argtypes = [vp] * 8
+        L.ibm_correct_cells.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
         L.ibm_get_fresh.argtypes = [vp, vp] + [vp] * 7
         L.ibm_destroy_grid.argtypes = [vp]
         L.ibm_last_error.restype = C.c_char_p
@@ -434,6 +436,43 @@ class Grid:
             code = self._check(lib().ibm_momentum_step(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]), _tptr(H[0]),
                                                        _tptr(H[1]), _tptr(H[2]), C.byref(o), C.byref(st), self._s()))
         return code, st
+
+    # fractional step: momentum half-step, then projection
+    def face_shapes(self):
+        nz, ny, nx = self.shape
+        return (nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)
+
+    def cell_to_faces(self, U, faces=None):
+        """Face-normal velocities (uf, vf, wf) from the cell-centred U (3, nz, ny, nx)."""
+        self._field(U, "U")
+        if faces is None:
+            faces = tuple(self.torch.empty(sh, dtype=self.torch.float64, device=self.device) for sh in self.face_shapes())
+        for a, nm in zip(faces, ("uf", "vf", "wf")):
+            self._field(a, nm)
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_cell_to_faces(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]), *(_tptr(a) for a in faces),
+                                                self._s()))
+        return faces
+
+    def correct_cells(self, U, p, dt):
+        """u_c -= mean of its two face corrections, on fluid cells (in place)."""
+        self._field(U, "U")
+        self._field(p, "p")
+        with self.torch.cuda.device(self.device):
+            self._check(lib().ibm_correct_cells(self._h, _tptr(U[0]), _tptr(U[1]), _tptr(U[2]), _tptr(p), float(dt),
+                                                self._s()))
+        return U
+
+    def fractional_step(self, U, H, nu, dt, p=None, first_step=False, m=8, mom_rel_tol=1e-10, **project_kw):
+        """One fractional step on the device: advection-diffusion half-step of the cell-centred
+        U (in u^n, out u^{n+1}) and H (in H^{n-1}, out H^n), face interpolation of u*, the
+        projection of the faces and the cell-centred correction.  Returns (faces, p,
+        momentum stats, projection stats); the faces hold the projected U^{n+1}."""
+        code, mst = self.momentum_step(U, H, nu, dt, first_step=first_step, m=m, rel_tol=mom_rel_tol)
+        faces = self.cell_to_faces(U)
+        p, pst = self.project(*faces, dt=dt, p=p, **project_kw)
+        self.correct_cells(U, p, dt)
+        return faces, p, mst, pst
 
     # moving bodies
     def move_geometry(self, verts, tris):
