@@ -183,7 +183,7 @@ def mixed_form(wl, u0, v0, w0, args):
     prof = g.profile()
     g.set_profiling(False)
     require_ok("mixed timed", sts)
-    last = (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
+    last = None if args.no_cpu_baseline else (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
     avg = prof["ms_fp32"] / max(prof["n_fp32"], 1)
     ach = SWEEP_BYTES["fp32"] * wl.ncells / (avg * 1e-3) / 1e9
     g.close()
@@ -594,9 +594,12 @@ def main():
     g.set_profiling(False)
     require_ok("timed", sts)
     cyc, vcyc = [s.cycles for s in sts], [s.vcycles for s in sts]
-    # the last timed projection's results, compared with the oracle below
-    last = (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
-    types_gpu = g.cell_types().cpu().numpy()
+    # the last timed projection's results, compared with the oracle below (copied to the
+    # host only when the oracle runs)
+    last, types_gpu = None, None
+    if not args.no_cpu_baseline:
+        last = (p.cpu().numpy(), inputs[-1][0].cpu().numpy())
+        types_gpu = g.cell_types().cpu().numpy()
     del inputs
     ms = (t1 - t0) * 1000.0 / args.steps
     value = 1000.0 / ms

@@ -19,6 +19,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibm.so")
 SOURCES = ["geometry.hip", "sweep.hip", "sweepc.hip", "finepass.hip", "solver.hip", "momentum.hip", "noalloc.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]  # named host ranges (roctx)
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
@@ -40,7 +41,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
@@ -71,7 +72,7 @@ def build_host_sanitized(out_dir: str) -> str:
         objs = list(ex.map(compile_one, SOURCES))
     out = os.path.join(out_dir, "libibm_san.so")
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *san,
-                        "-Xarch_host", "-shared-libsan", "-o", out, *objs], capture_output=True, text=True)
+                        "-Xarch_host", "-shared-libsan", "-o", out, *objs, *LIBS], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("sanitized link failed:\n%s" % r.stderr)
     return out

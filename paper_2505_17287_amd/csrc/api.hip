@@ -13,12 +13,24 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ibm_impl.hpp"
 #include "mesh_check.hpp"
 
 using namespace ibm;
 
 namespace {
+
+// A named host range around each entry point that enqueues device work and around each outer
+// iteration of a solve: `rocprofv3 --marker-trace` shows them above the kernels they launch.
+// Without a tool attached the calls return at once.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 thread_local std::string t_last_error;
 
@@ -316,6 +328,7 @@ size_t ibm_grid_workspace_bytes(const ibm_grid *gc, int64_t nv_max, int64_t nt_m
 
 ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64_t nv_max, int64_t nt_max,
                               int64_t max_ghosts, ibm_precision prec, void *stream) {
+    Range range_("ibm_bind_workspace");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_bind_workspace: NULL handle");
     if (!device_ptr || ((uintptr_t)device_ptr & 255)) return fail(g, IBM_E_ARG, "workspace must be 256-byte aligned");
     if (nv_max < 3 || nt_max < 1 || max_ghosts < 0) return fail(g, IBM_E_ARG, "invalid mesh / ghost capacities");
@@ -362,6 +375,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
 
 ibm_status ibm_set_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                             void *stream) {
+    Range range_("ibm_set_geometry");
     return set_geometry_impl(g, verts, nv, tris, nt, stream, false);
 }
 
@@ -449,6 +463,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
 }
 
 ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
+    Range range_("ibm_classify");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_classify: NULL handle");
     if (g->stage < ST_GEOMETRY) return fail(g, IBM_E_STATE, "ibm_classify before ibm_set_geometry");
     const double t_in = now_s();
@@ -485,6 +500,7 @@ ibm_status ibm_classify(ibm_grid *g, void *stream, int64_t counts_out[3]) {
 }
 
 ibm_status ibm_build_ghost_stencils(ibm_grid *g, void *stream, int64_t *n_ghost_out) {
+    Range range_("ibm_build_ghost_stencils");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_build_ghost_stencils: NULL handle");
     if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_build_ghost_stencils before ibm_classify");
     const double t_in = now_s();
@@ -676,6 +692,7 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
     if (hs->ref > 0.0 && (o->fixed_cycles > 0 || rel > o->rel_tol)) {
         const int nit = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
         for (it = 1; it <= nit; ++it) {
+            Range step_range("bicgstab step");
             HIP_TRY(krylov_step(g, x, o, s), "bicgstab step");
             HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
             HIP_TRY(hipStreamSynchronize(s), "step sync");
@@ -810,12 +827,14 @@ extern "C" {
 
 ibm_status ibm_poisson_solve(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, ibm_solve_stats *s,
                              void *stream) {
+    Range range_("ibm_poisson_solve");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_poisson_solve: NULL handle");
     return solve_core(g, rhs, p, o, s, (hipStream_t)stream);
 }
 
 ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, double *p, const ibm_solve_opts *o,
                        ibm_solve_stats *st, void *stream) {
+    Range range_("ibm_project");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_project: NULL handle");
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_project before ibm_build_ghost_stencils");
     if (!u || !v || !w || !p) return fail(g, IBM_E_ARG, "NULL velocity or pressure");
@@ -848,6 +867,7 @@ ibm_status ibm_project(ibm_grid *g, double *u, double *v, double *w, double dt, 
 
 ibm_status ibm_cell_to_faces(ibm_grid *g, const double *u, const double *v, const double *w, double *uf, double *vf,
                              double *wf, void *stream) {
+    Range range_("ibm_cell_to_faces");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_cell_to_faces: NULL handle");
     if (g->stage < ST_BOUND) return fail(g, IBM_E_STATE, "ibm_cell_to_faces before ibm_bind_workspace");
     if (!u || !v || !w || !uf || !vf || !wf) return fail(g, IBM_E_ARG, "ibm_cell_to_faces: NULL field");
@@ -858,6 +878,7 @@ ibm_status ibm_cell_to_faces(ibm_grid *g, const double *u, const double *v, cons
 }
 
 ibm_status ibm_correct_cells(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt, void *stream) {
+    Range range_("ibm_correct_cells");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_correct_cells: NULL handle");
     if (g->stage < ST_CLASSIFIED) return fail(g, IBM_E_STATE, "ibm_correct_cells before ibm_classify");
     if (!u || !v || !w || !p) return fail(g, IBM_E_ARG, "ibm_correct_cells: NULL field");
@@ -871,6 +892,7 @@ ibm_status ibm_correct_cells(ibm_grid *g, double *u, double *v, double *w, const
 // ---- step API --------------------------------------------------------------------------
 
 ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, void *stream) {
+    Range range_("ibm_solve_begin");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_solve_begin: NULL handle");
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_solve_begin before ibm_build_ghost_stencils");
     ibm_status cs = check_opts(g, o);
@@ -901,6 +923,7 @@ ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_
 }
 
 ibm_status ibm_solve_step(ibm_grid *g, int n_cycles) {
+    Range range_("ibm_solve_step");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_solve_step: NULL handle");
     SolveState &S = g->ss;
     if (!S.active || S.done) return fail(g, IBM_E_STATE, "no solve in flight");
@@ -1163,6 +1186,7 @@ ibm_status ibm_get_dirichlet_weights(const ibm_grid *gc, void *stream, double *b
 
 ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, double *hu, double *hv, double *hw,
                              const ibm_momentum_opts *o, ibm_momentum_stats *st, void *stream) {
+    Range range_("ibm_momentum_step");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_momentum_step: NULL handle");
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_momentum_step before ibm_build_ghost_stencils");
     if (!o) return fail(g, IBM_E_ARG, "NULL options");
@@ -1252,6 +1276,7 @@ ibm_status ibm_momentum_step(ibm_grid *g, double *u, double *v, double *w, doubl
 
 ibm_status ibm_move_geometry(ibm_grid *g, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                              void *stream, int64_t counts_out[3], int64_t *n_fresh_out) {
+    Range range_("ibm_move_geometry");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_move_geometry: NULL handle");
     if (g->stage < ST_STENCILS) return fail(g, IBM_E_STATE, "ibm_move_geometry before a first geometry's stencils");
     hipStream_t s = (hipStream_t)stream;
@@ -1299,6 +1324,7 @@ ibm_status ibm_get_fresh(const ibm_grid *gc, void *stream, int32_t *cell, double
 }
 
 ibm_status ibm_fill_fresh(ibm_grid *g, double *u, double *v, double *w, const double *ubi, void *stream) {
+    Range range_("ibm_fill_fresh");
     if (!g) return fail(nullptr, IBM_E_ARG, "ibm_fill_fresh: NULL handle");
     if (!u || !v || !w) return fail(g, IBM_E_ARG, "NULL velocity array");
     hipStream_t s = (hipStream_t)stream;
