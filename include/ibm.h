@@ -216,8 +216,18 @@ ibm_status ibm_solve_begin(ibm_grid *g, const double *rhs, double *p, const ibm_
 ibm_status ibm_solve_step(ibm_grid *g, int n_cycles);
 ibm_status ibm_solve_poll(ibm_grid *g, int *done, ibm_solve_stats *s);
 
-/* Level count and dims of the multigrid hierarchy (after build_ghost_stencils). */
+/* Level count and dims of the multigrid hierarchy (planned at ibm_create_grid from the face
+   coordinates alone; host call). */
 ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims /* 3*n_levels, may be NULL */);
+
+/* Child map of hierarchy level `level` (1 .. n_levels-1) along `axis` (0 x, 1 y, 2 z): coarse
+   index I holds the cells cs[I] .. cs[I+1]-1 of level - 1 (one or two).  cs: host, receives
+   dims[axis] + 1 ints.  The hierarchy coarsens by cell width (Section 2.1 leaves the solver's
+   multigrid to the implementation): level l merges two neighbouring cells of level l-1 along an
+   axis with at least 4 cells when their combined width is at most 3.5 x 2^(l-1) h_min (h_min the
+   smallest cell width of the grid), scanning from the low wall, and stops when nothing merges or
+   the coarse levels would together exceed half the grid's cell count.  Host call. */
+ibm_status ibm_get_level_map(const ibm_grid *g, int level, int axis, int *cs);
 
 /* ---- advection-diffusion half-step (Section 2.1) with Dirichlet ghost rows (2.2) ---- */
 

@@ -48,7 +48,9 @@
 typedef struct {
     int n[3];
     double *f[3], *c[3], *w[3]; /* faces (n+1), centres, widths */
-    int halved[3];              /* halved relative to the next finer level */
+    int halved[3];              /* some cells merged relative to the next finer level */
+    int *cs[3];                 /* coarse index I holds the finer cells cs[I] .. cs[I+1]-1 */
+    int *par[3];                /* (finer level) the coarse index holding each cell */
     uint8_t *active;
     double *T[3];               /* integrated transmissibility of each cell's low face */
     double *e, *R, *r;
@@ -167,7 +169,7 @@ static void free_hierarchy(orc_problem *P) {
         level_t *L = &P->lev[l];
         for (int d = 0; d < 3; ++d) {
             free(L->f[d]); free(L->c[d]); free(L->w[d]); free(L->T[d]);
-            free(L->plo[d]); free(L->phi[d]); free(L->pt[d]);
+            free(L->plo[d]); free(L->phi[d]); free(L->pt[d]); free(L->cs[d]); free(L->par[d]);
         }
         free(L->active); free(L->e); free(L->R); free(L->r);
         memset(L, 0, sizeof(*L));
@@ -912,24 +914,35 @@ static double min_width(const level_t *L, int d) {
     return m;
 }
 
-/* Semi-coarsening: an axis is coarsenable when its count is even and >= 4; among the
-   coarsenable axes, halve those whose smallest width is below 1.5x the smallest width of
-   any coarsenable axis.  Stop when no axis is coarsenable. */
-static int next_halving(const level_t *L, int halve[3]) {
-    double m = INFINITY;
-    int any = 0;
-    for (int d = 0; d < 3; ++d) {
-        halve[d] = 0;
-        if (L->n[d] >= 4 && L->n[d] % 2 == 0) m = fmin(m, min_width(L, d));
+/* Coarsening by cell width.  Along every axis with at least 4 cells, scanning from the low
+   wall, a cell is merged with the next one when their combined width is at most a threshold
+   t; every other cell is kept whole.  Level l (built from level l-1) starts from
+   t = MERGE_WIDTH x 2^(l-1) h_min (h_min: the smallest cell width of the grid over the axes
+   with at least two cells) and raises t by a factor 5/4 until the level holds at most half as
+   many cells as level l-1 or every axis is halved outright.  So the narrowest cells merge
+   first: on a uniform axis this is plain halving, and in a stretched region the cells already
+   wide along one axis are kept along it while they are still merged along the others, so
+   coarse cells tend to equal widths and point smoothing keeps working.  The hierarchy stops
+   when no axis merges a cell or after LEVEL_CAP levels.  merge_axis returns the coarse count
+   and fills cs. */
+#define LEVEL_CAP 24
+#define MERGE_WIDTH 3.5
+static int merge_axis(const level_t *F, int d, double wmax, int *cs) {
+    const int n = F->n[d];
+    int m = 0, i = 0;
+    while (i < n) {
+        cs[m++] = i;
+        if (n >= 4 && i + 1 < n && F->w[d][i] + F->w[d][i + 1] <= wmax) i += 2;
+        else i += 1;
     }
-    for (int d = 0; d < 3; ++d)
-        if (L->n[d] >= 4 && L->n[d] % 2 == 0 && min_width(L, d) < 1.5 * m) { halve[d] = 1; any = 1; }
-    return any;
+    cs[m] = n;
+    return m;
 }
 
 /* children range of coarse index I along an axis */
-static inline void child_range(int halved, int I, int *c0, int *c1) {
-    if (halved) { *c0 = 2 * I; *c1 = 2 * I + 1; } else { *c0 = I; *c1 = I; }
+static inline void child_range(const int *cs, int I, int *c0, int *c1) {
+    *c0 = cs[I];
+    *c1 = cs[I + 1] - 1;
 }
 
 static int build_hierarchy(orc_problem *P) {
@@ -952,17 +965,39 @@ static int build_hierarchy(orc_problem *P) {
                 if (L0->active[id]) P->vol_fluid += lvol(L0, i, j, k);
             }
     L0->vol_active = P->vol_fluid;
+    double hmin = INFINITY;
+    for (int d = 0; d < 3; ++d) if (L0->n[d] >= 2) hmin = fmin(hmin, min_width(L0, d));
     int nlev = 1;
-    while (nlev < MAXLEV) {
+    while (nlev < LEVEL_CAP) {
         level_t *F = &P->lev[nlev - 1];
-        int halve[3];
-        if (!next_halving(F, halve)) break;
         level_t *C = &P->lev[nlev];
+        const int64_t nf = (int64_t)F->n[0] * F->n[1] * F->n[2];
+        for (int d = 0; d < 3; ++d) C->cs[d] = ialloc(F->n[d] + 1);
+        double wmax = MERGE_WIDTH * ldexp(hmin, nlev - 1);
+        int any = 0;
+        for (int rise = 0; rise < 64; ++rise, wmax *= 1.25) {
+            int64_t nc = 1;
+            int full = 1;
+            any = 0;
+            for (int d = 0; d < 3; ++d) {
+                C->n[d] = merge_axis(F, d, wmax, C->cs[d]);
+                nc *= C->n[d];
+                any |= C->n[d] < F->n[d];
+                if (F->n[d] >= 4 && C->n[d] != (F->n[d] + 1) / 2) full = 0;
+            }
+            if (2 * nc <= nf || full) break;
+        }
+        for (int d = 0; d < 3; ++d) C->halved[d] = C->n[d] < F->n[d];
+        if (!any) {
+            for (int d = 0; d < 3; ++d) { free(C->cs[d]); C->cs[d] = NULL; }
+            break;
+        }
         for (int d = 0; d < 3; ++d) {
-            C->halved[d] = halve[d];
-            C->n[d] = halve[d] ? F->n[d] / 2 : F->n[d];
+            F->par[d] = ialloc(F->n[d]);
+            for (int I = 0; I < C->n[d]; ++I)
+                for (int i = C->cs[d][I]; i < C->cs[d][I + 1]; ++i) F->par[d][i] = I;
             C->f[d] = dalloc(C->n[d] + 1);
-            for (int q = 0; q <= C->n[d]; ++q) C->f[d][q] = F->f[d][halve[d] ? 2 * q : q];
+            for (int q = 0; q <= C->n[d]; ++q) C->f[d][q] = F->f[d][C->cs[d][q]];
             C->c[d] = dalloc(C->n[d]); C->w[d] = dalloc(C->n[d]);
             axis_metrics(C->n[d], C->f[d], C->c[d], C->w[d]);
         }
@@ -973,9 +1008,9 @@ static int build_hierarchy(orc_problem *P) {
             for (int J = 0; J < C->n[1]; ++J)
                 for (int I = 0; I < C->n[0]; ++I) {
                     int i0, i1, j0, j1, k0, k1, act = 0;
-                    child_range(halve[0], I, &i0, &i1);
-                    child_range(halve[1], J, &j0, &j1);
-                    child_range(halve[2], K, &k0, &k1);
+                    child_range(C->cs[0], I, &i0, &i1);
+                    child_range(C->cs[1], J, &j0, &j1);
+                    child_range(C->cs[2], K, &k0, &k1);
                     for (int k = k0; k <= k1; ++k)
                         for (int j = j0; j <= j1; ++j)
                             for (int i = i0; i <= i1; ++i) act |= F->active[LIDX(F, i, j, k)];
@@ -992,10 +1027,10 @@ static int build_hierarchy(orc_problem *P) {
                         int Ic[3] = {I, J, K};
                         int64_t cid = LIDX(C, I, J, K);
                         if (Ic[d] == 0) { C->T[d][cid] = 0.0; continue; }
-                        int fface = halve[d] ? 2 * Ic[d] : Ic[d];
+                        int fface = C->cs[d][Ic[d]];
                         int a0, a1, b0, b1;
-                        child_range(halve[e1], Ic[e1], &a0, &a1);
-                        child_range(halve[e2], Ic[e2], &b0, &b1);
+                        child_range(C->cs[e1], Ic[e1], &a0, &a1);
+                        child_range(C->cs[e2], Ic[e2], &b0, &b1);
                         double area = 0.0;
                         for (int b = b0; b <= b1; ++b)
                             for (int a = a0; a <= a1; ++a) {
@@ -1011,12 +1046,14 @@ static int build_hierarchy(orc_problem *P) {
                     }
         }
         /* prolongation tables for level nlev-1 from level nlev, per axis: value at fine
-           index i = (1-t) e[lo] + t e[hi] in physical coordinates, clamped at the walls */
+           index i = (1-t) e[lo] + t e[hi] in physical coordinates, lo the parent and hi the
+           parent's neighbour on the side of the fine centre (clamped at the walls); a cell
+           kept whole takes its parent alone */
         for (int d = 0; d < 3; ++d) {
             F->plo[d] = ialloc(F->n[d]); F->phi[d] = ialloc(F->n[d]); F->pt[d] = dalloc(F->n[d]);
             for (int i = 0; i < F->n[d]; ++i) {
-                if (!halve[d]) { F->plo[d][i] = i; F->phi[d][i] = i; F->pt[d][i] = 0.0; continue; }
-                int I = i / 2;
+                int I = F->par[d][i];
+                if (C->cs[d][I + 1] - C->cs[d][I] == 1) { F->plo[d][i] = I; F->phi[d][i] = I; F->pt[d][i] = 0.0; continue; }
                 double x = F->c[d][i], X = C->c[d][I];
                 int Jn = (x < X) ? I - 1 : I + 1;
                 if (Jn < 0 || Jn >= C->n[d]) { F->plo[d][i] = I; F->phi[d][i] = I; F->pt[d][i] = 0.0; continue; }
@@ -1040,6 +1077,14 @@ void orc_level_info(orc_problem *P, int l, int *dims, int *halved, double *vol_a
     for (int d = 0; d < 3; ++d) { dims[d] = L->n[d]; halved[d] = L->halved[d]; }
     *vol_active = L->vol_active;
 }
+/* children starts of level l >= 1 along axis d (n_l[d] + 1 entries) */
+void orc_level_map(orc_problem *P, int l, int d, int *cs) {
+    if (!P->nlev) build_hierarchy(P);
+    const level_t *L = &P->lev[l];
+    if (l < 1 || l >= P->nlev) return;
+    memcpy(cs, L->cs[d], sizeof(int) * (size_t)(L->n[d] + 1));
+}
+
 void orc_level_arrays(orc_problem *P, int l, uint8_t *active, double *Tx, double *Ty, double *Tz) {
     if (!P->nlev) build_hierarchy(P);
     level_t *L = &P->lev[l];
@@ -1112,9 +1157,9 @@ static void restrict_to(level_t *F, level_t *C, const double *rint) {
         for (int J = 0; J < C->n[1]; ++J)
             for (int I = 0; I < C->n[0]; ++I) {
                 int i0, i1, j0, j1, k0, k1;
-                child_range(C->halved[0], I, &i0, &i1);
-                child_range(C->halved[1], J, &j0, &j1);
-                child_range(C->halved[2], K, &k0, &k1);
+                child_range(C->cs[0], I, &i0, &i1);
+                child_range(C->cs[1], J, &j0, &j1);
+                child_range(C->cs[2], K, &k0, &k1);
                 double s = 0.0;
                 for (int k = k0; k <= k1; ++k)
                     for (int j = j0; j <= j1; ++j)
@@ -1152,7 +1197,7 @@ static void prolong_add(level_t *F, const level_t *C, double *target) {
                             s += (wx[a] * wy[b]) * wz[c] * C->e[cid];
                         }
                 if (!all) {
-                    int pi = C->halved[0] ? i / 2 : i, pj = C->halved[1] ? j / 2 : j, pk = C->halved[2] ? k / 2 : k;
+                    int pi = F->par[0][i], pj = F->par[1][j], pk = F->par[2][k];
                     s = C->e[LIDX(C, pi, pj, pk)];
                 }
                 target[fid] += s;

@@ -113,6 +113,7 @@ def _L():
         lib.orc_ghost_refresh.argtypes = [P, dp]
         lib.orc_num_levels.argtypes = [P]
         lib.orc_level_info.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p, dp]
+        lib.orc_level_map.argtypes = [P, C.c_int, C.c_int, C.c_void_p]
         lib.orc_level_arrays.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.orc_solve.argtypes = [P, dp, dp, C.POINTER(OracleOpts), C.POINTER(_Stats), C.c_void_p, C.c_int]
         lib.orc_rhs.argtypes = [P, dp, dp, dp, C.c_double, dp]
@@ -260,6 +261,17 @@ class OracleProblem:
             va = C.c_double()
             _L().orc_level_info(self._h, l, _vp(dims), _vp(hv), C.byref(va))
             out.append(dict(dims=tuple(int(x) for x in dims), halved=tuple(int(x) for x in hv), vol_active=va.value))
+        return out
+
+    def level_map(self, l):
+        """Children starts of level l >= 1 per axis: coarse index I holds the cells
+        cs[I] .. cs[I+1]-1 of level l-1."""
+        dims = self.levels()[l]["dims"]
+        out = []
+        for d in range(3):
+            cs = np.zeros(dims[d] + 1, dtype=np.int32)
+            _L().orc_level_map(self._h, l, d, _vp(cs))
+            out.append(cs)
         return out
 
     def level_arrays(self, l):

@@ -68,9 +68,33 @@ namespace ibm {
 
 ibm_status report_error(ibm_status st, const std::string &msg) { return fail(nullptr, st, msg); }
 
-// Semi-coarsening plan: an axis is coarsenable when its count is even and >= 4; among the
-// coarsenable axes, those whose smallest width is below 1.5x the smallest width of any
-// coarsenable axis are halved.  Coarse faces are every other fine face.
+// Coarsening by cell width.  Along every axis with at least 4 cells, scanning from the low
+// wall, a cell is merged with the next one when their combined width is at most a threshold
+// t; every other cell is kept whole.  Level l (built from level l-1) starts from
+// t = MERGE_WIDTH x 2^(l-1) h_min (h_min: the smallest cell width of the grid over the axes
+// with at least two cells) and raises t by a factor 5/4 until the level holds at most half as
+// many cells as level l-1 or every axis is halved outright, so the narrowest cells merge
+// first: uniform axes are halved, and in a stretched region cells already wide along one axis
+// are kept along it while they are still merged along the others, so coarse cells tend to
+// equal widths and point smoothing keeps working.  The plan stops when no axis merges a cell.
+// Coarse faces are the fine faces at the start of each coarse cell.
+constexpr double MERGE_WIDTH = 3.5;
+
+static int merge_axis(const std::vector<double> &w, double wmax, std::vector<int> &cs) {
+    const int n = (int)w.size();
+    cs.clear();
+    int i = 0;
+    while (i < n) {
+        cs.push_back(i);
+        if (n >= 4 && i + 1 < n && w[i] + w[i + 1] <= wmax)
+            i += 2;
+        else
+            i += 1;
+    }
+    cs.push_back(n);
+    return (int)cs.size() - 1;
+}
+
 void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, LevelHost *lev,
                  int *nlev) {
     LevelHost &L0 = lev[0];
@@ -78,8 +102,11 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
     L0.n[1] = ny;
     L0.n[2] = nz;
     const double *fs[3] = {xf, yf, zf};
+    double hmin = INFINITY;
     for (int d = 0; d < 3; ++d) {
         L0.halved[d] = 0;
+        L0.same[d] = 1;
+        L0.cs[d].clear();
         L0.f[d].assign(fs[d], fs[d] + L0.n[d] + 1);
         L0.c[d].resize(L0.n[d]);
         L0.w[d].resize(L0.n[d]);
@@ -87,31 +114,37 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
             L0.c[d][i] = 0.5 * (L0.f[d][i] + L0.f[d][i + 1]);
             L0.w[d][i] = L0.f[d][i + 1] - L0.f[d][i];
         }
+        if (L0.n[d] >= 2) hmin = std::min(hmin, *std::min_element(L0.w[d].begin(), L0.w[d].end()));
     }
     int n = 1;
     while (n < MAX_LEVELS) {
         LevelHost &F = lev[n - 1];
-        double m = INFINITY;
-        bool can[3];
-        double mw[3];
-        for (int d = 0; d < 3; ++d) {
-            can[d] = F.n[d] >= 4 && F.n[d] % 2 == 0;
-            mw[d] = *std::min_element(F.w[d].begin(), F.w[d].end());
-            if (can[d]) m = std::min(m, mw[d]);
-        }
-        int h[3];
+        LevelHost &C = lev[n];
+        const int64_t nf = F.ncell();
+        double wmax = MERGE_WIDTH * std::ldexp(hmin, n - 1);
         bool any = false;
-        for (int d = 0; d < 3; ++d) {
-            h[d] = (can[d] && mw[d] < 1.5 * m) ? 1 : 0;
-            any = any || h[d];
+        for (int rise = 0; rise < 64; ++rise, wmax *= 1.25) {
+            int64_t nc = 1;
+            bool full = true;
+            any = false;
+            for (int d = 0; d < 3; ++d) {
+                C.n[d] = merge_axis(F.w[d], wmax, C.cs[d]);
+                nc *= C.n[d];
+                any = any || C.n[d] < F.n[d];
+                if (F.n[d] >= 4 && C.n[d] != (F.n[d] + 1) / 2) full = false;
+            }
+            if (2 * nc <= nf || full) break;
         }
         if (!any) break;
-        LevelHost &C = lev[n];
         for (int d = 0; d < 3; ++d) {
-            C.halved[d] = h[d];
-            C.n[d] = h[d] ? F.n[d] / 2 : F.n[d];
+            C.same[d] = C.n[d] == F.n[d];
+            bool uniform = F.n[d] % 2 == 0 && C.n[d] * 2 == F.n[d];
+            for (int I = 0; uniform && I <= C.n[d]; ++I) uniform = C.cs[d][I] == 2 * I;
+            C.halved[d] = uniform ? 1 : 0;
+        }
+        for (int d = 0; d < 3; ++d) {
             C.f[d].resize(C.n[d] + 1);
-            for (int q = 0; q <= C.n[d]; ++q) C.f[d][q] = F.f[d][h[d] ? 2 * q : q];
+            for (int q = 0; q <= C.n[d]; ++q) C.f[d][q] = F.f[d][C.cs[d][q]];
             C.c[d].resize(C.n[d]);
             C.w[d].resize(C.n[d]);
             for (int i = 0; i < C.n[d]; ++i) {
@@ -119,11 +152,11 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
                 C.w[d][i] = C.f[d][i + 1] - C.f[d][i];
             }
         }
-        // side rule of the prolongation table (k_prolong_tab): fine i takes I = i/2 and the
-        // coarse neighbour on the side of its centre
+        // side rule of the prolongation table (k_prolong_tab) on uniformly halved axes: fine i
+        // takes I = i/2 and the coarse neighbour on the side of its centre
         bool sides = true;
         for (int d = 0; d < 3; ++d) {
-            if (!h[d]) continue;
+            if (!C.halved[d]) continue;
             for (int i = 0; i < F.n[d]; ++i) {
                 const int I = i / 2, jn = (F.c[d][i] < C.c[d][I]) ? I - 1 : I + 1;
                 if (jn >= 0 && jn < C.n[d] && jn != ((i & 1) ? I + 1 : I - 1)) sides = false;
@@ -133,6 +166,16 @@ void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, con
         ++n;
     }
     *nlev = n;
+}
+
+ChildMap child_map(const LevelHost &C) {
+    ChildMap M;
+    for (int d = 0; d < 3; ++d) {
+        M.cs[d] = C.cs_d[d];
+        M.halved[d] = C.halved[d];
+        M.same[d] = C.same[d];
+    }
+    return M;
 }
 
 size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t gmax,
@@ -222,6 +265,7 @@ size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int6
                 L.w32[d] = P.take<float>(L.n[d]);
                 L.c64[d] = P.take<double>(2 * L.n[d] + 1);  // centres, then the faces
             }
+            for (int d = 0; d < 3; ++d) L.cs_d[d] = P.take<int>(L.n[d] + 1);
             L.e64 = P.take<double>(NC);
             L.R64 = P.take<double>(NC);
             L.e32 = P.take<float>(NC);
@@ -358,10 +402,14 @@ ibm_status ibm_bind_workspace(ibm_grid *g, void *device_ptr, size_t bytes, int64
         HIP_TRY(hipMemcpyAsync(g->faces[d], fs[d]->data(), sizeof(double) * fs[d]->size(), hipMemcpyHostToDevice, s),
                 "upload faces");
     for (int l = 1; l < g->nlev; ++l)
-        for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d) {
             HIP_TRY(hipMemcpyAsync(g->lev[l].c64[d] + g->lev[l].n[d], g->lev[l].f[d].data(),
                                    sizeof(double) * (g->lev[l].n[d] + 1), hipMemcpyHostToDevice, s),
                     "upload coarse faces");
+            HIP_TRY(hipMemcpyAsync(g->lev[l].cs_d[d], g->lev[l].cs[d].data(), sizeof(int) * (g->lev[l].n[d] + 1),
+                                   hipMemcpyHostToDevice, s),
+                    "upload child maps");
+        }
     HIP_TRY(hipMemsetAsync(g->sc, 0, sizeof(Scalars), s), "memset scalars");
     HIP_TRY(launch_metrics(g, s), "metrics");
     HIP_TRY(hipStreamSynchronize(s), "bind sync");
@@ -592,6 +640,15 @@ ibm_status ibm_get_levels(const ibm_grid *g, int *n_levels, int *dims) {
 // ------------------------------------------------------------------------------------------
 // solve drivers
 // ------------------------------------------------------------------------------------------
+
+ibm_status ibm_get_level_map(const ibm_grid *g, int level, int axis, int *cs) {
+    if (!g || !cs) return fail(nullptr, IBM_E_ARG, "ibm_get_level_map: NULL argument");
+    if (level < 1 || level >= g->nlev || axis < 0 || axis > 2)
+        return fail(const_cast<ibm_grid *>(g), IBM_E_ARG, "ibm_get_level_map: level or axis out of range");
+    const std::vector<int> &m = g->lev[level].cs[axis];
+    std::copy(m.begin(), m.end(), cs);
+    return IBM_OK;
+}
 
 static ibm_status check_opts(ibm_grid *g, const ibm_solve_opts *o) {
     if (!o) return fail(g, IBM_E_ARG, "NULL options");

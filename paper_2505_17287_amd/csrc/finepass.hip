@@ -174,6 +174,57 @@ __global__ void __launch_bounds__(ZM_NT)
     zm_block_sum_store<ZM_NT>(psum, partials);
 }
 
+// Residual and restriction for any child map (cells merged on some axes only where they are
+// narrow): a thread per coarse column (I, J) marches over the coarse planes K of its chunk
+// and, for each of its fine cells (x fastest, then y, then z), forms the residual
+// (f - lambda) - S p with the same arithmetic as k_restrict0_zm and adds the
+// volume-integrated value of the fluid ones.  Fine neighbours come through the caches.
+constexpr int RMAP_TX = 64, RMAP_TY = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(RMAP_TX *RMAP_TY)
+    k_restrict0_map(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
+                    Coarse<T> C, ChildMap M, int kc, double *partials) {
+    const int I = blockIdx.x * RMAP_TX + (int)(threadIdx.x % RMAP_TX);
+    const int J = blockIdx.y * RMAP_TY + (int)(threadIdx.x / RMAP_TX);
+    const int K0 = blockIdx.z * kc, K1 = min(C.n[2], K0 + kc);
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    double psum = 0.0;
+    if (I < C.n[0] && J < C.n[1]) {
+        const T lam = *lamp;
+        const int i0 = M.cs[0][I], i1 = M.cs[0][I + 1], j0 = M.cs[1][J], j1 = M.cs[1][J + 1];
+        for (int K = K0; K < K1; ++K) {
+            const int k0 = M.cs[2][K], k1 = M.cs[2][K + 1];
+            T acc = 0;
+            for (int k = k0; k < k1; ++k)
+                for (int j = j0; j < j1; ++j)
+                    for (int i = i0; i < i1; ++i) {
+                        const int64_t id = (int64_t)k * plane + (int64_t)j * nx + i;
+                        const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1, hz0 = k > 0,
+                                   hz1 = k < nz - 1;
+                        const T pc = p[id];
+                        const T xm = hx0 ? p[id - 1] : T(0), xp = hx1 ? p[id + 1] : T(0);
+                        const T ym = hy0 ? p[id - nx] : T(0), yp = hy1 ? p[id + nx] : T(0);
+                        const T zm = hz0 ? p[id - plane] : T(0), zp = hz1 ? p[id + plane] : T(0);
+                        T num, diag;
+                        zm_stencil<T>(F.axm[i], F.axp[i], F.aym[j], F.ayp[j], F.azm[k], F.azp[k], hx0, hx1, hy0, hy1,
+                                      hz0, hz1, xm, xp, ym, yp, zm, zp, num, diag);
+                        const T r = (f[id] - lam) - (num - diag * pc);
+                        const T vxy = F.wx[i] * F.wy[j];
+                        if (F.type[id] == T_FLUID) acc += (vxy * F.wz[k]) * r;
+                    }
+            const int64_t cid = ((int64_t)K * C.n[1] + J) * C.n[0] + I;
+            C.R[cid] = acc;
+            C.e[cid] = T(0);
+            psum += (double)acc;
+        }
+    }
+    __shared__ double sh[RMAP_TX * RMAP_TY / 64];
+    const double tot = block_sum<RMAP_TX * RMAP_TY>(psum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+}
+
 // ---- prolongation ------------------------------------------------------------------------
 // pnext = pcur + P e_1 on fluid cells (ghost cells are refreshed afterwards).  The loads of
 // plane k+1 (its z table entry, fine values and the coarse contributors) are issued before
@@ -731,7 +782,22 @@ __global__ void __launch_bounds__(ZP_NT)
 
 template <typename T>
 hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
-                            const int halved[3], double *partials, int *nparts, hipStream_t s) {
+                            const ChildMap &M, double *partials, int *nparts, hipStream_t s) {
+    if (!((M.halved[0] || M.same[0]) && (M.halved[1] || M.same[1]) && (M.halved[2] || M.same[2]))) {
+        // some axis merges only part of its cells: the generic pass, with about 16 workgroups
+        // per CU (z chunks), at most zmarch_partials_max partials
+        const int gx = (C.n[0] + RMAP_TX - 1) / RMAP_TX, gy = (C.n[1] + RMAP_TY - 1) / RMAP_TY;
+        const int64_t want = (int64_t)16 * device_cu_count();
+        int gz = (int)std::max<int64_t>(1, std::min<int64_t>(C.n[2], want / std::max(1, gx * gy)));
+        gz = (int)std::min<int64_t>(gz, std::max<int64_t>(1, zmarch_partials_max(F.nx, F.ny, F.nz) / ((int64_t)gx * gy)));
+        const int kc = (C.n[2] + gz - 1) / gz;
+        gz = (C.n[2] + kc - 1) / kc;
+        hipLaunchKernelGGL(k_restrict0_map<T>, dim3(gx, gy, gz), dim3(RMAP_TX * RMAP_TY), 0, s, F, p, f, lam, C, M, kc,
+                           partials);
+        *nparts = gx * gy * gz;
+        return hipGetLastError();
+    }
+    const int halved[3] = {M.halved[0], M.halved[1], M.halved[2]};
     if ((F.nx & 1) == 0 && F.nx >= 2) {
         const ZTiles t = ztiles2(F.nx, F.ny, F.nz);
         hipLaunchKernelGGL(k_restrict0_zm2<T>, dim3(t.grid), dim3(ZP_NT), 0, s, F, p, f, lam, C, halved[0],
@@ -794,9 +860,9 @@ int64_t zmarch_partials_max(int nx, int ny, int nz) {
 }
 
 template hipError_t launch_restrict0<double>(const Fine<double> &, const double *, const double *, const double *,
-                                             const Coarse<double> &, const int[3], double *, int *, hipStream_t);
+                                             const Coarse<double> &, const ChildMap &, double *, int *, hipStream_t);
 template hipError_t launch_restrict0<float>(const Fine<float> &, const float *, const float *, const float *,
-                                            const Coarse<float> &, const int[3], double *, int *, hipStream_t);
+                                            const Coarse<float> &, const ChildMap &, double *, int *, hipStream_t);
 template hipError_t launch_prolong0<double>(const Fine<double> &, const double *, double *, const Coarse<double> &,
                                             const ProlongTab &, hipStream_t);
 template hipError_t launch_prolong0<float>(const Fine<float> &, const float *, float *, const Coarse<float> &,

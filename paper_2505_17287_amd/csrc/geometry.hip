@@ -52,8 +52,8 @@ __global__ void k_level_axis(int n, const double *__restrict__ f, double *c, dou
     wf[i] = (float)(f[i + 1] - f[i]);
 }
 
-__global__ void k_prolong_tab(int nf, int nc, int halved, const double *__restrict__ fc, const double *__restrict__ cc,
-                              int *lo, int *hi, double *t);
+__global__ void k_prolong_tab(int nf, int nc, const int *__restrict__ cs, const double *__restrict__ fc,
+                              const double *__restrict__ cc, int *lo, int *hi, double *t);
 
 hipError_t launch_metrics(ibm_grid *g, hipStream_t s) {
     int n[3] = {g->nx, g->ny, g->nz};
@@ -75,7 +75,7 @@ hipError_t launch_metrics(ibm_grid *g, hipStream_t s) {
         for (int d = 0; d < 3; ++d) {
             const double *fc = (l == 1) ? g->c0[d] : Fh.c64[d];
             hipLaunchKernelGGL(k_prolong_tab, dim3((Fh.n[d] + 127) / 128), dim3(128), 0, s, Fh.n[d], Ch.n[d],
-                               Ch.halved[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
+                               Ch.cs_d[d], fc, Ch.c64[d], Fh.plo[d], Fh.phi[d], Fh.pt[d]);
         }
     }
     return hipGetLastError();
@@ -1216,7 +1216,7 @@ hipError_t launch_fresh(ibm_grid *g, hipStream_t s, int64_t *nfresh) {
 
 struct LevelDims {
     int n[3];
-    int h[3];  // halved relative to the finer level
+    const int *cs[3];  // children starts in the finer level (coarse side of a pair only)
 };
 
 // active(C) = any active child; fine level 0 active = fluid
@@ -1230,9 +1230,9 @@ __global__ void k_coarsen_active(LevelDims F, LevelDims C, const uint8_t *__rest
     if (id < NC) {
         int I, J, K;
         unflatten(id, C.n[0], C.n[1], I, J, K);
-        int i0 = C.h[0] ? 2 * I : I, i1 = C.h[0] ? 2 * I + 1 : I;
-        int j0 = C.h[1] ? 2 * J : J, j1 = C.h[1] ? 2 * J + 1 : J;
-        int k0 = C.h[2] ? 2 * K : K, k1 = C.h[2] ? 2 * K + 1 : K;
+        const int i0 = C.cs[0][I], i1 = C.cs[0][I + 1] - 1;
+        const int j0 = C.cs[1][J], j1 = C.cs[1][J + 1] - 1;
+        const int k0 = C.cs[2][K], k1 = C.cs[2][K + 1] - 1;
         uint8_t act = 0;
         for (int k = k0; k <= k1; ++k)
             for (int j = j0; j <= j1; ++j)
@@ -1322,9 +1322,9 @@ __global__ void k_face_T(LevelDims F, LevelDims C, const uint8_t *__restrict__ f
     }
     const double *fw[3] = {fw0, fw1, fw2};
     int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
-    int fface = C.h[d] ? 2 * Ic[d] : Ic[d];
-    int a0 = C.h[e1] ? 2 * Ic[e1] : Ic[e1], a1 = C.h[e1] ? 2 * Ic[e1] + 1 : Ic[e1];
-    int b0 = C.h[e2] ? 2 * Ic[e2] : Ic[e2], b1 = C.h[e2] ? 2 * Ic[e2] + 1 : Ic[e2];
+    const int fface = C.cs[d][Ic[d]];
+    const int a0 = C.cs[e1][Ic[e1]], a1 = C.cs[e1][Ic[e1] + 1] - 1;
+    const int b0 = C.cs[e2][Ic[e2]], b1 = C.cs[e2][Ic[e2] + 1] - 1;
     double area = 0.0;
     for (int b = b0; b <= b1; ++b)
         for (int a = a0; a <= a1; ++a) {
@@ -1345,19 +1345,29 @@ __global__ void k_face_T(LevelDims F, LevelDims C, const uint8_t *__restrict__ f
     T32[id] = (float)t;
 }
 
-// prolongation table of a fine axis: value(i) = (1-t) e[lo] + t e[hi], physical coordinates,
-// clamped at the walls; axes not halved map to themselves
-__global__ void k_prolong_tab(int nf, int nc, int halved, const double *__restrict__ fc, const double *__restrict__ cc,
-                              int *lo, int *hi, double *t) {
+// prolongation table of a fine axis: value(i) = (1-t) e[lo] + t e[hi], physical coordinates;
+// lo is the parent (the coarse cell holding i, found in the children starts cs), hi the
+// parent's neighbour on the side of the fine centre, clamped at the walls; a cell kept whole
+// takes its parent alone
+__global__ void k_prolong_tab(int nf, int nc, const int *__restrict__ cs, const double *__restrict__ fc,
+                              const double *__restrict__ cc, int *lo, int *hi, double *t) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    if (!halved) {
-        lo[i] = i;
-        hi[i] = i;
+    int a = 0, b = nc;  // cs[a] <= i < cs[b]
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (cs[m] <= i)
+            a = m;
+        else
+            b = m;
+    }
+    const int I = a;
+    if (cs[I + 1] - cs[I] == 1) {
+        lo[i] = I;
+        hi[i] = I;
         t[i] = 0.0;
         return;
     }
-    int I = i / 2;
     double x = fc[i], X = cc[I];
     int Jn = (x < X) ? I - 1 : I + 1;
     if (Jn < 0 || Jn >= nc) {
@@ -1381,9 +1391,9 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
         LevelDims F, C;
         for (int d = 0; d < 3; ++d) {
             F.n[d] = Fh.n[d];
-            F.h[d] = Fh.halved[d];
+            F.cs[d] = nullptr;
             C.n[d] = Ch.n[d];
-            C.h[d] = Ch.halved[d];
+            C.cs[d] = Ch.cs_d[d];
         }
         const bool fine_type = (l == 1);
         const uint8_t *fa = fine_type ? g->type : Fh.active;
@@ -1410,7 +1420,7 @@ hipError_t launch_hierarchy(ibm_grid *g, hipStream_t s) {
         LevelDims C;
         for (int d = 0; d < 3; ++d) {
             C.n[d] = C1.n[d];
-            C.h[d] = C1.halved[d];
+            C.cs[d] = C1.cs_d[d];
         }
         hipLaunchKernelGGL(k_inject0, dim3((unsigned)((g->N + 255) / 256)), dim3(256), 0, s, g->nx, g->ny, g->nz,
                            g->type, C, C1.active, F0.plo[0], F0.phi[0], F0.plo[1], F0.phi[1], F0.plo[2], F0.phi[2],

@@ -73,17 +73,27 @@ bool sweepC_fused_ok(const int n[3]);
 template <typename T>
 hipError_t launch_sweepC_fused(const Coarse<T> &L, T *eout, hipStream_t s);
 
-struct ProlongTab {  // fine index -> (lo, hi, weight of hi) per axis
+// fine index -> (lo, hi, weight of hi) per axis; lo is always the parent (the coarse cell
+// holding the fine one)
+struct ProlongTab {
     const int *lo[3], *hi[3];
     const double *t[3];
-    int halved[3];
+    int halved[3];  // 1: the axis is halved uniformly (fine 2I and 2I+1 make coarse I)
+};
+
+// Children of a coarse level (device): coarse index I along axis d holds the finer cells
+// cs[d][I] .. cs[d][I+1]-1 (one or two).
+struct ChildMap {
+    const int *cs[3];
+    int halved[3];  // 1: uniform halving along d
+    int same[3];    // 1: nothing merged along d (cs[I] = I)
 };
 
 // z-march passes of level 0 (finepass.hip).  The reductions write one partial per
 // workgroup; *nparts receives their count (at most zmarch_partials_max).
 template <typename T>
 hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
-                            const int halved[3], double *partials, int *nparts, hipStream_t s);
+                            const ChildMap &M, double *partials, int *nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coarse<T> &C, const ProlongTab &P,
                            hipStream_t s);
@@ -141,8 +151,11 @@ struct Scalars {
 
 struct LevelHost {
     int n[3];
-    int halved[3];
+    int halved[3];  // uniform halving relative to the next finer level (see plan_levels)
+    int same[3];    // nothing merged relative to the next finer level
     std::vector<double> f[3], c[3], w[3];
+    std::vector<int> cs[3];  // children starts in the next finer level (levels >= 1)
+    int *cs_d[3] = {nullptr, nullptr, nullptr};  // device copy of cs
     int64_t ncell() const { return (int64_t)n[0] * n[1] * n[2]; }
     // device
     uint8_t *active = nullptr;
@@ -303,6 +316,8 @@ struct Plan {
 };
 
 // hierarchy plan on the host (dims + coarse faces), same rule for sizing and binding
+// the level's child map (device pointers; level >= 1)
+ChildMap child_map(const LevelHost &C);
 void plan_levels(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
                  LevelHost *lev, int *nlev);
 size_t layout(ibm_grid *g, Plan &P, int nx, int ny, int nz, int64_t nv_max, int64_t nt_max, int64_t gmax,

@@ -253,13 +253,10 @@ __device__ __forceinline__ void coarse_stencil(const Coarse<T> &L, const T *__re
 // residual + restriction, fused with block partial sums of the coarse right-hand side
 // =======================================================================================
 
-struct Halv {
-    int h[3];
-};
-
-// level l -> l+1 (l >= 1): R_{l+1}(C) = sum over active children of r, r = (R - V mu) - S e
+// level l -> l+1 (l >= 1): R_{l+1}(C) = sum over active children of r, r = (R - V mu) - S e;
+// the children (one or two per axis) are summed x fastest, then y, then z
 template <typename T>
-__global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partials) {
+__global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, ChildMap M, double *partials) {
     __shared__ double sh[4];
     const int64_t NC = (int64_t)C.n[0] * C.n[1] * C.n[2];
     const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,22 +265,18 @@ __global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, Halv H, double *partial
         const T mu = (T)(*L.mu);
         int I, J, K;
         unflatten(cid, C.n[0], C.n[1], I, J, K);
-        const int i0 = H.h[0] ? 2 * I : I, j0 = H.h[1] ? 2 * J : J, k0 = H.h[2] ? 2 * K : K;
+        const int i0 = M.cs[0][I], i1 = M.cs[0][I + 1], j0 = M.cs[1][J], j1 = M.cs[1][J + 1];
+        const int k0 = M.cs[2][K], k1 = M.cs[2][K + 1];
         T R = 0;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const bool ok = (a == 0 || H.h[0]) && (b == 0 || H.h[1]) && (c == 0 || H.h[2]);
-                    const int i = i0 + (H.h[0] ? a : 0), j = j0 + (H.h[1] ? b : 0), k = k0 + (H.h[2] ? c : 0);
+        for (int k = k0; k < k1; ++k)
+            for (int j = j0; j < j1; ++j)
+                for (int i = i0; i < i1; ++i) {
                     const int64_t id = ((int64_t)k * L.n[1] + j) * L.n[0] + i;
                     T num, diag;
                     coarse_stencil(L, L.e, i, j, k, id, num, diag);
                     const T vol = (L.w[0][i] * L.w[1][j]) * L.w[2][k];
                     const T rc = (L.R[id] - vol * mu) - (num - diag * L.e[id]);
-                    if (ok && L.active[id]) R += rc;
+                    if (L.active[id]) R += rc;
                 }
         C.R[cid] = R;
         C.e[cid] = T(0);
@@ -534,6 +527,7 @@ struct TailArgs {
     int nl;                   // tail levels; index 0 is the first, nl - 1 the coarsest
     Coarse<T> L[TAIL_MAX];    // level views (e and R in global memory)
     ProlongTab P[TAIL_MAX];   // P[q]: table of tail level q from level q + 1
+    const int *cs[TAIL_MAX][3];  // cs[q]: children starts of tail level q + 1 in level q
     int off[TAIL_MAX];        // offset of each level's iterate in LDS
     const double *vol[TAIL_MAX];
     double *mu[TAIL_MAX];
@@ -755,19 +749,16 @@ __global__ void __launch_bounds__(TAIL_NT) k_tailC(TailArgs<T> A) {
         const Coarse<T> &L = A.L[q];
         tail_smooth<T>(L, es + A.off[q], acts + A.off[q], A.nu1, (T)mu_s[q], A.vol[q], 0, nullptr, rs, sh, &mean_s);
         const Coarse<T> &C = A.L[q + 1];
-        const int *h = A.P[q].halved;
+        const int *const *cs = A.cs[q];
         const int NCC = C.n[0] * C.n[1] * C.n[2];
         double psum = 0.0;
         for (int cid = tid; cid < NCC; cid += TAIL_NT) {
             int I, J, K;
             tail_ijk(C, cid, I, J, K);
-            const int i0 = h[0] ? 2 * I : I, i1 = h[0] ? 2 * I + 1 : I;
-            const int j0 = h[1] ? 2 * J : J, j1 = h[1] ? 2 * J + 1 : J;
-            const int k0 = h[2] ? 2 * K : K, k1 = h[2] ? 2 * K + 1 : K;
             T R = 0;
-            for (int k = k0; k <= k1; ++k)
-                for (int j = j0; j <= j1; ++j)
-                    for (int i = i0; i <= i1; ++i) R += rs[(k * L.n[1] + j) * L.n[0] + i];
+            for (int k = cs[2][K]; k < cs[2][K + 1]; ++k)
+                for (int j = cs[1][J]; j < cs[1][J + 1]; ++j)
+                    for (int i = cs[0][I]; i < cs[0][I + 1]; ++i) R += rs[(k * L.n[1] + j) * L.n[0] + i];
             C.R[cid] = R;
             es[A.off[q + 1] + cid] = T(0);
             psum += (double)R;
@@ -883,8 +874,8 @@ __device__ __forceinline__ double prolong_value(const Coarse<T> &C, const Prolon
                     s += term;
                 }
             }
-    if (!all) {
-        const int pi = P.halved[0] ? i / 2 : i, pj = P.halved[1] ? j / 2 : j, pk = P.halved[2] ? k / 2 : k;
+    if (!all) {  // the parent: the first contributor on every axis
+        const int pi = P.lo[0][i], pj = P.lo[1][j], pk = P.lo[2][k];
         s = (double)C.e[((int64_t)pk * C.n[1] + pj) * C.n[0] + pi];
     }
     return s;
@@ -1225,20 +1216,25 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
     if (g->nlev > 1) {
         const int Lc = g->nlev - 1;
         // the tail: every level from the first one with at most SMALL_LEVEL cells down to the
-        // coarsest, run by one workgroup (levels only shrink, so all of them are small)
+        // coarsest, run by one workgroup, when those levels fit its LDS together (TAIL_E cells)
+        // and number at most TAIL_MAX; else the tail starts further down
         int lt = Lc + 1;
-        for (int l = 1; l <= Lc; ++l)
-            if (g->lev[l].ncell() <= SMALL_LEVEL) {
+        for (int l = 1; l <= Lc; ++l) {
+            if (g->lev[l].ncell() > SMALL_LEVEL || Lc - l + 1 > TAIL_MAX) continue;
+            int64_t tot = 0;
+            for (int q = l; q <= Lc; ++q) tot += g->lev[q].ncell();
+            if (tot <= TAIL_E) {
                 lt = l;
                 break;
             }
-        const bool tail = lt <= Lc && Lc - lt + 1 <= TAIL_MAX;
+        }
+        const bool tail = lt <= Lc;
         const int Lb = tail ? lt : Lc;  // levels 1 .. Lb-1 run level by level
         int nparts = 0;                 // restriction partials into level Lb
         {
             Coarse<T> C1 = coarse_view<T>(g, 1);
-            if ((e = launch_restrict0<T>(F, bufs[*cur], rhs, lam, C1, g->lev[1].halved, g->partials, &nparts, s)) !=
-                hipSuccess)
+            if ((e = launch_restrict0<T>(F, bufs[*cur], rhs, lam, C1, child_map(g->lev[1]), g->partials, &nparts,
+                                         s)) != hipSuccess)
                 return e;
             if (!(tail && lt == 1))
                 hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nparts, &g->sc->vol[1],
@@ -1252,13 +1248,12 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             }
             Coarse<T> L = coarse_view<T>(g, l);  // after the sweeps: the current error buffer
             Coarse<T> C = coarse_view<T>(g, l + 1);
-            Halv H;
-            for (int d = 0; d < 3; ++d) H.h[d] = g->lev[l + 1].halved[d];
+            const ChildMap M = child_map(g->lev[l + 1]);
             int nbc = nblk(g->lev[l + 1].ncell());
-            if (H.h[0] && H.h[1] && H.h[2])
+            if (M.halved[0] && M.halved[1] && M.halved[2])
                 hipLaunchKernelGGL(k_resrestrictC8<T>, dim3(nbc), dim3(256), 0, s, L, C, g->partials);
             else
-                hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, H, g->partials);
+                hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, M, g->partials);
             nparts = nbc;
             if (!(tail && l + 1 == lt))
                 hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
@@ -1271,7 +1266,10 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             for (int q = 0; q < A.nl; ++q) {
                 const int l = lt + q;
                 A.L[q] = coarse_view<T>(g, l);
-                if (q + 1 < A.nl) A.P[q] = prolong_tab(g, l);
+                if (q + 1 < A.nl) {
+                    A.P[q] = prolong_tab(g, l);
+                    for (int d = 0; d < 3; ++d) A.cs[q][d] = g->lev[l + 1].cs_d[d];
+                }
                 A.off[q] = off;
                 off += (int)g->lev[l].ncell();
                 A.vol[q] = &g->sc->vol[l];

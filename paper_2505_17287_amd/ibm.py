@@ -124,6 +124,7 @@ def lib():
         L.ibm_move_geometry.argtypes = [vp, dp, i64, vp, i64, vp, vp, vp]
         L.ibm_fill_fresh.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ibm_cell_to_faces.argtypes = [vp] * 8
+        L.ibm_get_level_map.argtypes = [vp, C.c_int, C.c_int, vp]
         L.ibm_correct_cells.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp]
         L.ibm_get_fresh.argtypes = [vp, vp] + [vp] * 7
         L.ibm_destroy_grid.argtypes = [vp]

@@ -66,22 +66,35 @@ def test_workspace_bound_covers_every_plan():
         L.ibm_destroy_grid(h)
 
 
-def test_levels_follow_semicoarsening_rule():
-    """Level plan of the library equals the oracle's (same rule, independent code)."""
+def test_levels_follow_width_coarsening_rule():
+    """Level plan and child maps of the library equal the oracle's (same rule, independent
+    code): stretched, uniform, odd, flat and anisotropic grids."""
     from oracle import OracleProblem
     from paper_2505_17287_amd import inputs as I
     L = ibm.lib()
-    for wl in (I.wing(64, 32, 32), I.multibody(48, n_bodies=1, level=1), I.cylinder2d(64)):
-        nx, ny, nz = wl.shape
-        code, h = _create(nx, ny, nz, wl.xf, wl.yf, wl.zf)
+    grids = [I.wing(64, 32, 32), I.multibody(48, n_bodies=1, level=1), I.cylinder2d(64), I.multibody(96, n_bodies=1, level=1)]
+    extra = [(np.linspace(0, 1, 34), np.linspace(0, 3, 25), np.linspace(0, 0.5, 9)),
+             (np.cumsum(np.r_[0, 1.07 ** np.arange(40)]), np.linspace(0, 1, 17), np.linspace(0, 1, 6))]
+    cases = [(wl.xf, wl.yf, wl.zf) for wl in grids] + extra
+    for xf, yf, zf in cases:
+        nx, ny, nz = len(xf) - 1, len(yf) - 1, len(zf) - 1
+        code, h = _create(nx, ny, nz, xf, yf, zf)
+        assert code == 0
         n = C.c_int()
         dims = np.zeros(96, np.int32)
         assert L.ibm_get_levels(h, C.byref(n), C.c_void_p(dims.ctypes.data)) == 0
-        P = OracleProblem(wl.xf, wl.yf, wl.zf)
+        P = OracleProblem(xf, yf, zf)
         P.classify()
         ref = [lv["dims"] for lv in P.levels()]
         got = [tuple(int(x) for x in dims[3 * l:3 * l + 3]) for l in range(n.value)]
         assert got == ref
+        for l in range(1, n.value):
+            maps = P.level_map(l)
+            for d in range(3):
+                cs = np.zeros(got[l][d] + 1, np.int32)
+                assert L.ibm_get_level_map(h, l, d, C.c_void_p(cs.ctypes.data)) == 0
+                assert np.array_equal(cs, maps[d]), (l, d)
+        assert L.ibm_get_level_map(h, 0, 0, C.c_void_p(dims.ctypes.data)) == ibm.IBM_E_ARG
         L.ibm_destroy_grid(h)
 
 
