@@ -175,53 +175,80 @@ __global__ void __launch_bounds__(ZM_NT)
 }
 
 // Residual and restriction for any child map (cells merged on some axes only where they are
-// narrow): a thread per coarse column (I, J) marches over the coarse planes K of its chunk
-// and, for each of its fine cells (x fastest, then y, then z), forms the residual
-// (f - lambda) - S p with the same arithmetic as k_restrict0_zm and adds the
-// volume-integrated value of the fluid ones.  Fine neighbours come through the caches.
-constexpr int RMAP_TX = 64, RMAP_TY = 4;
+// narrow).  A workgroup owns RT_CX x RT_CY coarse columns and a chunk of coarse planes; its
+// threads cover the fine columns of those coarse columns (at most 2 RT_CX x 2 RT_CY) and
+// march up the fine planes as k_restrict0_zm does (the planes below and above the column in
+// registers, in-plane neighbours through the caches), forming the residual
+// (f - lambda) - S p with the same arithmetic.  Per fine plane the volume-integrated
+// residuals of the fluid cells go to LDS, and one thread per coarse column adds its children
+// to its running sum in the oracle's order (x fastest, then y, plane by plane); the sum is
+// stored when the coarse plane's last fine plane is done.
+constexpr int RT_CX = 32, RT_CY = 2, RT_FX = 2 * RT_CX, RT_FY = 2 * RT_CY, RT_NT = RT_FX * RT_FY;
 
 template <typename T>
-__global__ void __launch_bounds__(RMAP_TX *RMAP_TY)
+__global__ void __launch_bounds__(RT_NT)
     k_restrict0_map(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
                     Coarse<T> C, ChildMap M, int kc, double *partials) {
-    const int I = blockIdx.x * RMAP_TX + (int)(threadIdx.x % RMAP_TX);
-    const int J = blockIdx.y * RMAP_TY + (int)(threadIdx.x / RMAP_TX);
+    __shared__ T sv[2][RT_FY][RT_FX];
+    const int I0 = blockIdx.x * RT_CX, J0 = blockIdx.y * RT_CY;
     const int K0 = blockIdx.z * kc, K1 = min(C.n[2], K0 + kc);
     const int nx = F.nx, ny = F.ny, nz = F.nz;
     const int64_t plane = (int64_t)nx * ny;
+    // fine span of the tile
+    const int fx0 = M.cs[0][I0], fx1 = M.cs[0][min(I0 + RT_CX, C.n[0])];
+    const int fy0 = M.cs[1][J0], fy1 = M.cs[1][min(J0 + RT_CY, C.n[1])];
+    const int lx = (int)threadIdx.x % RT_FX, ly = (int)threadIdx.x / RT_FX;
+    const int i = fx0 + lx, j = fy0 + ly;
+    const bool in = i < fx1 && j < fy1;
+    const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+    const int64_t rowoff = (int64_t)jc * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1, hy0 = jc > 0, hy1 = jc < ny - 1;
+    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
+    const T axm = F.axm[ic], axp = F.axp[ic], aym = F.aym[jc], ayp = F.ayp[jc];
+    const T vxy = F.wx[ic] * F.wy[jc];
+    const T lam = *lamp;
+    // the owner thread of coarse column (I, J): its children, local to the tile's span
+    const int oI = I0 + (int)threadIdx.x % RT_CX, oJ = J0 + (int)threadIdx.x / RT_CX;
+    const bool owner = threadIdx.x < RT_CX * RT_CY && oI < C.n[0] && oJ < C.n[1];
+    const int ox0 = owner ? M.cs[0][oI] - fx0 : 0, ox1 = owner ? M.cs[0][oI + 1] - fx0 : 0;
+    const int oy0 = owner ? M.cs[1][oJ] - fy0 : 0, oy1 = owner ? M.cs[1][oJ + 1] - fy0 : 0;
+    const int k0 = (K0 < K1) ? M.cs[2][K0] : 0, k1 = (K0 < K1) ? M.cs[2][K1] : 0;
+    T pm = (k0 > 0) ? p[(int64_t)(k0 - 1) * plane + rowoff] : T(0);
+    T pc = (k0 < k1) ? p[(int64_t)k0 * plane + rowoff] : T(0);
+    T acc = 0;
     double psum = 0.0;
-    if (I < C.n[0] && J < C.n[1]) {
-        const T lam = *lamp;
-        const int i0 = M.cs[0][I], i1 = M.cs[0][I + 1], j0 = M.cs[1][J], j1 = M.cs[1][J + 1];
-        for (int K = K0; K < K1; ++K) {
-            const int k0 = M.cs[2][K], k1 = M.cs[2][K + 1];
-            T acc = 0;
-            for (int k = k0; k < k1; ++k)
-                for (int j = j0; j < j1; ++j)
-                    for (int i = i0; i < i1; ++i) {
-                        const int64_t id = (int64_t)k * plane + (int64_t)j * nx + i;
-                        const bool hx0 = i > 0, hx1 = i < nx - 1, hy0 = j > 0, hy1 = j < ny - 1, hz0 = k > 0,
-                                   hz1 = k < nz - 1;
-                        const T pc = p[id];
-                        const T xm = hx0 ? p[id - 1] : T(0), xp = hx1 ? p[id + 1] : T(0);
-                        const T ym = hy0 ? p[id - nx] : T(0), yp = hy1 ? p[id + nx] : T(0);
-                        const T zm = hz0 ? p[id - plane] : T(0), zp = hz1 ? p[id + plane] : T(0);
-                        T num, diag;
-                        zm_stencil<T>(F.axm[i], F.axp[i], F.aym[j], F.ayp[j], F.azm[k], F.azp[k], hx0, hx1, hy0, hy1,
-                                      hz0, hz1, xm, xp, ym, yp, zm, zp, num, diag);
-                        const T r = (f[id] - lam) - (num - diag * pc);
-                        const T vxy = F.wx[i] * F.wy[j];
-                        if (F.type[id] == T_FLUID) acc += (vxy * F.wz[k]) * r;
-                    }
-            const int64_t cid = ((int64_t)K * C.n[1] + J) * C.n[0] + I;
-            C.R[cid] = acc;
-            C.e[cid] = T(0);
-            psum += (double)acc;
+    int K = K0, kend = (K0 < K1) ? M.cs[2][K0 + 1] : 0;  // the coarse plane and its end
+    int buf = 0;
+    for (int k = k0; k < k1; ++k) {
+        const int64_t base = (int64_t)k * plane + rowoff;
+        const T pp = (k < nz - 1) ? p[base + plane] : T(0);
+        T num, diag;
+        zm_stencil<T>(axm, axp, aym, ayp, F.azm[k], F.azp[k], hx0, hx1, hy0, hy1, k > 0, k < nz - 1, p[base + dxm],
+                      p[base + dxp], p[base + dym], p[base + dyp], pm, pp, num, diag);
+        const T r = (f[base] - lam) - (num - diag * pc);
+        sv[buf][ly][lx] = (in && F.type[base] == T_FLUID) ? (vxy * F.wz[k]) * r : T(0);
+        __syncthreads();
+        if (owner) {
+            for (int jj = oy0; jj < oy1; ++jj)
+                for (int ii = ox0; ii < ox1; ++ii) acc += sv[buf][jj][ii];
         }
+        if (k + 1 == kend) {  // the coarse plane K is complete
+            if (owner) {
+                const int64_t cid = ((int64_t)K * C.n[1] + oJ) * C.n[0] + oI;
+                C.R[cid] = acc;
+                C.e[cid] = T(0);
+                psum += (double)acc;
+            }
+            acc = T(0);
+            ++K;
+            kend = (K < K1) ? M.cs[2][K + 1] : k1;
+        }
+        buf ^= 1;
+        pm = pc;
+        pc = pp;
     }
-    __shared__ double sh[RMAP_TX * RMAP_TY / 64];
-    const double tot = block_sum<RMAP_TX * RMAP_TY>(psum, sh, threadIdx.x);
+    __shared__ double sh[RT_NT / 64];
+    const double tot = block_sum<RT_NT>(psum, sh, threadIdx.x);
     if (threadIdx.x == 0) partials[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
@@ -786,14 +813,13 @@ hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *l
     if (!((M.halved[0] || M.same[0]) && (M.halved[1] || M.same[1]) && (M.halved[2] || M.same[2]))) {
         // some axis merges only part of its cells: the generic pass, with about 16 workgroups
         // per CU (z chunks), at most zmarch_partials_max partials
-        const int gx = (C.n[0] + RMAP_TX - 1) / RMAP_TX, gy = (C.n[1] + RMAP_TY - 1) / RMAP_TY;
+        const int gx = (C.n[0] + RT_CX - 1) / RT_CX, gy = (C.n[1] + RT_CY - 1) / RT_CY;
         const int64_t want = (int64_t)16 * device_cu_count();
         int gz = (int)std::max<int64_t>(1, std::min<int64_t>(C.n[2], want / std::max(1, gx * gy)));
         gz = (int)std::min<int64_t>(gz, std::max<int64_t>(1, zmarch_partials_max(F.nx, F.ny, F.nz) / ((int64_t)gx * gy)));
         const int kc = (C.n[2] + gz - 1) / gz;
         gz = (C.n[2] + kc - 1) / kc;
-        hipLaunchKernelGGL(k_restrict0_map<T>, dim3(gx, gy, gz), dim3(RMAP_TX * RMAP_TY), 0, s, F, p, f, lam, C, M, kc,
-                           partials);
+        hipLaunchKernelGGL(k_restrict0_map<T>, dim3(gx, gy, gz), dim3(RT_NT), 0, s, F, p, f, lam, C, M, kc, partials);
         *nparts = gx * gy * gz;
         return hipGetLastError();
     }

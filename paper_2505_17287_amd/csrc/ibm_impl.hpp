@@ -67,8 +67,7 @@ hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *po
                               hipStream_t s);
 
 // fused red-black sweep of a coarse level (sweepc.hip): eout = one RB-GS sweep of L.e, the
-// two buffers distinct; for levels with an even row length and at least 2^19 cells
-// (sweepC_fused_ok)
+// two buffers distinct; for levels of at least SWC_MIN_CELLS cells (sweepC_fused_ok)
 bool sweepC_fused_ok(const int n[3]);
 template <typename T>
 hipError_t launch_sweepC_fused(const Coarse<T> &L, T *eout, hipStream_t s);

@@ -44,7 +44,7 @@ constexpr int SWC_KC_MIN = 8;    // shortest z chunk (each chunk re-reads four p
 // Levels below this size keep the two one-colour passes: there the z-march is bound by the
 // latency of its plane steps, not by bandwidth (at 64^3 the fused pass took 10.4 us against
 // 2 x 4.8 us; at 128^3 22 us against 2 x 19.5 us).
-constexpr int64_t SWC_MIN_CELLS = 1 << 19;
+constexpr int64_t SWC_MIN_CELLS = 3 << 17;
 
 // Relaxation value of one cell: the six neighbour products summed from zero in the order
 // -x, +x, -y, +y, -z, +z, the diagonal summed in the same order.  A missing neighbour meets
@@ -73,12 +73,14 @@ __device__ __forceinline__ T rbc_update(T txm, T txp, T tym, T typ, T tzm, T tzp
 
 // Thread layout as in the level-0 sweep: 32 threads span the 64 columns of a tile row; a
 // wave holds two rows of the same parity, so the colour phase is uniform per wave and the
-// plane loop is specialised for both phases.  Requires an even row length (pairs aligned).
+// plane loop is specialised for both phases.  VEC (even row length): a thread's column pair
+// is 2-element aligned and moves as one access; with an odd row length the two columns are
+// loaded and stored one by one.
 // Every thread issues the same loads for every plane (addresses clamped into the level);
 // values read through clamped addresses are finite copies of level cells that only meet
 // zero transmissibilities (walls, or the masked high faces of the last row, column and
 // plane), so they enter no result.
-template <typename T, int BY, int QD>
+template <typename T, int BY, int QD, bool VEC>
 __global__ void __launch_bounds__(32 * BY)
     k_rbgsC_fused(Coarse<T> L, T *__restrict__ eout, int ntx, int nty, int kc, int ntiles) {
     static_assert(BY % 4 == 0, "two same-parity rows of 32 threads per wave");
@@ -124,14 +126,17 @@ __global__ void __launch_bounds__(32 * BY)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const int jc = min(max(j, 0), ny - 1);
     const int icv = min(max(ia, 0), nx - 2);
-    const uint32_t rowoff = (uint32_t)jc * nx + icv;
+    // unpaired path: each column clamped on its own
+    const int ic0 = min(max(ia, 0), nx - 1), ic1 = min(max(ia + 1, 0), nx - 1);
+    const uint32_t rowoff = (uint32_t)jc * nx + (VEC ? icv : ic0);
     // The outermost halo rows are never updated: their right-hand side and x, z
     // transmissibilities are read from the adjacent row (lines the tile reads anyway), and
     // so is the y transmissibility of the first row (the last row's is the +y face of the
     // row below it).
     const int jr = min(max((ty == 0) ? j + 1 : (ty == BY - 1) ? j - 1 : j, 0), ny - 1);
     const int jy = min(max((ty == 0) ? j + 1 : j, 0), ny - 1);
-    const uint32_t roff = (uint32_t)jr * nx + icv, yoff = (uint32_t)jy * nx + icv;
+    const uint32_t roff = (uint32_t)jr * nx + (VEC ? icv : ic0), yoff = (uint32_t)jy * nx + (VEC ? icv : ic0);
+    const uint32_t d1 = VEC ? 1u : (uint32_t)(ic1 - ic0);  // offset of the second column
     const T vxy0 = in0 ? L.w[0][ia] * L.w[1][jc] : T(0);
     const T vxy1 = in1 ? L.w[0][ia + 1] * L.w[1][jc] : T(0);
     const T mu = (T)(*L.mu);
@@ -149,11 +154,24 @@ __global__ void __launch_bounds__(32 * BY)
     auto load = [=](int k) -> PD {
         PD d;
         const uint32_t base = (uint32_t)min(max(k, 0), klast) * plane;
-        d.e = *reinterpret_cast<const V *>(pe + base + rowoff);
-        d.r = *reinterpret_cast<const V *>(pr + base + roff);
-        d.x = *reinterpret_cast<const V *>(px + base + roff);
-        d.y = *reinterpret_cast<const V *>(py + base + yoff);
-        d.z = *reinterpret_cast<const V *>(pz + base + roff);
+        if constexpr (VEC) {
+            d.e = *reinterpret_cast<const V *>(pe + base + rowoff);
+            d.r = *reinterpret_cast<const V *>(pr + base + roff);
+            d.x = *reinterpret_cast<const V *>(px + base + roff);
+            d.y = *reinterpret_cast<const V *>(py + base + yoff);
+            d.z = *reinterpret_cast<const V *>(pz + base + roff);
+        } else {
+            d.e.x = pe[base + rowoff];
+            d.e.y = pe[base + rowoff + d1];
+            d.r.x = pr[base + roff];
+            d.r.y = pr[base + roff + d1];
+            d.x.x = px[base + roff];
+            d.x.y = px[base + roff + d1];
+            d.y.x = py[base + yoff];
+            d.y.y = py[base + yoff + d1];
+            d.z.x = pz[base + roff];
+            d.z.y = pz[base + roff + d1];
+        }
         return d;
     };
     // LDS buffer of plane q's y transmissibilities (q >= k0 - 1)
@@ -213,11 +231,17 @@ __global__ void __launch_bounds__(32 * BY)
             out0 = ((FR) && live_) ? v_ : pb0;                                                                     \
             out1 = (!(FR) && live_) ? v_ : pb1;                                                                    \
         }                                                                                                          \
-        if ((k) < k1 && blk0) { /* a pair is wholly inside or outside the tile interior */                        \
-            V o_;                                                                                                  \
-            o_.x = out0;                                                                                           \
-            o_.y = out1;                                                                                           \
-            *reinterpret_cast<V *>(eout + ((uint32_t)(k) * plane + (uint32_t)j * nx + ia)) = o_;                       \
+        if constexpr (VEC) {                                                                                       \
+            if ((k) < k1 && blk0) { /* a pair is wholly inside or outside the tile interior */                    \
+                V o_;                                                                                              \
+                o_.x = out0;                                                                                       \
+                o_.y = out1;                                                                                       \
+                *reinterpret_cast<V *>(eout + ((uint32_t)(k) * plane + (uint32_t)j * nx + ia)) = o_;                   \
+            }                                                                                                      \
+        } else if ((k) < k1) {                                                                                     \
+            const uint32_t o_ = (uint32_t)(k) * plane + (uint32_t)j * nx + ia;                                     \
+            if (blk0) eout[o_] = out0;                                                                             \
+            if (blk1) eout[o_ + 1] = out1;                                                                         \
         }                                                                                                          \
         pa0 = pb0;                                                                                                 \
         pa1 = pb1;                                                                                                 \
@@ -295,7 +319,7 @@ struct SwcRows<float> {
 };
 
 bool sweepC_fused_ok(const int n[3]) {
-    return n[0] >= 2 && (n[0] & 1) == 0 && (int64_t)n[0] * n[1] * n[2] >= SWC_MIN_CELLS;
+    return n[0] >= 2 && (int64_t)n[0] * n[1] * n[2] >= SWC_MIN_CELLS;
 }
 
 template <typename T>
@@ -316,7 +340,12 @@ hipError_t launch_sweepC_fused(const Coarse<T> &L, T *eout, hipStream_t s) {
     nchunk = (L.n[2] + kc - 1) / kc;
     const int ntiles = (int)(per_slab * nchunk);
     const int grid = ((ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_rbgsC_fused<T, BY, QD>), dim3(grid), dim3(32 * BY), 0, s, L, eout, ntx, nty, kc, ntiles);
+    if ((L.n[0] & 1) == 0)
+        hipLaunchKernelGGL((k_rbgsC_fused<T, BY, QD, true>), dim3(grid), dim3(32 * BY), 0, s, L, eout, ntx, nty, kc,
+                           ntiles);
+    else
+        hipLaunchKernelGGL((k_rbgsC_fused<T, BY, QD, false>), dim3(grid), dim3(32 * BY), 0, s, L, eout, ntx, nty, kc,
+                           ntiles);
     return hipGetLastError();
 }
 
