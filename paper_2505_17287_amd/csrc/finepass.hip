@@ -213,40 +213,68 @@ __global__ void __launch_bounds__(RT_NT)
     const int ox0 = owner ? M.cs[0][oI] - fx0 : 0, ox1 = owner ? M.cs[0][oI + 1] - fx0 : 0;
     const int oy0 = owner ? M.cs[1][oJ] - fy0 : 0, oy1 = owner ? M.cs[1][oJ + 1] - fy0 : 0;
     const int k0 = (K0 < K1) ? M.cs[2][K0] : 0, k1 = (K0 < K1) ? M.cs[2][K1] : 0;
+    // the loads of plane k+1 are issued before plane k is computed (RPlane: p at k+1 above
+    // the column, the in-plane neighbours, f, the type and the z metrics of plane k)
+    auto ld = [=](int k) -> RPlane<T> {
+        RPlane<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t base = (int64_t)kk * plane + rowoff;
+        d.pp = p[base + (kk < nz - 1 ? plane : 0)];
+        d.xm = p[base + dxm];
+        d.xp = p[base + dxp];
+        d.ym = p[base + dym];
+        d.yp = p[base + dyp];
+        d.fv = f[base];
+        d.ty = F.type[base];
+        d.azm = F.azm[kk];
+        d.azp = F.azp[kk];
+        d.wz = F.wz[kk];
+        return d;
+    };
     T pm = (k0 > 0) ? p[(int64_t)(k0 - 1) * plane + rowoff] : T(0);
-    T pc = (k0 < k1) ? p[(int64_t)k0 * plane + rowoff] : T(0);
+    T pc = p[(int64_t)min(k0, nz - 1) * plane + rowoff];
     T acc = 0;
     double psum = 0.0;
     int K = K0, kend = (K0 < K1) ? M.cs[2][K0 + 1] : 0;  // the coarse plane and its end
     int buf = 0;
-    for (int k = k0; k < k1; ++k) {
-        const int64_t base = (int64_t)k * plane + rowoff;
-        const T pp = (k < nz - 1) ? p[base + plane] : T(0);
-        T num, diag;
-        zm_stencil<T>(axm, axp, aym, ayp, F.azm[k], F.azp[k], hx0, hx1, hy0, hy1, k > 0, k < nz - 1, p[base + dxm],
-                      p[base + dxp], p[base + dym], p[base + dyp], pm, pp, num, diag);
-        const T r = (f[base] - lam) - (num - diag * pc);
-        sv[buf][ly][lx] = (in && F.type[base] == T_FLUID) ? (vxy * F.wz[k]) * r : T(0);
-        __syncthreads();
-        if (owner) {
-            for (int jj = oy0; jj < oy1; ++jj)
-                for (int ii = ox0; ii < ox1; ++ii) acc += sv[buf][jj][ii];
-        }
-        if (k + 1 == kend) {  // the coarse plane K is complete
-            if (owner) {
-                const int64_t cid = ((int64_t)K * C.n[1] + oJ) * C.n[0] + oI;
-                C.R[cid] = acc;
-                C.e[cid] = T(0);
-                psum += (double)acc;
-            }
-            acc = T(0);
-            ++K;
-            kend = (K < K1) ? M.cs[2][K + 1] : k1;
-        }
-        buf ^= 1;
-        pm = pc;
-        pc = pp;
+    // one fine plane; the loop is unrolled by two so the two plane slots change roles by name
+#define IBM_RMAP_PLANE(D, kk)                                                                                     \
+    {                                                                                                              \
+        const int k_ = (kk);                                                                                       \
+        T num, diag;                                                                                               \
+        zm_stencil<T>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,        \
+                      (D).xp, (D).ym, (D).yp, pm, (D).pp, num, diag);                                              \
+        const T r = ((D).fv - lam) - (num - diag * pc);                                                           \
+        sv[buf][ly][lx] = (in && (D).ty == T_FLUID) ? (vxy * (D).wz) * r : T(0);                                   \
+        __syncthreads();                                                                                           \
+        if (owner) {                                                                                               \
+            for (int jj = oy0; jj < oy1; ++jj)                                                                     \
+                for (int ii = ox0; ii < ox1; ++ii) acc += sv[buf][jj][ii];                                         \
+        }                                                                                                          \
+        if (k_ + 1 == kend) { /* the coarse plane K is complete */                                                \
+            if (owner) {                                                                                           \
+                const int64_t cid = ((int64_t)K * C.n[1] + oJ) * C.n[0] + oI;                                      \
+                C.R[cid] = acc;                                                                                    \
+                C.e[cid] = T(0);                                                                                   \
+                psum += (double)acc;                                                                               \
+            }                                                                                                      \
+            acc = T(0);                                                                                            \
+            ++K;                                                                                                   \
+            kend = (K < K1) ? M.cs[2][K + 1] : k1;                                                                 \
+        }                                                                                                          \
+        buf ^= 1;                                                                                                  \
+        pm = pc;                                                                                                   \
+        pc = (D).pp;                                                                                               \
     }
+    RPlane<T> qa = ld(k0), qb;
+    for (int k = k0; k < k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_RMAP_PLANE(qa, k);
+        if (k + 1 >= k1) break;
+        qa = ld(k + 2);
+        IBM_RMAP_PLANE(qb, k + 1);
+    }
+#undef IBM_RMAP_PLANE
     __shared__ double sh[RT_NT / 64];
     const double tot = block_sum<RT_NT>(psum, sh, threadIdx.x);
     if (threadIdx.x == 0) partials[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
