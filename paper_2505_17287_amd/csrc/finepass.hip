@@ -354,6 +354,115 @@ __global__ void __launch_bounds__(ZM_NT)
 #undef IBM_PROLONG_PLANE
 }
 
+// Prolongation for any child map, with the coarse values staged in LDS: a workgroup's 64 x 4
+// fine columns draw on at most PL_CW x PL_CH coarse columns, so each coarse plane the chunk
+// needs is read once into a ring of four LDS planes (the next one while the current fine
+// plane is computed) instead of eight gathers per fine cell.  Same arithmetic, order of
+// summation and injection rule as k_prolong0_zm.
+constexpr int PL_CW = 68, PL_CH = 6, PL_RING = 4, PL_PER = (PL_CW * PL_CH + ZM_NT - 1) / ZM_NT;
+
+template <typename T>
+struct PFine {
+    T pv;
+    uint8_t ty, inj;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(ZM_NT)
+    k_prolong0_lds(Fine<T> F, const T *__restrict__ pcur, T *__restrict__ pnext, Coarse<T> C, ProlongTab P,
+                   ZTiles t) {
+    __shared__ T ec[PL_RING][PL_CH][PL_CW];
+    const ZPos z = zpos(t, F.nz);
+    if (!z.live) return;
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    // the tile's coarse window (tables are monotone: lo non-decreasing, hi = lo or lo +- 1)
+    const int ia = min(z.i - z.lane, nx - 1), ib = min(z.i - z.lane + ZM_TX - 1, nx - 1);
+    const int ja = min(z.j - z.wave, ny - 1), jb = min(z.j - z.wave + ZM_TY - 1, ny - 1);
+    const int cx0 = min(P.lo[0][ia], P.hi[0][ia]), cx1 = max(P.lo[0][ib], P.hi[0][ib]);
+    const int cy0 = min(P.lo[1][ja], P.hi[1][ja]), cy1 = max(P.lo[1][jb], P.hi[1][jb]);
+    const int cw = cx1 - cx0 + 1, ch = cy1 - cy0 + 1;
+    const int ix[2] = {P.lo[0][ic] - cx0, P.hi[0][ic] - cx0}, iy[2] = {P.lo[1][jc] - cy0, P.hi[1][jc] - cy0};
+    const double tx = P.t[0][ic], ty = P.t[1][jc];
+    const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty};
+    const bool twox = ix[0] != ix[1], twoy = iy[0] != iy[1];
+    const int64_t cny = C.n[1], cnx = C.n[0];
+    // coarse values this thread stages for one coarse plane
+    auto cload = [=](int K, T (&v)[PL_PER]) {
+#pragma unroll
+        for (int q = 0; q < PL_PER; ++q) {
+            const int e = (int)threadIdx.x + q * ZM_NT;
+            const int r = e / PL_CW, c = e % PL_CW;
+            const bool ok = r < ch && c < cw;
+            v[q] = ok ? C.e[((int64_t)K * cny + cy0 + r) * cnx + cx0 + c] : T(0);
+        }
+    };
+    auto cstore = [&](int K, const T (&v)[PL_PER]) {
+#pragma unroll
+        for (int q = 0; q < PL_PER; ++q) {
+            const int e = (int)threadIdx.x + q * ZM_NT;
+            if (e < PL_CW * PL_CH) ec[K & (PL_RING - 1)][e / PL_CW][e % PL_CW] = v[q];
+        }
+    };
+    auto fload = [=](int k) -> PFine<T> {
+        PFine<T> d;
+        const int64_t base = (int64_t)min(k, nz - 1) * plane + rowoff;
+        d.pv = pcur[base];
+        d.ty = F.type[base];
+        d.inj = F.inject[base];
+        return d;
+    };
+    // coarse planes needed by fine plane k: [lo, hi] of its z table
+    auto need_hi = [=](int k) { return max(P.lo[2][k], P.hi[2][k]); };
+    const int k0 = z.k0, k1 = z.k1;
+    int have;  // highest coarse plane staged
+    {
+        const int a = min(P.lo[2][k0], P.hi[2][k0]), b = need_hi(k0);
+        T v[PL_PER];
+        for (int K = a; K <= b; ++K) {
+            cload(K, v);
+            cstore(K, v);
+        }
+        have = b;
+        __syncthreads();
+    }
+    PFine<T> qa = fload(k0);
+    for (int k = k0; k < k1; ++k) {
+        const PFine<T> qb = fload(k + 1);
+        // the next fine plane needs at most one more coarse plane: load it now, stage it after
+        const int nb = (k + 1 < nz) ? need_hi(k + 1) : have;
+        const bool more = nb > have;
+        T v[PL_PER];
+        if (more) cload(nb, v);
+        const int iz[2] = {P.lo[2][k], P.hi[2][k]};
+        const double tz = P.t[2][k];
+        const double wz[2] = {1.0 - tz, tz};
+        const bool twoz = iz[0] != iz[1];
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const bool ok = (a == 0 || twox) && (b == 0 || twoy) && (c == 0 || twoz);
+                    const double term = (wx[a] * wy[b]) * wz[c] * (double)ec[iz[c] & (PL_RING - 1)][iy[b]][ix[a]];
+                    if (ok) s += term;
+                }
+        if (qa.inj) s = (double)ec[iz[0] & (PL_RING - 1)][iy[0]][ix[0]];
+        if (in && qa.ty == T_FLUID) store_stream<T>(pnext + (int64_t)k * plane + rowoff, (T)((double)qa.pv + s));
+        if (more) {
+            __syncthreads();  // every thread is done with the slot the new plane goes to
+            cstore(nb, v);
+            have = nb;
+        }
+        __syncthreads();
+        qa = qb;
+    }
+}
+
 // Prolongation when z is halved (the usual case).  Fine planes 2K and 2K+1 have the coarse
 // plane K as their first contributor and K-1 or K+1 as their second, so a column needs one
 // new coarse plane per pair of fine planes: a window of three coarse planes (four
@@ -873,7 +982,7 @@ hipError_t launch_prolong0(const Fine<T> &F, const T *pcur, T *pnext, const Coar
     if (P.halved[2] && (F.nz & 1) == 0)
         hipLaunchKernelGGL(k_prolong0_zh<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
     else
-        hipLaunchKernelGGL(k_prolong0_zm<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
+        hipLaunchKernelGGL(k_prolong0_lds<T>, dim3(t.grid), dim3(ZM_NT), 0, s, F, pcur, pnext, C, P, t);
     return hipGetLastError();
 }
 
