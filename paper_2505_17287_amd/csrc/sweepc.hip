@@ -137,6 +137,10 @@ __global__ void __launch_bounds__(32 * BY)
     const int jy = min(max((ty == 0) ? j + 1 : j, 0), ny - 1);
     const uint32_t roff = (uint32_t)jr * nx + (VEC ? icv : ic0), yoff = (uint32_t)jy * nx + (VEC ? icv : ic0);
     const uint32_t d1 = VEC ? 1u : (uint32_t)(ic1 - ic0);  // offset of the second column
+    // unpaired path: the second column is missing at the high wall of an odd row, where the
+    // first column's high face is the wall (its x transmissibility must read 0, not the
+    // clamped copy of the first column's low face)
+    const bool x1in = VEC || ia + 1 < nx;
     const T vxy0 = in0 ? L.w[0][ia] * L.w[1][jc] : T(0);
     const T vxy1 = in1 ? L.w[0][ia + 1] * L.w[1][jc] : T(0);
     const T mu = (T)(*L.mu);
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(32 * BY)
             d.r.x = pr[base + roff];
             d.r.y = pr[base + roff + d1];
             d.x.x = px[base + roff];
-            d.x.y = px[base + roff + d1];
+            d.x.y = x1in ? px[base + roff + d1] : T(0);
             d.y.x = py[base + yoff];
             d.y.y = py[base + yoff + d1];
             d.z.x = pz[base + roff];
