@@ -359,8 +359,9 @@ ibm_status ibm_debug_vector(const ibm_grid *g, int which, double *dst_device, vo
 ibm_status ibm_debug_poison(ibm_grid *g, int on);
 
 /* Timing of the level-0 smoother.  on = 0: off.  on = n >= 1: every n-th fine-level
-   red-black sweep (counted from this call) is bracketed by HIP events on its launch stream
-   (at most 32 sweeps between two host synchronisations are timed); a stride above one keeps
+   red-black sweep (counted from this call) is timed by two HIP events that the runtime records
+   on its launch stream when the kernel starts and when it ends (hipExtLaunchKernel; at most 32
+   sweeps between two host synchronisations are timed); a stride above one keeps
    the events' own cost out of the timed run, and a stride coprime to the sweeps of a cycle
    samples every position in it.  on < 0 -> IBM_E_ARG.  get_profile returns the summed
    milliseconds and the number of timed FP64 and FP32 sweeps since profiling was switched on. */

@@ -59,9 +59,11 @@ struct Coarse {  // coarse-level view in precision T
     const double *mu;     // compatibility shift per unit volume (device scalar)
 };
 
-// fused red-black sweep of level 0 (sweep.hip): pout = one RB-GS sweep of pin
+// fused red-black sweep of level 0 (sweep.hip): pout = one RB-GS sweep of pin; ev0, ev1
+// (optional): events recorded when the kernel starts and when it ends
 template <typename T>
-hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s);
+hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // the same FP32 sweep writing its result widened to FP64, dead cells zero
 hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *pout, const float *f, const float *lam,
                               hipStream_t s);

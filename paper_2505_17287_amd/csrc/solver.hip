@@ -1155,17 +1155,18 @@ struct FineOf<float> {
 // bufs[0..1]: the two level-0 buffers, *cur: index of the current iterate.
 // rhs: level-0 right-hand side; lam: device scalar shift of the right-hand side;
 // gh: right-hand sides of the ghost equations (nullptr: homogeneous error equation).
-// level-0 sweep, bracketed by timing events when profiling is on
+// level-0 sweep, timed by start and end events when profiling is on
 template <typename T>
 static hipError_t timed_sweep(ibm_grid *g, const Fine<T> &F, const T *pin, T *pout, const T *rhs, const T *lam,
                               hipStream_t s) {
     Prof &P = g->prof;
     const bool rec = P.on && (P.seq++ % P.stride) == 0 && P.used + 2 <= (int)P.ev.size();
     hipError_t e;
-    if (rec && (e = hipEventRecord(P.ev[P.used], s)) != hipSuccess) return e;
-    if ((e = launch_sweep<T>(F, pin, pout, rhs, lam, s)) != hipSuccess) return e;
+    // the runtime records the two events at the kernel's own start and end
+    if ((e = launch_sweep<T>(F, pin, pout, rhs, lam, s, rec ? P.ev[P.used] : nullptr,
+                             rec ? P.ev[P.used + 1] : nullptr)) != hipSuccess)
+        return e;
     if (rec) {
-        if ((e = hipEventRecord(P.ev[P.used + 1], s)) != hipSuccess) return e;
         P.kind[P.used / 2] = (sizeof(T) == 8) ? 0 : 1;
         P.used += 2;
     }

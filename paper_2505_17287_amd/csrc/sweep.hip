@@ -1,6 +1,7 @@
 // Fused red-black Gauss-Seidel sweep of the fine level (paper Section 2.1: red-black
 // Gauss-Seidel smoothing of the pressure equation on a non-uniform Cartesian grid).
 // Kept in a file of its own: it is the kernel the bandwidth figures are quoted for.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -326,8 +327,10 @@ constexpr int SW_CHUNK_COST = 4;  // plane steps a z chunk costs beyond its own 
 // Tiles of 64 x BY columns (interior 60 x (BY - 4)).  The paired path (nx even) uses 32 rows:
 // one 1024-thread workgroup per CU, 12 % fewer halo rows re-read than two 16-row tiles; the
 // unpaired path keeps 16 rows (its larger register set would spill at 1024 threads).
+// ev0, ev1 (optional): events the runtime records when the kernel starts and ends
 template <typename T, typename TO, int BY, bool VEC>
-static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, TO *pout, const T *f, const T *lam, hipStream_t s) {
+static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, TO *pout, const T *f, const T *lam, hipStream_t s,
+                                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     constexpr int TXC = 2 * SW_BXT - 4, TY = BY - 4;
     const int ntx = (F.nx + TXC - 1) / TXC, nty = (F.ny + TY - 1) / TY;
     const int64_t per_slab = (int64_t)ntx * nty;
@@ -357,15 +360,20 @@ static hipError_t launch_sweep_tiles(const Fine<T> &F, const T *pin, TO *pout, c
     nchunk = (F.nz + kc - 1) / kc;
     const int ntiles = (int)(per_slab * nchunk);
     const int grid = ((ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_rbgs_fused<T, TO, SW_BXT, BY, VEC>), dim3(grid), dim3(SW_BXT * BY), 0, s, F, pin, pout, f, lam,
-                       ntx, nty, kc, ntiles);
+    if (ev0)
+        hipExtLaunchKernelGGL((k_rbgs_fused<T, TO, SW_BXT, BY, VEC>), dim3(grid), dim3(SW_BXT * BY), 0, s, ev0, ev1, 0, F,
+                              pin, pout, f, lam, ntx, nty, kc, ntiles);
+    else
+        hipLaunchKernelGGL((k_rbgs_fused<T, TO, SW_BXT, BY, VEC>), dim3(grid), dim3(SW_BXT * BY), 0, s, F, pin, pout, f,
+                           lam, ntx, nty, kc, ntiles);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s) {
-    if ((F.nx & 1) == 0) return launch_sweep_tiles<T, T, 32, true>(F, pin, pout, f, lam, s);
-    return launch_sweep_tiles<T, T, 16, false>(F, pin, pout, f, lam, s);
+hipError_t launch_sweep(const Fine<T> &F, const T *pin, T *pout, const T *f, const T *lam, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+    if ((F.nx & 1) == 0) return launch_sweep_tiles<T, T, 32, true>(F, pin, pout, f, lam, s, ev0, ev1);
+    return launch_sweep_tiles<T, T, 16, false>(F, pin, pout, f, lam, s, ev0, ev1);
 }
 
 hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *pout, const float *f, const float *lam,
@@ -375,8 +383,8 @@ hipError_t launch_sweep_widen(const Fine<float> &F, const float *pin, double *po
 }
 
 template hipError_t launch_sweep<double>(const Fine<double> &, const double *, double *, const double *,
-                                         const double *, hipStream_t);
+                                         const double *, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sweep<float>(const Fine<float> &, const float *, float *, const float *, const float *,
-                                        hipStream_t);
+                                        hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace ibm
