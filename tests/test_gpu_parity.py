@@ -350,3 +350,50 @@ def test_stretched_hierarchy_fixed_cycles(method):
         print(method, ncyc, "error", err, flush=True)
         assert err <= 1e-9
     g.close()
+
+
+def _hierarchy_cases():
+    """Grids whose level plans take the less common branches of the width-based coarsening:
+    a stretched 2D grid (one z cell), a tiny grid of odd counts below the merge limit on one
+    axis, and a grid whose z cells are four times wider than x and y (z kept until the others
+    catch up)."""
+    cases = {}
+    xf = I.stretched_faces(-8.0, 8.0, -2.0, 2.0, 96)
+    h = float(np.min(np.diff(xf)))
+    v, t = I.prism_mesh(0.5, 128, -1.0, 1.0)
+    cases["cyl2d_stretched"] = I.Workload("cyl2d_stretched", xf, xf.copy(), np.array([-h / 2, h / 2]), v, t, 3)
+    vs, ts = I.icosphere(3)
+    cases["tiny_odd"] = I.Workload("tiny_odd", np.linspace(-1, 1, 8), np.linspace(-1, 1, 6), np.linspace(-1, 1, 5),
+                                   vs * 0.45 + np.array([0.05, -0.03, 0.02]), ts, 4)
+    cases["coarse_z"] = I.Workload("coarse_z", np.linspace(-1, 1, 49), np.linspace(-1, 1, 49),
+                                   np.linspace(-1, 1, 13), vs * 0.5, ts, 5)
+    return cases
+
+
+@pytest.mark.parametrize("name", ["cyl2d_stretched", "tiny_odd", "coarse_z"])
+@pytest.mark.parametrize("method", ["vcycle", "bicgstab"])
+def test_hierarchy_branches_fixed_cycles(name, method):
+    torch = _torch()
+    from paper_2505_17287_amd import ibm
+    wl = _hierarchy_cases()[name]
+    print("hierarchy case", name, wl.shape, method, flush=True)
+    P = OracleProblem.from_workload(wl)
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf)
+    g.setup(wl.verts, wl.tris)
+    assert np.array_equal(g.cell_types().cpu().numpy(), P.types())
+    f = P.rhs(*wl.velocity())
+    act = P.types() != 2
+    fd = torch.from_numpy(f).cuda()
+    for ncyc in (1, 3):
+        pr, sr = P.solve(f, fixed_cycles=ncyc, method=method)
+        pg, sg = g.poisson_solve(fd, fixed_cycles=ncyc, method=method)
+        a = pg.cpu().numpy()
+        a, b = a - a[act].mean(), pr - pr[act].mean()
+        assert np.max(np.abs(a[act] - b[act])) <= 1e-9 * np.max(np.abs(b[act]))
+    pr, sr = P.solve(f, rel_tol=1e-12, max_cycles=400, method="bicgstab")
+    pg, sg = g.poisson_solve(fd, rel_tol=1e-12, max_cycles=400)
+    assert sg.status == 0 and sr.status == 0
+    a = pg.cpu().numpy()
+    a, b = a - a[act].mean(), pr - pr[act].mean()
+    assert np.max(np.abs(a[act] - b[act])) <= 1e-9 * np.max(np.abs(b[act]))
+    g.close()
