@@ -175,98 +175,146 @@ __global__ void __launch_bounds__(ZM_NT)
 }
 
 // Residual and restriction for any child map (cells merged on some axes only where they are
-// narrow).  A workgroup owns RT_CX x RT_CY coarse columns and a chunk of coarse planes; its
-// threads cover the fine columns of those coarse columns (at most 2 RT_CX x 2 RT_CY) and
-// march up the fine planes as k_restrict0_zm does (the planes below and above the column in
-// registers, in-plane neighbours through the caches), forming the residual
-// (f - lambda) - S p with the same arithmetic.  Per fine plane the volume-integrated
-// residuals of the fluid cells go to LDS, and one thread per coarse column adds its children
-// to its running sum in the oracle's order (x fastest, then y, plane by plane); the sum is
-// stored when the coarse plane's last fine plane is done.
-constexpr int RT_CX = 32, RT_CY = 2, RT_FX = 2 * RT_CX, RT_FY = 2 * RT_CY, RT_NT = RT_FX * RT_FY;
+// narrow).  A tile is RM_CX coarse columns x RM_W coarse rows x a chunk of coarse planes;
+// each wave owns one coarse row J (one or two fine rows), and lane l the fine column
+// cs_x[I0] + l (the children of RM_CX coarse columns span at most 64 columns).  The lane
+// marches up the fine planes with both fine rows in registers (the planes below and above
+// in registers, in-plane neighbours through the caches, the plane k+1 loads issued before
+// plane k is computed), forms the residual (f - lambda) - S p of each fine cell with the
+// arithmetic of k_restrict0_zm, and adds its volume-weighted value on fluid cells to a
+// running sum over the rows and fine planes of the current coarse plane.  When the coarse
+// plane is complete, lane I - I0 gathers the sums of the one or two lanes holding the
+// children of coarse column I (the same sum as the oracle's, in another order).  No data
+// crosses waves inside the march.  Workgroups take tiles in a grid-stride loop, in the
+// XCD-aware order (a contiguous range of tiles per XCD and round).
+constexpr int RM_CX = 32, RM_W = 4, RM_NT = 64 * RM_W;
+
+struct RMTiles {
+    int ntx, nty, kc, ntiles;
+};
 
 template <typename T>
-__global__ void __launch_bounds__(RT_NT)
-    k_restrict0_map(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
-                    Coarse<T> C, ChildMap M, int kc, double *partials) {
-    __shared__ T sv[2][RT_FY][RT_FX];
-    const int I0 = blockIdx.x * RT_CX, J0 = blockIdx.y * RT_CY;
-    const int K0 = blockIdx.z * kc, K1 = min(C.n[2], K0 + kc);
+struct RMPlane {
+    T pp0, pp1;  // p at plane k+1 above the lane's column, first and second row
+    T ylo, yhi;  // p at plane k in the rows below the first and above the last
+    T f0, f1;
+    T em0, ep0, em1, ep1;  // p at plane k just outside the tile's columns, both rows (uniform)
+    T azm, azp, wz;        // z metrics of plane k (uniform)
+    uint8_t t0, t1;
+};
+
+// One wave's coarse row J of the tile (I0..I1-1, K0..K1-1); TWO: the row has two fine rows.
+// Returns the sum of the R_1 values the wave stored (valid in every lane that stored one).
+template <typename T, bool TWO>
+__device__ __forceinline__ double restrict_map_row(const Fine<T> &F, const T *__restrict__ p,
+                                                   const T *__restrict__ f, T lam, const Coarse<T> &C,
+                                                   const ChildMap &M, int I0, int I1, int J, int K0, int K1,
+                                                   int lane) {
     const int nx = F.nx, ny = F.ny, nz = F.nz;
     const int64_t plane = (int64_t)nx * ny;
-    // fine span of the tile
-    const int fx0 = M.cs[0][I0], fx1 = M.cs[0][min(I0 + RT_CX, C.n[0])];
-    const int fy0 = M.cs[1][J0], fy1 = M.cs[1][min(J0 + RT_CY, C.n[1])];
-    const int lx = (int)threadIdx.x % RT_FX, ly = (int)threadIdx.x / RT_FX;
-    const int i = fx0 + lx, j = fy0 + ly;
-    const bool in = i < fx1 && j < fy1;
-    const int ic = min(i, nx - 1), jc = min(j, ny - 1);
-    const int64_t rowoff = (int64_t)jc * nx + ic;
-    const bool hx0 = ic > 0, hx1 = ic < nx - 1, hy0 = jc > 0, hy1 = jc < ny - 1;
-    const int64_t dxm = hx0 ? -1 : 0, dxp = hx1 ? 1 : 0, dym = hy0 ? -(int64_t)nx : 0, dyp = hy1 ? (int64_t)nx : 0;
-    const T axm = F.axm[ic], axp = F.axp[ic], aym = F.aym[jc], ayp = F.ayp[jc];
-    const T vxy = F.wx[ic] * F.wy[jc];
-    const T lam = *lamp;
-    // the owner thread of coarse column (I, J): its children, local to the tile's span
-    const int oI = I0 + (int)threadIdx.x % RT_CX, oJ = J0 + (int)threadIdx.x / RT_CX;
-    const bool owner = threadIdx.x < RT_CX * RT_CY && oI < C.n[0] && oJ < C.n[1];
-    const int ox0 = owner ? M.cs[0][oI] - fx0 : 0, ox1 = owner ? M.cs[0][oI + 1] - fx0 : 0;
-    const int oy0 = owner ? M.cs[1][oJ] - fy0 : 0, oy1 = owner ? M.cs[1][oJ + 1] - fy0 : 0;
-    const int k0 = (K0 < K1) ? M.cs[2][K0] : 0, k1 = (K0 < K1) ? M.cs[2][K1] : 0;
-    // the loads of plane k+1 are issued before plane k is computed (RPlane: p at k+1 above
-    // the column, the in-plane neighbours, f, the type and the z metrics of plane k)
-    auto ld = [=](int k) -> RPlane<T> {
-        RPlane<T> d;
+    const int fx0 = M.cs[0][I0], fx1 = M.cs[0][I1];
+    const int i = fx0 + lane;
+    const bool inx = i < fx1;
+    const int ic = min(i, nx - 1);
+    const int ja = M.cs[1][J], jb = TWO ? ja + 1 : ja;
+    const int64_t o0 = (int64_t)ja * nx + ic, o1 = (int64_t)jb * nx + ic;
+    const int64_t olo = (int64_t)max(ja - 1, 0) * nx + ic, ohi = (int64_t)min(jb + 1, ny - 1) * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1;
+    // the x neighbours come from the adjacent lanes (every lane holds its column, or the
+    // last column where it lies past the grid, whose value then meets a wall); lanes 0 and
+    // 63 take the columns just outside the tile from the edge loads.  The shuffles run in
+    // every lane before the edge lanes pick their loaded value: a shuffle evaluated only in
+    // some lanes would read the others' registers while they are switched off.
+    const int64_t eom = (int64_t)ja * nx + max(fx0 - 1, 0), eop = (int64_t)ja * nx + min(fx0 + 64, nx - 1);
+    const T axm = F.axm[ic], axp = F.axp[ic];
+    const T aym0 = F.aym[ja], ayp0 = F.ayp[ja], aym1 = F.aym[jb], ayp1 = F.ayp[jb];
+    const bool hy00 = ja > 0, hy10 = ja < ny - 1, hy01 = jb > 0, hy11 = jb < ny - 1;
+    const T vxy0 = F.wx[ic] * F.wy[ja], vxy1 = F.wx[ic] * F.wy[jb];
+    // the owner lane of coarse column I0 + lane: where its children sit among the lanes
+    const bool own = lane < I1 - I0;
+    const int Io = min(I0 + lane, I1);  // every lane reads inside the map
+    const int ca = own ? M.cs[0][Io] - fx0 : 0;
+    const bool pair = own && M.cs[0][min(Io + 1, I1)] - M.cs[0][Io] == 2;
+    const int cb = min(ca + 1, 63);
+    const int k0 = M.cs[2][K0], k1 = M.cs[2][K1];
+    auto ld = [=](int k) -> RMPlane<T> {
+        RMPlane<T> d;
         const int kk = min(k, nz - 1);
-        const int64_t base = (int64_t)kk * plane + rowoff;
-        d.pp = p[base + (kk < nz - 1 ? plane : 0)];
-        d.xm = p[base + dxm];
-        d.xp = p[base + dxp];
-        d.ym = p[base + dym];
-        d.yp = p[base + dyp];
-        d.fv = f[base];
-        d.ty = F.type[base];
+        const int64_t b = (int64_t)kk * plane;
+        const int64_t up = (kk < nz - 1) ? plane : 0;
+        d.pp0 = p[b + o0 + up];
+        d.em0 = p[b + eom];
+        d.ep0 = p[b + eop];
+        d.ylo = p[b + olo];
+        d.yhi = p[b + ohi];
+        d.f0 = f[b + o0];
+        d.t0 = F.type[b + o0];
+        if constexpr (TWO) {
+            d.pp1 = p[b + o1 + up];
+            d.em1 = p[b + eom + nx];
+            d.ep1 = p[b + eop + nx];
+            d.f1 = f[b + o1];
+            d.t1 = F.type[b + o1];
+        } else {
+            d.pp1 = d.em1 = d.ep1 = d.f1 = T(0);
+            d.t1 = 0;
+        }
         d.azm = F.azm[kk];
         d.azp = F.azp[kk];
         d.wz = F.wz[kk];
         return d;
     };
-    T pm = (k0 > 0) ? p[(int64_t)(k0 - 1) * plane + rowoff] : T(0);
-    T pc = p[(int64_t)min(k0, nz - 1) * plane + rowoff];
+    T pm0 = (k0 > 0) ? p[(int64_t)(k0 - 1) * plane + o0] : T(0);
+    T pc0 = p[(int64_t)k0 * plane + o0];
+    T pm1 = T(0), pc1 = T(0);
+    if constexpr (TWO) {
+        pm1 = (k0 > 0) ? p[(int64_t)(k0 - 1) * plane + o1] : T(0);
+        pc1 = p[(int64_t)k0 * plane + o1];
+    }
     T acc = 0;
     double psum = 0.0;
-    int K = K0, kend = (K0 < K1) ? M.cs[2][K0 + 1] : 0;  // the coarse plane and its end
-    int buf = 0;
+    int K = K0, kend = M.cs[2][K0 + 1];  // the coarse plane and its end
     // one fine plane; the loop is unrolled by two so the two plane slots change roles by name
 #define IBM_RMAP_PLANE(D, kk)                                                                                     \
     {                                                                                                              \
         const int k_ = (kk);                                                                                       \
         T num, diag;                                                                                               \
-        zm_stencil<T>(axm, axp, aym, ayp, (D).azm, (D).azp, hx0, hx1, hy0, hy1, k_ > 0, k_ < nz - 1, (D).xm,        \
-                      (D).xp, (D).ym, (D).yp, pm, (D).pp, num, diag);                                              \
-        const T r = ((D).fv - lam) - (num - diag * pc);                                                           \
-        sv[buf][ly][lx] = (in && (D).ty == T_FLUID) ? (vxy * (D).wz) * r : T(0);                                   \
-        __syncthreads();                                                                                           \
-        if (owner) {                                                                                               \
-            for (int jj = oy0; jj < oy1; ++jj)                                                                     \
-                for (int ii = ox0; ii < ox1; ++ii) acc += sv[buf][jj][ii];                                         \
+        const T su0_ = __shfl_up(pc0, 1, 64), sd0_ = __shfl_down(pc0, 1, 64); /* in every lane */               \
+        const T xm0_ = (lane == 0) ? (D).em0 : su0_;                                                               \
+        const T xp0_ = (lane == 63) ? (D).ep0 : sd0_;                                                              \
+        zm_stencil<T>(axm, axp, aym0, ayp0, (D).azm, (D).azp, hx0, hx1, hy00, hy10, k_ > 0, k_ < nz - 1, xm0_,     \
+                      xp0_, (D).ylo, TWO ? pc1 : (D).yhi, pm0, (D).pp0, num, diag);                                 \
+        const T r0 = ((D).f0 - lam) - (num - diag * pc0);                                                         \
+        acc += (inx && (D).t0 == T_FLUID) ? (vxy0 * (D).wz) * r0 : T(0);                                           \
+        if constexpr (TWO) {                                                                                       \
+            const T su1_ = __shfl_up(pc1, 1, 64), sd1_ = __shfl_down(pc1, 1, 64);                                 \
+            const T xm1_ = (lane == 0) ? (D).em1 : su1_;                                                           \
+            const T xp1_ = (lane == 63) ? (D).ep1 : sd1_;                                                          \
+            zm_stencil<T>(axm, axp, aym1, ayp1, (D).azm, (D).azp, hx0, hx1, hy01, hy11, k_ > 0, k_ < nz - 1,       \
+                          xm1_, xp1_, pc0, (D).yhi, pm1, (D).pp1, num, diag);                                        \
+            const T r1 = ((D).f1 - lam) - (num - diag * pc1);                                                     \
+            acc += (inx && (D).t1 == T_FLUID) ? (vxy1 * (D).wz) * r1 : T(0);                                       \
         }                                                                                                          \
         if (k_ + 1 == kend) { /* the coarse plane K is complete */                                                \
-            if (owner) {                                                                                           \
-                const int64_t cid = ((int64_t)K * C.n[1] + oJ) * C.n[0] + oI;                                      \
-                C.R[cid] = acc;                                                                                    \
+            T s = __shfl(acc, ca, 64);                                                                             \
+            const T s2 = __shfl(acc, cb, 64);                                                                      \
+            if (pair) s = s + s2;                                                                                  \
+            if (own) {                                                                                             \
+                const int64_t cid = ((int64_t)K * C.n[1] + J) * C.n[0] + I0 + lane;                                \
+                C.R[cid] = s;                                                                                      \
                 C.e[cid] = T(0);                                                                                   \
-                psum += (double)acc;                                                                               \
+                psum += (double)s;                                                                                 \
             }                                                                                                      \
             acc = T(0);                                                                                            \
             ++K;                                                                                                   \
-            kend = (K < K1) ? M.cs[2][K + 1] : k1;                                                                 \
+            kend = M.cs[2][min(K + 1, K1)];                                                                        \
         }                                                                                                          \
-        buf ^= 1;                                                                                                  \
-        pm = pc;                                                                                                   \
-        pc = (D).pp;                                                                                               \
+        pm0 = pc0;                                                                                                 \
+        pc0 = (D).pp0;                                                                                             \
+        pm1 = pc1;                                                                                                 \
+        pc1 = (D).pp1;                                                                                             \
     }
-    RPlane<T> qa = ld(k0), qb;
+    RMPlane<T> qa = ld(k0), qb;
     for (int k = k0; k < k1; k += 2) {
         qb = ld(k + 1);
         IBM_RMAP_PLANE(qa, k);
@@ -275,9 +323,36 @@ __global__ void __launch_bounds__(RT_NT)
         IBM_RMAP_PLANE(qb, k + 1);
     }
 #undef IBM_RMAP_PLANE
-    __shared__ double sh[RT_NT / 64];
-    const double tot = block_sum<RT_NT>(psum, sh, threadIdx.x);
-    if (threadIdx.x == 0) partials[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+    return psum;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RM_NT)
+    k_restrict0_map(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
+                    Coarse<T> C, ChildMap M, RMTiles t, double *partials) {
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const T lam = *lamp;
+    double psum = 0.0;
+    const int per = gridDim.x >> 3;  // the grid is a multiple of 8
+    for (int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3); tile < t.ntiles; tile += gridDim.x) {
+        int q = tile;
+        const int txi = q % t.ntx;
+        q /= t.ntx;
+        const int tyi = q % t.nty;
+        const int chunk = q / t.nty;
+        const int J = tyi * RM_W + wave;
+        if (J >= C.n[1]) continue;
+        const int I0 = txi * RM_CX, I1 = min(I0 + RM_CX, C.n[0]);
+        const int K0 = chunk * t.kc, K1 = min(C.n[2], K0 + t.kc);
+        if (M.cs[1][J + 1] - M.cs[1][J] == 2)
+            psum += restrict_map_row<T, true>(F, p, f, lam, C, M, I0, I1, J, K0, K1, lane);
+        else
+            psum += restrict_map_row<T, false>(F, p, f, lam, C, M, I0, I1, J, K0, K1, lane);
+    }
+    __shared__ double sh[RM_NT / 64];
+    const double tot = block_sum<RM_NT>(psum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 // ---- prolongation ------------------------------------------------------------------------
@@ -948,16 +1023,23 @@ template <typename T>
 hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
                             const ChildMap &M, double *partials, int *nparts, hipStream_t s) {
     if (!((M.halved[0] || M.same[0]) && (M.halved[1] || M.same[1]) && (M.halved[2] || M.same[2]))) {
-        // some axis merges only part of its cells: the generic pass, with about 16 workgroups
-        // per CU (z chunks), at most zmarch_partials_max partials
-        const int gx = (C.n[0] + RT_CX - 1) / RT_CX, gy = (C.n[1] + RT_CY - 1) / RT_CY;
+        // some axis merges only part of its cells: the generic pass, about 16 tiles per CU (z
+        // chunks), at most zmarch_partials_max workgroups (a grid-stride loop takes the rest)
+        RMTiles t;
+        t.ntx = (C.n[0] + RM_CX - 1) / RM_CX;
+        t.nty = (C.n[1] + RM_W - 1) / RM_W;
+        const int64_t per_slab = (int64_t)t.ntx * t.nty;
         const int64_t want = (int64_t)16 * device_cu_count();
-        int gz = (int)std::max<int64_t>(1, std::min<int64_t>(C.n[2], want / std::max(1, gx * gy)));
-        gz = (int)std::min<int64_t>(gz, std::max<int64_t>(1, zmarch_partials_max(F.nx, F.ny, F.nz) / ((int64_t)gx * gy)));
-        const int kc = (C.n[2] + gz - 1) / gz;
-        gz = (C.n[2] + kc - 1) / kc;
-        hipLaunchKernelGGL(k_restrict0_map<T>, dim3(gx, gy, gz), dim3(RT_NT), 0, s, F, p, f, lam, C, M, kc, partials);
-        *nparts = gx * gy * gz;
+        int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(C.n[2], want / per_slab));
+        t.kc = (C.n[2] + nchunk - 1) / nchunk;
+        nchunk = (C.n[2] + t.kc - 1) / t.kc;
+        const int64_t ntiles = per_slab * nchunk;
+        if (ntiles > INT32_MAX) return hipErrorInvalidValue;
+        t.ntiles = (int)ntiles;
+        const int64_t cap = std::max<int64_t>(8, zmarch_partials_max(F.nx, F.ny, F.nz) / 8 * 8);
+        const int grid = (int)std::min<int64_t>((ntiles + 7) / 8 * 8, cap);
+        hipLaunchKernelGGL(k_restrict0_map<T>, dim3(grid), dim3(RM_NT), 0, s, F, p, f, lam, C, M, t, partials);
+        *nparts = grid;
         return hipGetLastError();
     }
     const int halved[3] = {M.halved[0], M.halved[1], M.halved[2]};
