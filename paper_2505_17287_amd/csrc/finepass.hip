@@ -187,11 +187,7 @@ __global__ void __launch_bounds__(ZM_NT)
 // children of coarse column I (the same sum as the oracle's, in another order).  No data
 // crosses waves inside the march.  Workgroups take tiles in a grid-stride loop, in the
 // XCD-aware order (a contiguous range of tiles per XCD and round).
-constexpr int RM_CX = 32, RM_W = 4, RM_NT = 64 * RM_W;
-
-struct RMTiles {
-    int ntx, nty, kc, ntiles;
-};
+constexpr int RM_TILES_PER_CU = 16, RM_KMIN = 1;  // tiles per CU, least coarse planes per tile
 
 template <typename T>
 struct RMPlane {
@@ -329,7 +325,7 @@ __device__ __forceinline__ double restrict_map_row(const Fine<T> &F, const T *__
 template <typename T>
 __global__ void __launch_bounds__(RM_NT)
     k_restrict0_map(Fine<T> F, const T *__restrict__ p, const T *__restrict__ f, const T *__restrict__ lamp,
-                    Coarse<T> C, ChildMap M, RMTiles t, double *partials) {
+                    Coarse<T> C, ChildMap M, RowTiles t, double *partials) {
     const int lane = (int)threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const T lam = *lamp;
@@ -1023,21 +1019,11 @@ template <typename T>
 hipError_t launch_restrict0(const Fine<T> &F, const T *p, const T *f, const T *lam, const Coarse<T> &C,
                             const ChildMap &M, double *partials, int *nparts, hipStream_t s) {
     if (!((M.halved[0] || M.same[0]) && (M.halved[1] || M.same[1]) && (M.halved[2] || M.same[2]))) {
-        // some axis merges only part of its cells: the generic pass, about 16 tiles per CU (z
-        // chunks), at most zmarch_partials_max workgroups (a grid-stride loop takes the rest)
-        RMTiles t;
-        t.ntx = (C.n[0] + RM_CX - 1) / RM_CX;
-        t.nty = (C.n[1] + RM_W - 1) / RM_W;
-        const int64_t per_slab = (int64_t)t.ntx * t.nty;
-        const int64_t want = (int64_t)16 * device_cu_count();
-        int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(C.n[2], want / per_slab));
-        t.kc = (C.n[2] + nchunk - 1) / nchunk;
-        nchunk = (C.n[2] + t.kc - 1) / t.kc;
-        const int64_t ntiles = per_slab * nchunk;
-        if (ntiles > INT32_MAX) return hipErrorInvalidValue;
-        t.ntiles = (int)ntiles;
-        const int64_t cap = std::max<int64_t>(8, zmarch_partials_max(F.nx, F.ny, F.nz) / 8 * 8);
-        const int grid = (int)std::min<int64_t>((ntiles + 7) / 8 * 8, cap);
+        // some axis merges only part of its cells: the generic pass
+        RowTiles t;
+        int grid;
+        const hipError_t e = row_tiles(C.n, RM_TILES_PER_CU, RM_KMIN, zmarch_partials_max(F.nx, F.ny, F.nz), &t, &grid);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_restrict0_map<T>, dim3(grid), dim3(RM_NT), 0, s, F, p, f, lam, C, M, t, partials);
         *nparts = grid;
         return hipGetLastError();
@@ -1096,6 +1082,22 @@ hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *
     const ZTiles t = ztiles(F.nx, F.ny, F.nz);
     hipLaunchKernelGGL(k_jacobi0_zm, dim3(t.grid), dim3(ZM_NT), 0, s, F, y, f, out, omega, t);
     return hipGetLastError();
+}
+
+hipError_t row_tiles(const int cn[3], int per_cu, int kmin, int64_t cap, RowTiles *t, int *grid) {
+    t->ntx = (cn[0] + RM_CX - 1) / RM_CX;
+    t->nty = (cn[1] + RM_W - 1) / RM_W;
+    const int64_t per_slab = (int64_t)t->ntx * t->nty;
+    const int64_t want = (int64_t)per_cu * device_cu_count();
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(want / per_slab, cn[2] / std::max(1, kmin)));
+    t->kc = (cn[2] + nchunk - 1) / nchunk;
+    nchunk = (cn[2] + t->kc - 1) / t->kc;
+    const int64_t ntiles = per_slab * nchunk;
+    if (ntiles > INT32_MAX) return hipErrorInvalidValue;
+    t->ntiles = (int)ntiles;
+    cap = std::max<int64_t>(8, cap / 8 * 8);
+    *grid = (int)std::min<int64_t>((ntiles + 7) / 8 * 8, cap);
+    return hipSuccess;
 }
 
 // upper bound of the workgroup count of any z-march launch, whatever the CU count

@@ -108,6 +108,17 @@ hipError_t launch_jacobi0(const Fine<double> &F, const double *y, const double *
                           hipStream_t s);
 int64_t zmarch_partials_max(int nx, int ny, int nz);
 
+// Tiling of the row-wise restrictions (a wave per coarse row: RM_CX coarse columns, RM_W
+// coarse rows and kc coarse planes per workgroup of 64 RM_W threads), taken tile by tile
+// in a grid-stride loop.  row_tiles picks the z chunks for about per_cu tiles per CU with
+// at least kmin coarse planes each (fewer when the level has fewer) and returns the grid:
+// a multiple of 8, at most the tile count rounded up and at most cap (a multiple of 8).
+constexpr int RM_CX = 32, RM_W = 4, RM_NT = 64 * RM_W;
+struct RowTiles {
+    int ntx, nty, kc, ntiles;
+};
+hipError_t row_tiles(const int cn[3], int per_cu, int kmin, int64_t cap, RowTiles *t, int *grid);
+
 struct GhostView {
     int64_t ng;
     const int32_t *cell;

@@ -286,6 +286,200 @@ __global__ void k_resrestrictC(Coarse<T> L, Coarse<T> C, ChildMap M, double *par
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// The same for any child map, row-wise (the tiling of the level-0 restriction k_restrict0_map):
+// a wave owns one coarse row J (one or two finer rows) of a tile of RM_CX coarse columns, a
+// lane one finer column, and the lane marches up the finer planes with both rows in
+// registers; the x neighbours and the high x face come from the adjacent lanes (lanes 0 and
+// 63 from edge loads), the high y face of the first row is the second row's low face, the
+// high z face the next plane's low face, loaded with that plane.  Per cell the operations
+// are those of coarse_stencil; each lane sums its active cells over the rows and planes of
+// the current coarse plane, and when that plane is complete lane I - I0 adds the sums of the
+// one or two lanes holding the children of coarse column I (the same sum as
+// k_resrestrictC's, in another order).
+// the row-wise pass from levels of at least this many cells (below, a thread per coarse cell)
+constexpr int64_t RC_MAP_MIN_CELLS = 1 << 17;
+constexpr int RC_TILES_PER_CU = 8, RC_KMIN = 4;
+
+template <typename T>
+struct RCPlane {
+    T en0, en1, tzn0, tzn1;  // e and the low z face of plane k+1
+    T r0, r1, tx0, tx1, ty0, ty1;
+    T ylo, yhi, tyh;         // e below the first and above the last row, the low y face above the last
+    T eL0, eR0, eL1, eR1, txR0, txR1;  // e just outside the tile's columns, the low x face right of it
+    T w2;
+    uint8_t a0, a1;
+};
+
+template <typename T, bool TWO>
+__device__ __forceinline__ double resrestrict_row(const Coarse<T> &L, const Coarse<T> &C, const ChildMap &M, T mu,
+                                                  int I0, int I1, int J, int K0, int K1, int lane) {
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const int64_t plane = (int64_t)nx * ny;
+    const int fx0 = M.cs[0][I0], fx1 = M.cs[0][I1];
+    const int i = fx0 + lane;
+    const bool inx = i < fx1;
+    const int ic = min(i, nx - 1);
+    const int ja = M.cs[1][J], jb = TWO ? ja + 1 : ja;
+    const int64_t o0 = (int64_t)ja * nx + ic, o1 = (int64_t)jb * nx + ic;
+    const int64_t olo = (int64_t)max(ja - 1, 0) * nx + ic, ohi = (int64_t)min(jb + 1, ny - 1) * nx + ic;
+    const bool hx0 = ic > 0, hx1 = ic < nx - 1;
+    const bool hy00 = ja > 0, hy10 = ja < ny - 1, hy01 = jb > 0, hy11 = jb < ny - 1;
+    const int64_t eom = (int64_t)ja * nx + max(fx0 - 1, 0), eop = (int64_t)ja * nx + min(fx0 + 64, nx - 1);
+    const T w0 = L.w[0][ic];
+    const T vxy0 = w0 * L.w[1][ja], vxy1 = w0 * L.w[1][jb];
+    const bool own = lane < I1 - I0;
+    const int Io = min(I0 + lane, I1);
+    const int ca = own ? M.cs[0][Io] - fx0 : 0;
+    const bool pair = own && M.cs[0][min(Io + 1, I1)] - M.cs[0][Io] == 2;
+    const int cb = min(ca + 1, 63);
+    const int k0 = M.cs[2][K0], k1 = M.cs[2][K1];
+    const T *__restrict__ pe = L.e;
+    const T *__restrict__ pr = L.R;
+    const T *__restrict__ px = L.Tl[0];
+    const T *__restrict__ py = L.Tl[1];
+    const T *__restrict__ pz = L.Tl[2];
+    auto ld = [=](int k) -> RCPlane<T> {
+        RCPlane<T> d;
+        const int kk = min(k, nz - 1);
+        const int64_t b = (int64_t)kk * plane, bn = (int64_t)min(kk + 1, nz - 1) * plane;
+        d.en0 = pe[bn + o0];
+        d.tzn0 = pz[bn + o0];
+        d.r0 = pr[b + o0];
+        d.tx0 = px[b + o0];
+        d.ty0 = py[b + o0];
+        d.a0 = L.active[b + o0];
+        d.ylo = pe[b + olo];
+        d.yhi = pe[b + ohi];
+        d.tyh = py[b + ohi];
+        d.eL0 = pe[b + eom];
+        d.eR0 = pe[b + eop];
+        d.txR0 = px[b + eop];
+        if constexpr (TWO) {
+            d.en1 = pe[bn + o1];
+            d.tzn1 = pz[bn + o1];
+            d.r1 = pr[b + o1];
+            d.tx1 = px[b + o1];
+            d.ty1 = py[b + o1];
+            d.a1 = L.active[b + o1];
+            d.eL1 = pe[b + eom + nx];
+            d.eR1 = pe[b + eop + nx];
+            d.txR1 = px[b + eop + nx];
+        } else {
+            d.en1 = d.tzn1 = d.r1 = d.tx1 = d.ty1 = d.eL1 = d.eR1 = d.txR1 = T(0);
+            d.a1 = 0;
+        }
+        d.w2 = L.w[2][kk];
+        return d;
+    };
+    T em0 = (k0 > 0) ? pe[(int64_t)(k0 - 1) * plane + o0] : T(0);
+    T ec0 = pe[(int64_t)k0 * plane + o0], tzc0 = pz[(int64_t)k0 * plane + o0];
+    T em1 = T(0), ec1 = T(0), tzc1 = T(0);
+    if constexpr (TWO) {
+        em1 = (k0 > 0) ? pe[(int64_t)(k0 - 1) * plane + o1] : T(0);
+        ec1 = pe[(int64_t)k0 * plane + o1];
+        tzc1 = pz[(int64_t)k0 * plane + o1];
+    }
+    T acc = 0;
+    double psum = 0.0;
+    int K = K0, kend = M.cs[2][K0 + 1];
+    // one cell of plane k: coarse_stencil's operations, then the residual
+#define IBM_RC_CELL(TXM, TXP, TYM, TYP, TZM, TZP, XM, XP, YM, YP, ZM, ZP, EC, HY0, HY1, RV, VXY, W2, ACT)      \
+    {                                                                                                          \
+        const T txp_ = hx1 ? (TXP) : T(0), typ_ = (HY1) ? (TYP) : T(0), tzp_ = hz1_ ? (TZP) : T(0);            \
+        T s_ = 0;                                                                                              \
+        s_ = s_ + (hx0 ? (TXM) * (XM) : T(0));                                                                 \
+        s_ = s_ + (hx1 ? txp_ * (XP) : T(0));                                                                  \
+        s_ = s_ + ((HY0) ? (TYM) * (YM) : T(0));                                                               \
+        s_ = s_ + ((HY1) ? typ_ * (YP) : T(0));                                                                \
+        s_ = s_ + (hz0_ ? (TZM) * (ZM) : T(0));                                                                \
+        s_ = s_ + (hz1_ ? tzp_ * (ZP) : T(0));                                                                 \
+        T d_ = (TXM) + txp_;                                                                                   \
+        d_ = d_ + (TYM);                                                                                       \
+        d_ = d_ + typ_;                                                                                        \
+        d_ = d_ + (TZM);                                                                                       \
+        d_ = d_ + tzp_;                                                                                        \
+        const T vol_ = (VXY) * (W2);                                                                           \
+        const T rc_ = ((RV) - vol_ * mu) - (s_ - d_ * (EC));                                                   \
+        acc += (inx && (ACT)) ? rc_ : T(0);                                                                    \
+    }
+#define IBM_RC_PLANE(D, kk)                                                                                    \
+    {                                                                                                          \
+        const int k_ = (kk);                                                                                   \
+        const bool hz0_ = k_ > 0, hz1_ = k_ < nz - 1;                                                          \
+        /* shuffles in every lane; the edge lanes then pick their loaded values */                             \
+        const T su0_ = __shfl_up(ec0, 1, 64), sd0_ = __shfl_down(ec0, 1, 64), st0_ = __shfl_down((D).tx0, 1, 64); \
+        IBM_RC_CELL((D).tx0, lane == 63 ? (D).txR0 : st0_, (D).ty0, TWO ? (D).ty1 : (D).tyh, tzc0, (D).tzn0,     \
+                    lane == 0 ? (D).eL0 : su0_, lane == 63 ? (D).eR0 : sd0_, (D).ylo, TWO ? ec1 : (D).yhi, em0,  \
+                    (D).en0, ec0, hy00, hy10, (D).r0, vxy0, (D).w2, (D).a0 != 0);                              \
+        if constexpr (TWO) {                                                                                   \
+            const T su1_ = __shfl_up(ec1, 1, 64), sd1_ = __shfl_down(ec1, 1, 64),                              \
+                    st1_ = __shfl_down((D).tx1, 1, 64);                                                        \
+            IBM_RC_CELL((D).tx1, lane == 63 ? (D).txR1 : st1_, (D).ty1, (D).tyh, tzc1, (D).tzn1,               \
+                        lane == 0 ? (D).eL1 : su1_, lane == 63 ? (D).eR1 : sd1_, ec0, (D).yhi, em1, (D).en1, ec1, \
+                        hy01, hy11, (D).r1, vxy1, (D).w2, (D).a1 != 0);                                        \
+        }                                                                                                      \
+        if (k_ + 1 == kend) { /* the coarse plane K is complete */                                            \
+            T s = __shfl(acc, ca, 64);                                                                         \
+            const T s2 = __shfl(acc, cb, 64);                                                                  \
+            if (pair) s = s + s2;                                                                              \
+            if (own) {                                                                                         \
+                const int64_t cid = ((int64_t)K * C.n[1] + J) * C.n[0] + I0 + lane;                            \
+                C.R[cid] = s;                                                                                  \
+                C.e[cid] = T(0);                                                                               \
+                psum += (double)s;                                                                             \
+            }                                                                                                  \
+            acc = T(0);                                                                                        \
+            ++K;                                                                                               \
+            kend = M.cs[2][min(K + 1, K1)];                                                                    \
+        }                                                                                                      \
+        em0 = ec0;                                                                                             \
+        ec0 = (D).en0;                                                                                         \
+        tzc0 = (D).tzn0;                                                                                       \
+        em1 = ec1;                                                                                             \
+        ec1 = (D).en1;                                                                                         \
+        tzc1 = (D).tzn1;                                                                                       \
+    }
+    RCPlane<T> qa = ld(k0), qb;
+    for (int k = k0; k < k1; k += 2) {
+        qb = ld(k + 1);
+        IBM_RC_PLANE(qa, k);
+        if (k + 1 >= k1) break;
+        qa = ld(k + 2);
+        IBM_RC_PLANE(qb, k + 1);
+    }
+#undef IBM_RC_PLANE
+#undef IBM_RC_CELL
+    return psum;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RM_NT)
+    k_resrestrictC_map(Coarse<T> L, Coarse<T> C, ChildMap M, RowTiles t, double *partials) {
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const T mu = (T)(*L.mu);
+    double psum = 0.0;
+    const int per = gridDim.x >> 3;  // the grid is a multiple of 8
+    for (int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3); tile < t.ntiles; tile += gridDim.x) {
+        int q = tile;
+        const int txi = q % t.ntx;
+        q /= t.ntx;
+        const int tyi = q % t.nty;
+        const int chunk = q / t.nty;
+        const int J = tyi * RM_W + wave;
+        if (J >= C.n[1]) continue;
+        const int I0 = txi * RM_CX, I1 = min(I0 + RM_CX, C.n[0]);
+        const int K0 = chunk * t.kc, K1 = min(C.n[2], K0 + t.kc);
+        if (M.cs[1][J + 1] - M.cs[1][J] == 2)
+            psum += resrestrict_row<T, true>(L, C, M, mu, I0, I1, J, K0, K1, lane);
+        else
+            psum += resrestrict_row<T, false>(L, C, M, mu, I0, I1, J, K0, K1, lane);
+    }
+    __shared__ double sh[RM_NT / 64];
+    const double tot = block_sum<RM_NT>(psum, sh, threadIdx.x);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 // The same for a level pair with every axis halved: a thread per coarse cell loads its
 // 2 x 2 x 2 children as x pairs (one vector access per row and array), the neighbour layers
 // around the block and the high-face transmissibilities once, all before any arithmetic,
@@ -1251,10 +1445,17 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
             Coarse<T> C = coarse_view<T>(g, l + 1);
             const ChildMap M = child_map(g->lev[l + 1]);
             int nbc = nblk(g->lev[l + 1].ncell());
-            if (M.halved[0] && M.halved[1] && M.halved[2])
+            if (M.halved[0] && M.halved[1] && M.halved[2]) {
                 hipLaunchKernelGGL(k_resrestrictC8<T>, dim3(nbc), dim3(256), 0, s, L, C, g->partials);
-            else
+            } else if (g->lev[l].ncell() >= RC_MAP_MIN_CELLS) {
+                RowTiles t;
+                if ((e = row_tiles(C.n, RC_TILES_PER_CU, RC_KMIN, zmarch_partials_max(g->nx, g->ny, g->nz), &t,
+                                   &nbc)) != hipSuccess)
+                    return e;
+                hipLaunchKernelGGL(k_resrestrictC_map<T>, dim3(nbc), dim3(RM_NT), 0, s, L, C, M, t, g->partials);
+            } else {
                 hipLaunchKernelGGL(k_resrestrictC<T>, dim3(nbc), dim3(256), 0, s, L, C, M, g->partials);
+            }
             nparts = nbc;
             if (!(tail && l + 1 == lt))
                 hipLaunchKernelGGL(k_finalize_mu, dim3(1), dim3(256), 0, s, g->partials, nbc, &g->sc->vol[l + 1],
