@@ -15,6 +15,7 @@
 
 #include "device_util.hpp"
 #include "ibm_impl.hpp"
+#include "zmarch.hpp"
 
 namespace ibm {
 
@@ -1085,6 +1086,117 @@ __global__ void k_prolongC(Coarse<T> L, Coarse<T> C, ProlongTab P) {
     L.e[id] = (T)((double)L.e[id] + prolong_value(C, P, i, j, k));
 }
 
+// The same for any child map, on large levels, with the coarser values staged in LDS: the
+// tiling and the ring of coarser planes of the level-0 prolongation k_prolong0_lds (a
+// workgroup's 64 x 4 columns draw on at most PLC_CW x PLC_CH coarser columns; each coarser
+// plane it needs is read once, values and activity, the next one while the current plane is
+// computed).  Per cell the terms, their order and the fallback to the parent are those of
+// prolong_value, so the result is bitwise that of k_prolongC.
+constexpr int PLC_CW = 68, PLC_CH = 6, PLC_RING = 4, PLC_PER = (PLC_CW * PLC_CH + ZM_NT - 1) / ZM_NT;
+constexpr int64_t PROLONG_LDS_MIN_CELLS = 1 << 18;
+
+template <typename T>
+__global__ void __launch_bounds__(ZM_NT) k_prolongC_lds(Coarse<T> L, Coarse<T> C, ProlongTab P, ZTiles t) {
+    __shared__ T ec[PLC_RING][PLC_CH][PLC_CW];
+    __shared__ uint8_t ca[PLC_RING][PLC_CH][PLC_CW];
+    const ZPos z = zpos(t, L.n[2]);
+    if (!z.live) return;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const bool in = z.i < nx && z.j < ny;
+    const int ic = min(z.i, nx - 1), jc = min(z.j, ny - 1);
+    const int64_t plane = (int64_t)nx * ny, rowoff = (int64_t)jc * nx + ic;
+    // the tile's coarser window (tables are monotone: lo non-decreasing, hi = lo or lo +- 1)
+    const int ia = min(z.i - z.lane, nx - 1), ib = min(z.i - z.lane + ZM_TX - 1, nx - 1);
+    const int ja = min(z.j - z.wave, ny - 1), jb = min(z.j - z.wave + ZM_TY - 1, ny - 1);
+    const int cx0 = min(P.lo[0][ia], P.hi[0][ia]), cx1 = max(P.lo[0][ib], P.hi[0][ib]);
+    const int cy0 = min(P.lo[1][ja], P.hi[1][ja]), cy1 = max(P.lo[1][jb], P.hi[1][jb]);
+    const int cw = cx1 - cx0 + 1, ch = cy1 - cy0 + 1;
+    const int ix[2] = {P.lo[0][ic] - cx0, P.hi[0][ic] - cx0}, iy[2] = {P.lo[1][jc] - cy0, P.hi[1][jc] - cy0};
+    const double tx = P.t[0][ic], ty = P.t[1][jc];
+    const double wx[2] = {1.0 - tx, tx}, wy[2] = {1.0 - ty, ty};
+    const bool twox = ix[0] != ix[1], twoy = iy[0] != iy[1];
+    const int64_t cny = C.n[1], cnx = C.n[0];
+    // coarser values and activity this thread stages for one coarser plane
+    auto cload = [=](int K, T (&v)[PLC_PER], uint8_t (&a)[PLC_PER]) {
+#pragma unroll
+        for (int q = 0; q < PLC_PER; ++q) {
+            const int e = (int)threadIdx.x + q * ZM_NT;
+            const int r = e / PLC_CW, c = e % PLC_CW;
+            const bool ok = r < ch && c < cw;
+            const int64_t id = ((int64_t)K * cny + cy0 + min(r, ch - 1)) * cnx + cx0 + min(c, cw - 1);
+            v[q] = ok ? C.e[id] : T(0);
+            a[q] = ok ? C.active[id] : (uint8_t)0;
+        }
+    };
+    auto cstore = [&](int K, const T (&v)[PLC_PER], const uint8_t (&a)[PLC_PER]) {
+#pragma unroll
+        for (int q = 0; q < PLC_PER; ++q) {
+            const int e = (int)threadIdx.x + q * ZM_NT;
+            if (e < PLC_CW * PLC_CH) {
+                ec[K & (PLC_RING - 1)][e / PLC_CW][e % PLC_CW] = v[q];
+                ca[K & (PLC_RING - 1)][e / PLC_CW][e % PLC_CW] = a[q];
+            }
+        }
+    };
+    auto need_hi = [=](int k) { return max(P.lo[2][k], P.hi[2][k]); };
+    const int k0 = z.k0, k1 = z.k1;
+    int have;  // highest coarser plane staged
+    {
+        const int a = min(P.lo[2][k0], P.hi[2][k0]), b = need_hi(k0);
+        T v[PLC_PER];
+        uint8_t av[PLC_PER];
+        for (int K = a; K <= b; ++K) {
+            cload(K, v, av);
+            cstore(K, v, av);
+        }
+        have = b;
+        __syncthreads();
+    }
+    T ecur = L.e[(int64_t)k0 * plane + rowoff];
+    uint8_t acur = L.active[(int64_t)k0 * plane + rowoff];
+    for (int k = k0; k < k1; ++k) {
+        const int64_t nbase = (int64_t)min(k + 1, nz - 1) * plane + rowoff;
+        const T enext = L.e[nbase];
+        const uint8_t anext = L.active[nbase];
+        // the next plane needs at most one more coarser plane: load it now, stage it after
+        const int nb = (k + 1 < nz) ? need_hi(k + 1) : have;
+        const bool more = nb > have;
+        T v[PLC_PER];
+        uint8_t av[PLC_PER];
+        if (more) cload(nb, v, av);
+        const int iz[2] = {P.lo[2][k], P.hi[2][k]};
+        const double tz = P.t[2][k];
+        const double wz[2] = {1.0 - tz, tz};
+        const bool twoz = iz[0] != iz[1];
+        bool all = true;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const bool ok = (a == 0 || twox) && (b == 0 || twoy) && (c == 0 || twoz);
+                    const int r = iz[c] & (PLC_RING - 1);
+                    const double term = (wx[a] * wy[b]) * wz[c] * (double)ec[r][iy[b]][ix[a]];
+                    if (ok) {
+                        if (!ca[r][iy[b]][ix[a]]) all = false;
+                        s += term;
+                    }
+                }
+        if (!all) s = (double)ec[iz[0] & (PLC_RING - 1)][iy[0]][ix[0]];
+        if (in && acur) L.e[(int64_t)k * plane + rowoff] = (T)((double)ecur + s);
+        if (more) {
+            __syncthreads();  // every thread is done with the slot the new plane goes to
+            cstore(nb, v, av);
+            have = nb;
+        }
+        __syncthreads();
+        ecur = enext;
+        acur = anext;
+    }
+}
+
 // The same for a level pair with every axis halved: a thread per coarse cell updates its
 // 2 x 2 x 2 children, loaded and stored as x pairs.  On a halved axis the first contributor
 // of a child is its parent and the second (if any) the parent's neighbour on the child's
@@ -1497,7 +1609,11 @@ static hipError_t vcycle_impl(ibm_grid *g, T **bufs, int *cur, const T *rhs, con
                 g->lev[l].ncell() >= PROLONG8_MIN_CELLS)
                 hipLaunchKernelGGL(k_prolongC8<T>, dim3(nblk(g->lev[l + 1].ncell())), dim3(256), 0, s, L,
                                    coarse_view<T>(g, l + 1), PT);
-            else
+            else if (g->lev[l].ncell() >= PROLONG_LDS_MIN_CELLS) {
+                const ZTiles t = ztiles(L.n[0], L.n[1], L.n[2]);
+                hipLaunchKernelGGL(k_prolongC_lds<T>, dim3(t.grid), dim3(ZM_NT), 0, s, L, coarse_view<T>(g, l + 1), PT,
+                                   t);
+            } else
                 hipLaunchKernelGGL(k_prolongC<T>, dim3(nb), dim3(256), 0, s, L, coarse_view<T>(g, l + 1), PT);
             if (g->lev[l].ncell() <= SMALL_LEVEL) {
                 if (o->nu2 > 0) launch_smallC<T>(L, g->lev[l].ncell(), o->nu2, &g->sc->vol[l], 0, s);
