@@ -86,6 +86,8 @@ __global__ void __launch_bounds__(32 * BY)
     static_assert(BY % 4 == 0, "two same-parity rows of 32 threads per wave");
     static_assert(QD == 4 || QD == 6, "planes held per thread");
     using V = typename Pair2<T>::type;
+    typedef T U2v __attribute__((ext_vector_type(2)));
+    typedef U2v U __attribute__((aligned(sizeof(T))));  // a pair at element alignment (odd rows)
     using PD = CPlane<T>;
     constexpr int NC = SWC_NC, TXC = NC - 4, TY = BY - 4;
     __shared__ T so[2][BY][NC + 1];  // old values of the plane whose red values are formed
@@ -126,17 +128,20 @@ __global__ void __launch_bounds__(32 * BY)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const int jc = min(max(j, 0), ny - 1);
     const int icv = min(max(ia, 0), nx - 2);
-    // unpaired path: each column clamped on its own
-    const int ic0 = min(max(ia, 0), nx - 1), ic1 = min(max(ia + 1, 0), nx - 1);
-    const uint32_t rowoff = (uint32_t)jc * nx + (VEC ? icv : ic0);
+    // Odd row length: rows start at alternating parity, so a thread's pair is only 8-byte
+    // aligned; it still moves as one access (the target allows vector accesses at element
+    // alignment), starting at icv like the aligned pairs.  On the last column of a row
+    // (ia = nx - 1) the pair is (nx - 2, nx - 1) and the thread's first cell is its second
+    // element (shifted); its second cell lies past the grid.
+    const bool shf = !VEC && ia == nx - 1;
+    const uint32_t rowoff = (uint32_t)jc * nx + icv;
     // The outermost halo rows are never updated: their right-hand side and x, z
     // transmissibilities are read from the adjacent row (lines the tile reads anyway), and
     // so is the y transmissibility of the first row (the last row's is the +y face of the
     // row below it).
     const int jr = min(max((ty == 0) ? j + 1 : (ty == BY - 1) ? j - 1 : j, 0), ny - 1);
     const int jy = min(max((ty == 0) ? j + 1 : j, 0), ny - 1);
-    const uint32_t roff = (uint32_t)jr * nx + (VEC ? icv : ic0), yoff = (uint32_t)jy * nx + (VEC ? icv : ic0);
-    const uint32_t d1 = VEC ? 1u : (uint32_t)(ic1 - ic0);  // offset of the second column
+    const uint32_t roff = (uint32_t)jr * nx + icv, yoff = (uint32_t)jy * nx + icv;
     // unpaired path: the second column is missing at the high wall of an odd row, where the
     // first column's high face is the wall (its x transmissibility must read 0, not the
     // clamped copy of the first column's low face)
@@ -165,16 +170,21 @@ __global__ void __launch_bounds__(32 * BY)
             d.y = *reinterpret_cast<const V *>(py + base + yoff);
             d.z = *reinterpret_cast<const V *>(pz + base + roff);
         } else {
-            d.e.x = pe[base + rowoff];
-            d.e.y = pe[base + rowoff + d1];
-            d.r.x = pr[base + roff];
-            d.r.y = pr[base + roff + d1];
-            d.x.x = px[base + roff];
-            d.x.y = x1in ? px[base + roff + d1] : T(0);
-            d.y.x = py[base + yoff];
-            d.y.y = py[base + yoff + d1];
-            d.z.x = pz[base + roff];
-            d.z.y = pz[base + roff + d1];
+            const U e2 = *reinterpret_cast<const U *>(pe + base + rowoff);
+            const U r2 = *reinterpret_cast<const U *>(pr + base + roff);
+            const U x2 = *reinterpret_cast<const U *>(px + base + roff);
+            const U y2 = *reinterpret_cast<const U *>(py + base + yoff);
+            const U z2 = *reinterpret_cast<const U *>(pz + base + roff);
+            d.e.x = shf ? e2.y : e2.x;
+            d.e.y = e2.y;
+            d.r.x = shf ? r2.y : r2.x;
+            d.r.y = r2.y;
+            d.x.x = shf ? x2.y : x2.x;
+            d.x.y = x1in ? x2.y : T(0);
+            d.y.x = shf ? y2.y : y2.x;
+            d.y.y = y2.y;
+            d.z.x = shf ? z2.y : z2.x;
+            d.z.y = z2.y;
         }
         return d;
     };
@@ -242,10 +252,16 @@ __global__ void __launch_bounds__(32 * BY)
                 o_.y = out1;                                                                                       \
                 *reinterpret_cast<V *>(eout + ((uint32_t)(k) * plane + (uint32_t)j * nx + ia)) = o_;                   \
             }                                                                                                      \
-        } else if ((k) < k1) {                                                                                     \
+        } else if ((k) < k1) { /* both cells or, at the last column of a row, the first alone */                  \
             const uint32_t o_ = (uint32_t)(k) * plane + (uint32_t)j * nx + ia;                                     \
-            if (blk0) eout[o_] = out0;                                                                             \
-            if (blk1) eout[o_ + 1] = out1;                                                                         \
+            if (blk0 && blk1) {                                                                                    \
+                U o2_;                                                                                             \
+                o2_.x = out0;                                                                                      \
+                o2_.y = out1;                                                                                      \
+                *reinterpret_cast<U *>(eout + o_) = o2_;                                                           \
+            } else if (blk0) {                                                                                     \
+                eout[o_] = out0;                                                                                   \
+            }                                                                                                      \
         }                                                                                                          \
         pa0 = pb0;                                                                                                 \
         pa1 = pb1;                                                                                                 \
