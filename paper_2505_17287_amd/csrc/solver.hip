@@ -1756,32 +1756,38 @@ hipError_t rhs_pass(ibm_grid *g, const double *u, const double *v, const double 
     return hipGetLastError();
 }
 
-// u_f -= dt (p_nb - p_c)/d_f on interior faces with at least one fluid cell; axis d
-__global__ void k_correct(const uint8_t *__restrict__ type, int nx, int ny, int nz, int d,
-                          const double *__restrict__ dc, const double *__restrict__ p, double dt, double *u) {
-    // faces along d: index space with n_d + 1 entries along d
-    const int fx = nx + (d == 0), fy = ny + (d == 1), fz = nz + (d == 2);
-    const int64_t NF = (int64_t)fx * fy * fz;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= NF) return;
+// u_f -= dt (p_nb - p_c)/d_f on interior faces with at least one fluid cell.  A thread owns
+// cell (i, j, k) and corrects its three low faces (the cell reads p and its type once for
+// all three); the low faces of the first cells and the high faces of the last cells along
+// an axis are box walls and stay as they are.
+__global__ void k_correct(const uint8_t *__restrict__ type, int nx, int ny, int nz, const double *__restrict__ dcx,
+                          const double *__restrict__ dcy, const double *__restrict__ dcz, const double *__restrict__ p,
+                          double dt, double *u, double *v, double *w) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= N) return;
     int i, j, k;
-    unflatten(id, fx, fy, i, j, k);
-    int q = (d == 0) ? i : (d == 1) ? j : k;
-    int n = (d == 0) ? nx : (d == 1) ? ny : nz;
-    if (q == 0 || q == n) return;  // domain walls
-    const int64_t b = ((int64_t)k * ny + j) * nx + i;
-    const int64_t a = b - ((d == 0) ? 1 : (d == 1) ? (int64_t)nx : (int64_t)nx * ny);
-    if (type[a] != T_FLUID && type[b] != T_FLUID) return;
-    u[id] -= dt * (p[b] - p[a]) / dc[q];
+    unflatten(b, nx, ny, i, j, k);
+    const bool fb = type[b] == T_FLUID;
+    const double pb = p[b];
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    if (i > 0 && (fb || type[b - 1] == T_FLUID)) {
+        const int64_t f = ((int64_t)k * ny + j) * (nx + 1) + i;
+        u[f] -= dt * (pb - p[b - 1]) / dcx[i];
+    }
+    if (j > 0 && (fb || type[b - sy] == T_FLUID)) {
+        const int64_t f = ((int64_t)k * (ny + 1) + j) * nx + i;
+        v[f] -= dt * (pb - p[b - sy]) / dcy[j];
+    }
+    if (k > 0 && (fb || type[b - sz] == T_FLUID)) {
+        const int64_t f = ((int64_t)k * ny + j) * nx + i;
+        w[f] -= dt * (pb - p[b - sz]) / dcz[k];
+    }
 }
 
 hipError_t correct_pass(ibm_grid *g, double *u, double *v, double *w, const double *p, double dt, hipStream_t s) {
-    double *arr[3] = {u, v, w};
-    for (int d = 0; d < 3; ++d) {
-        int64_t NF = (int64_t)(g->nx + (d == 0)) * (g->ny + (d == 1)) * (g->nz + (d == 2));
-        hipLaunchKernelGGL(k_correct, dim3(nblk(NF)), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, d, g->dc0[d], p, dt,
-                           arr[d]);
-    }
+    hipLaunchKernelGGL(k_correct, dim3(nblk(g->N)), dim3(256), 0, s, g->type, g->nx, g->ny, g->nz, g->dc0[0], g->dc0[1],
+                       g->dc0[2], p, dt, u, v, w);
     return hipGetLastError();
 }
 
