@@ -232,6 +232,25 @@ def test_determinism_bitwise():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_determinism_bitwise_stretched(precision):
+    """Run to run bitwise on a hierarchy that merges cells on part of each axis: the row-wise
+    restrictions (fixed tiling, per-lane sums gathered in a fixed order, one partial per
+    workgroup), the staged prolongations and the paired sweeps of odd coarse rows."""
+    torch = _torch()
+    from paper_2505_17287_amd import ibm
+    wl = I.multibody(158, n_bodies=2, level=3)
+    P = OracleProblem.from_workload(wl)
+    g = ibm.Grid(wl.xf, wl.yf, wl.zf, precision=precision)
+    g.setup(wl.verts, wl.tris)
+    fd = torch.from_numpy(P.rhs(*wl.velocity())).cuda()
+    a, sa = g.poisson_solve(fd, method="bicgstab", precision=precision)
+    b, sb = g.poisson_solve(fd, method="bicgstab", precision=precision)
+    assert sa.status == 0 and sa.cycles == sb.cycles
+    assert torch.equal(a, b)
+    g.close()
+
+
 @pytest.mark.parametrize("stride", [1, 3])
 def test_profiling_times_every_stride_th_sweep(stride):
     """Two fixed V(2,2) cycles run eight level-0 sweeps; profiling with a stride times the
