@@ -373,14 +373,16 @@ def test_stretched_hierarchy_fixed_cycles(method):
 
 def _hierarchy_cases():
     """Grids whose level plans take the less common branches of the width-based coarsening:
-    a stretched 2D grid (one z cell), a tiny grid of odd counts below the merge limit on one
-    axis, and a grid whose z cells are four times wider than x and y (z kept until the others
-    catch up)."""
+    a stretched 2D grid (one z cell), the same at 1024^2 (its 586^2 level 1 takes the
+    row-wise coarse restriction and the LDS-staged coarse prolongation in 2D), a tiny grid of
+    odd counts below the merge limit on one axis, and a grid whose z cells are four times
+    wider than x and y (z kept until the others catch up)."""
     cases = {}
-    xf = I.stretched_faces(-8.0, 8.0, -2.0, 2.0, 96)
-    h = float(np.min(np.diff(xf)))
     v, t = I.prism_mesh(0.5, 128, -1.0, 1.0)
-    cases["cyl2d_stretched"] = I.Workload("cyl2d_stretched", xf, xf.copy(), np.array([-h / 2, h / 2]), v, t, 3)
+    for name, n in (("cyl2d_stretched", 96), ("cyl2d_large", 1024)):
+        xf = I.stretched_faces(-8.0, 8.0, -2.0, 2.0, n)
+        h = float(np.min(np.diff(xf)))
+        cases[name] = I.Workload(name, xf, xf.copy(), np.array([-h / 2, h / 2]), v, t, 3)
     vs, ts = I.icosphere(3)
     cases["tiny_odd"] = I.Workload("tiny_odd", np.linspace(-1, 1, 8), np.linspace(-1, 1, 6), np.linspace(-1, 1, 5),
                                    vs * 0.45 + np.array([0.05, -0.03, 0.02]), ts, 4)
@@ -389,7 +391,7 @@ def _hierarchy_cases():
     return cases
 
 
-@pytest.mark.parametrize("name", ["cyl2d_stretched", "tiny_odd", "coarse_z"])
+@pytest.mark.parametrize("name", ["cyl2d_stretched", "cyl2d_large", "tiny_odd", "coarse_z"])
 @pytest.mark.parametrize("method", ["vcycle", "bicgstab"])
 def test_hierarchy_branches_fixed_cycles(name, method):
     torch = _torch()
