@@ -682,8 +682,6 @@ static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const
     if ((e = ref_norm_pass(g, rhs, s)) != hipSuccess) return e;
     if ((e = init_solution(g, p, g->p2, o->use_initial_guess, s)) != hipSuccess) return e;
     if (krylov_method(o->method)) {
-        if ((e = hipMemsetAsync(g->kv[2], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(g->kv[3], 0, sizeof(double) * g->N, s)) != hipSuccess) return e;
         if ((e = krylov_residual(g, rhs, g->p2, s)) != hipSuccess) return e;
     } else {
         if ((e = norm_pass(g, g->p2, rhs, s, o->precision == IBM_MIXED, true)) != hipSuccess) return e;
@@ -691,11 +689,12 @@ static hipError_t enqueue_begin(ibm_grid *g, const double *rhs, double *p, const
     return hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s);
 }
 
+// first: the solve's first cycle
 static hipError_t enqueue_cycle(ibm_grid *g, const double *rhs, double *p, const ibm_solve_opts *o, int *cur,
-                                hipStream_t s) {
+                                bool first, hipStream_t s) {
     if (krylov_method(o->method)) {
         *cur = 1;  // the Krylov iterate lives in the second buffer
-        return krylov_step(g, g->p2, o, s);
+        return krylov_step(g, g->p2, o, first, s);
     }
     double *bufs[2] = {p, g->p2};
     hipError_t e;
@@ -728,8 +727,6 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
     HIP_TRY(hipMemsetAsync(g->sc, 0, offsetof(Scalars, mu), s), "memset scalars");
     HIP_TRY(ref_norm_pass(g, rhs, s), "reference norm");
     HIP_TRY(init_solution(g, p, x, o->use_initial_guess, s), "init");
-    HIP_TRY(hipMemsetAsync(g->kv[2], 0, sizeof(double) * g->N, s), "memset");
-    HIP_TRY(hipMemsetAsync(g->kv[3], 0, sizeof(double) * g->N, s), "memset");
     HIP_TRY(krylov_residual(g, rhs, x, s), "residual");
     Scalars *hs = g->sc_host;
     HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
@@ -750,7 +747,7 @@ static ibm_status solve_krylov(ibm_grid *g, const double *rhs, double *p, const 
         const int nit = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
         for (it = 1; it <= nit; ++it) {
             Range step_range("bicgstab step");
-            HIP_TRY(krylov_step(g, x, o, s), "bicgstab step");
+            HIP_TRY(krylov_step(g, x, o, it == 1, s), "bicgstab step");
             HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read");
             HIP_TRY(hipStreamSynchronize(s), "step sync");
             if (g->prof.on) prof_collect(g);
@@ -842,7 +839,7 @@ static ibm_status solve_core(ibm_grid *g, const double *rhs, double *p, const ib
     if (hs->ref > 0.0) {
         const int ncyc = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
         for (cycles = 1; cycles <= ncyc; ++cycles) {
-            HIP_TRY(enqueue_cycle(g, rhs, p, o, &cur, s), "cycle");
+            HIP_TRY(enqueue_cycle(g, rhs, p, o, &cur, cycles == 1, s), "cycle");
             HIP_TRY(hipMemcpyAsync(hs, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, s), "read norm");
             HIP_TRY(hipStreamSynchronize(s), "cycle sync");
             if (g->prof.on) prof_collect(g);
@@ -989,7 +986,7 @@ ibm_status ibm_solve_step(ibm_grid *g, int n_cycles) {
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
     const int ncyc = S.o.fixed_cycles > 0 ? S.o.fixed_cycles : S.o.max_cycles;
     for (int q = 0; q < n_cycles && S.cycles < ncyc; ++q) {
-        HIP_TRY(enqueue_cycle(g, S.rhs, S.p_user, &S.o, &S.cur, S.stream), "step");
+        HIP_TRY(enqueue_cycle(g, S.rhs, S.p_user, &S.o, &S.cur, S.cycles == 0, S.stream), "step");
         S.cycles++;
     }
     HIP_TRY(hipMemcpyAsync(g->sc_host, g->sc, offsetof(Scalars, mu), hipMemcpyDeviceToHost, S.stream), "read");

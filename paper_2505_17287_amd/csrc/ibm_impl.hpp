@@ -391,7 +391,8 @@ hipError_t divmax_pass(ibm_grid *g, const double *u, const double *v, const doub
 hipError_t init_solution(ibm_grid *g, double *p, double *p2, int use_guess, hipStream_t s);
 hipError_t krylov_setup(ibm_grid *g, hipStream_t s);
 hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStream_t s);
-hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s);
+// first: the first step after krylov_residual of a new solve (p and v are not read)
+hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, bool first, hipStream_t s);
 // the handle's last geometry set-up time is g->t_setup (seconds, host wall clock)
 hipError_t krylov_restart(ibm_grid *g, hipStream_t s);
 

@@ -2168,8 +2168,9 @@ __global__ void k_krylov_finalize_dots(const double *part, int nb, int ns, const
 // pd = r + beta (pd - omega v) on fluid + ghost cells
 // r32 (mixed precision, else null): the FP32 right-hand side of the preconditioner, the
 // fluid part of the result rounded to FP32 and zero elsewhere
+// first: the first step of a solve, p = r (beta is 0 and p, v hold nothing yet: not read)
 __global__ void k_p_update(const uint8_t *__restrict__ type, int64_t N, const double *__restrict__ r,
-                           const double *__restrict__ v, double *pd, const Scalars *sc, float *r32) {
+                           const double *__restrict__ v, double *pd, const Scalars *sc, float *r32, int first) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
     const uint8_t ty = type[id];
@@ -2178,8 +2179,8 @@ __global__ void k_p_update(const uint8_t *__restrict__ type, int64_t N, const do
         if (r32) r32[id] = 0.0f;
         return;
     }
-    const double beta = sc->beta, omega = sc->omega;
-    const double pv = r[id] + beta * (pd[id] - omega * v[id]);
+    double pv = r[id];
+    if (!first) pv = pv + sc->beta * (pd[id] - sc->omega * v[id]);
     __builtin_nontemporal_store(pv, pd + id);
     if (r32) r32[id] = (ty == T_FLUID) ? (float)pv : 0.0f;
 }
@@ -2369,13 +2370,13 @@ hipError_t krylov_residual(ibm_grid *g, const double *f, const double *x, hipStr
 }
 
 // one BiCGStab step on x (kv: r, rh, pd, v, s, t, ya, yb, za, zb)
-hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, hipStream_t s) {
+hipError_t krylov_step(ibm_grid *g, double *x, const ibm_solve_opts *o, bool first, hipStream_t s) {
     double *r = g->kv[0], *rh = g->kv[1], *pd = g->kv[2], *v = g->kv[3], *sv = g->kv[4], *t = g->kv[5];
     double *ya = g->kv[6], *yb = g->kv[7], *za = g->kv[8], *zb = g->kv[9];
     const unsigned nbN = (unsigned)nblk(g->N);
     hipError_t e;
     float *r32 = o->precision == IBM_MIXED ? g->r32 : nullptr;  // FP32 right-hand side of the mixed cycle
-    hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc, r32);
+    hipLaunchKernelGGL(k_p_update, dim3(nbN), dim3(256), 0, s, g->type, g->N, r, v, pd, g->sc, r32, first ? 1 : 0);
     double *y = nullptr, *z = nullptr;
     if ((e = precondition(g, pd, ya, yb, &y, o, s)) != hipSuccess) return e;
     if ((e = apply_projected(g, y, v, rh, 0, K_ALPHA, o->breakdown_tol, s)) != hipSuccess) return e;
