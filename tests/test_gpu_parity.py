@@ -298,6 +298,22 @@ def test_step_api_equals_blocking_solve(precision, method):
         assert st.status == st_ref.status and st.cycles == st_ref.cycles, (kw, st, st_ref)
         assert idle >= 1
         assert torch.equal(p, ref), (precision, method, kw)
+    # all three fixed cycles enqueued by one step call (only the first is a solve's first)
+    ref, st_ref = g.poisson_solve(fd, precision=precision, method=method, fixed_cycles=3)
+    p = torch.empty_like(fd)
+    g.solve_begin(fd, p, precision=precision, method=method, fixed_cycles=3)
+    done, polls = 0, 0
+    while done != 1:
+        polls += 1
+        assert polls < 200000
+        done, st = g.solve_poll()
+        if done == -1:
+            g.solve_step(3)
+        elif done == 0:
+            time.sleep(1e-4)
+    torch.cuda.synchronize()
+    assert st.cycles == 3 and st_ref.cycles == 3
+    assert torch.equal(p, ref), (precision, method, "one step call")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
