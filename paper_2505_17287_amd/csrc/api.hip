@@ -456,7 +456,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
         g->topo_valid = true;
     }
     // bucket grid over the mesh bounding box: buckets at least as large as the largest
-    // triangle extent, so a triangle overlaps at most 2 buckets per axis
+    // triangle extent; each triangle is listed in the bucket of its bounding box's low corner
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext[3] = {0, 0, 0};
     for (int64_t t = 0; t < nt; ++t) {
         double tl[3] = {INFINITY, INFINITY, INFINITY}, th[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -477,7 +477,9 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
         span[d] = std::max(hi[d] - lo[d], 1e-12);
         vol *= span[d];
     }
-    double target = std::cbrt(vol / (double)std::max<int64_t>(nt, 1));
+    // about eight buckets per triangle over the bounding volume: a search box then spans few
+    // triangles beyond those it meets (each triangle is listed once)
+    double target = 0.5 * std::cbrt(vol / (double)std::max<int64_t>(nt, 1));
     int64_t total = 1;
     for (int d = 0; d < 3; ++d) {
         double sz = std::max(ext[d], target);
@@ -492,6 +494,7 @@ static ibm_status set_geometry_impl(ibm_grid *g, const double *verts, int64_t nv
     for (int d = 0; d < 3; ++d) {
         g->bmin[d] = lo[d];
         g->bsize[d] = span[d] / g->nb[d];
+        g->bext[d] = ext[d] + 1e-9 * span[d];  // covers the rounding of the extents
     }
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(g->device), "hipSetDevice");

@@ -161,8 +161,11 @@ static hipError_t scan_counts(const int32_t *in, int32_t *out, int64_t n, int64_
 // triangle bucket grid for the closest-point search
 // ---------------------------------------------------------------------------------------
 
+// Each triangle is listed once, in the bucket holding the low corner of its bounding box;
+// a box query reaches every triangle whose bounding box meets it by extending the box's low
+// side by the largest triangle extent ext.
 struct BucketGrid {
-    double bmin[3], bsize[3];
+    double bmin[3], bsize[3], ext[3];
     int nb[3];
 };
 
@@ -188,24 +191,17 @@ __global__ void k_bucket_pass(const double *__restrict__ V, const int32_t *__res
     if (t >= nt) return;
     double lo[3], hi[3];
     tri_bbox(V, T, t, lo, hi);
-    int b0[3], b1[3];
-    for (int d = 0; d < 3; ++d) {
-        b0[d] = bucket_coord(lo[d], G.bmin[d], G.bsize[d], G.nb[d]);
-        b1[d] = bucket_coord(hi[d], G.bmin[d], G.bsize[d], G.nb[d]);
+    int bc[3];
+    for (int d = 0; d < 3; ++d) bc[d] = bucket_coord(lo[d], G.bmin[d], G.bsize[d], G.nb[d]);
+    const int b = (bc[2] * G.nb[1] + bc[1]) * G.nb[0] + bc[0];
+    if (!ent) {
+        atomicAdd(&cnt[b], 1);
+    } else {
+        int slot = atomicAdd(&fill[b], 1);
+        int64_t pos = (int64_t)off[b] + slot;
+        if (pos < cap) ent[pos] = (int32_t)t;
+        else atomicAdd((unsigned long long *)overflow, 1ull);
     }
-    for (int z = b0[2]; z <= b1[2]; ++z)
-        for (int y = b0[1]; y <= b1[1]; ++y)
-            for (int x = b0[0]; x <= b1[0]; ++x) {
-                int b = (z * G.nb[1] + y) * G.nb[0] + x;
-                if (!ent) {
-                    atomicAdd(&cnt[b], 1);
-                } else {
-                    int slot = atomicAdd(&fill[b], 1);
-                    int64_t pos = (int64_t)off[b] + slot;
-                    if (pos < cap) ent[pos] = (int32_t)t;
-                    else atomicAdd((unsigned long long *)overflow, 1ull);
-                }
-            }
 }
 
 hipError_t launch_buckets(ibm_grid *g, hipStream_t s) {
@@ -213,6 +209,7 @@ hipError_t launch_buckets(ibm_grid *g, hipStream_t s) {
     for (int d = 0; d < 3; ++d) {
         G.bmin[d] = g->bmin[d];
         G.bsize[d] = g->bsize[d];
+        G.ext[d] = g->bext[d];
         G.nb[d] = g->nb[d];
     }
     int64_t nbk = (int64_t)g->nb[0] * g->nb[1] * g->nb[2];
@@ -813,7 +810,7 @@ __global__ void __launch_bounds__(64 * CLOSEST_WAVES)
     int32_t bt = 0x7fffffff;
     int b0[3], b1[3];
     for (int d = 0; d < 3; ++d) {
-        b0[d] = bucket_coord(x[d] - r, G.bmin[d], G.bsize[d], G.nb[d]);
+        b0[d] = bucket_coord(x[d] - r - G.ext[d], G.bmin[d], G.bsize[d], G.nb[d]);
         b1[d] = bucket_coord(x[d] + r, G.bmin[d], G.bsize[d], G.nb[d]);
     }
     // The box's bucket entries are laid end to end: lane L of a chunk of 64 buckets holds
@@ -1082,6 +1079,7 @@ hipError_t launch_stencils(ibm_grid *g, hipStream_t s) {
     for (int d = 0; d < 3; ++d) {
         G.bmin[d] = g->bmin[d];
         G.bsize[d] = g->bsize[d];
+        G.ext[d] = g->bext[d];
         G.nb[d] = g->nb[d];
     }
     unsigned nb = (unsigned)((g->ng + 127) / 128);
@@ -1199,6 +1197,7 @@ hipError_t launch_fresh(ibm_grid *g, hipStream_t s, int64_t *nfresh) {
     for (int d = 0; d < 3; ++d) {
         G.bmin[d] = g->bmin[d];
         G.bsize[d] = g->bsize[d];
+        G.ext[d] = g->bext[d];
         G.nb[d] = g->nb[d];
     }
     hipLaunchKernelGGL(k_closest, dim3((unsigned)((nf + CLOSEST_WAVES - 1) / CLOSEST_WAVES)), dim3(64 * CLOSEST_WAVES),

@@ -28,7 +28,7 @@ constexpr uint8_t T_FLUID = 0, T_GHOST = 1, T_DEAD = 2;
 constexpr int GF_DEGENERATE = 1, GF_CLAMPED = 2, GF_NFALLBACK = 4, GF_SELF = 8;
 constexpr int MAX_LEVELS = 24;
 constexpr int RED_BLOCKS = 4096;  // fixed block count of the deterministic reductions (enough waves to fill every SIMD)
-constexpr int NBUCKET_MAX = 1 << 20;
+constexpr int NBUCKET_MAX = 1 << 21;
 
 // ---------------------------------------------------------------------------------------
 // device views
@@ -261,6 +261,7 @@ struct ibm_grid {
     int32_t *bucket_off = nullptr, *bucket_cnt = nullptr, *bucket_ent = nullptr;
     int nb[3] = {1, 1, 1};
     double bmin[3] = {0, 0, 0}, bsize[3] = {1, 1, 1};
+    double bext[3] = {0, 0, 0};  // largest triangle extent per axis (padded for rounding)
     int32_t *col_cnt = nullptr, *col_off = nullptr, *col_fill = nullptr;
     double *crossings = nullptr;
     int64_t cross_cap = 0;
